@@ -1,0 +1,266 @@
+"""Plain CPU oracle for the Pauli decomposition -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this module.  The product library never does, and this
+module imports nothing from the product package: the two share no code.
+
+Two independent evaluations of the definition (paper, Sec. II-A)
+
+    c_P = 2^-n Tr(P A),   P = s_{n-1} (x) ... (x) s_0,  s_q in {I, X, Y, Z}
+
+are provided:
+
+* ``decompose_textbook`` (numpy, tiny n): builds every P with ``np.kron`` from
+  the 2x2 matrices printed in Sec. I and takes ``np.trace(P @ A) / 2^n`` --
+  the "straightforward decomposition method" of Sec. II-A, cost O(2^{4n}).
+* ``decompose`` / ``decompose_int`` / ``coeffs`` (C, ``oracle.c``): the
+  sparse form (k, m) of each P from the PauliComposer iteration (Sec. II-B)
+  and the trace sum of Algorithm 2, read as sum_j m[j] A[k[j]][j], in
+  double precision (exact int64 for Gaussian-integer inputs).
+
+Output layout (a convention the paper leaves open, see oracle.c): a complex
+array ``c`` of shape (2^n, 2^n) with ``c[x, z]`` the coefficient of the string
+whose qubit q carries (x_q, z_q) = (0,0) I, (1,0) X, (1,1) Y, (0,1) Z; qubit q
+is bit q of the matrix index, so the leftmost letter of a label is qubit n-1.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+_lock = threading.Lock()
+
+# Sec. I: the four Pauli matrices.
+PAULI_MATRICES = {
+    "I": np.array([[1, 0], [0, 1]], dtype=np.complex128),
+    "X": np.array([[0, 1], [1, 0]], dtype=np.complex128),
+    "Y": np.array([[0, -1j], [1j, 0]], dtype=np.complex128),
+    "Z": np.array([[1, 0], [0, -1]], dtype=np.complex128),
+}
+_LETTER_CODE = {"I": 0, "X": 1, "Y": 2, "Z": 3}
+_XZ_TO_LETTER = {(0, 0): "I", (1, 0): "X", (1, 1): "Y", (0, 1): "Z"}
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc (plain C11 + pthreads)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-Wall", _SRC, "-o", tmp]
+        )
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH):
+                build()
+            lib = ctypes.CDLL(_LIB_PATH)
+            P = ctypes.c_void_p
+            lib.oracle_pauli_sparse.argtypes = [ctypes.c_int, P, P, P, P]
+            lib.oracle_pauli_sparse.restype = None
+            lib.oracle_pauli_sparse_kron.argtypes = [ctypes.c_int, P, P, P, P]
+            lib.oracle_pauli_sparse_kron.restype = None
+            lib.oracle_decompose_f64.argtypes = [ctypes.c_int, P, P, ctypes.c_int]
+            lib.oracle_decompose_f64.restype = ctypes.c_int
+            lib.oracle_decompose_i64.argtypes = [ctypes.c_int, P, P, ctypes.c_int]
+            lib.oracle_decompose_i64.restype = ctypes.c_int
+            lib.oracle_coeffs_f64.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P, P, ctypes.c_int]
+            lib.oracle_coeffs_f64.restype = ctypes.c_int
+            lib.oracle_reconstruct_f64.argtypes = [ctypes.c_int, P, P]
+            lib.oracle_reconstruct_f64.restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def default_threads() -> int:
+    return max(1, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count() or 1)
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _nqubits(A: np.ndarray) -> int:
+    N = A.shape[0]
+    if A.ndim != 2 or A.shape[1] != N or N < 2 or (N & (N - 1)):
+        raise ValueError("expected a square 2^n x 2^n matrix, got shape %r" % (A.shape,))
+    return N.bit_length() - 1
+
+
+# --------------------------------------------------------------------------
+# labels and letters (conventions only, no arithmetic of the method)
+
+def letters(x: int, z: int, n: int) -> list[str]:
+    """Letters [s_0, ..., s_{n-1}] of the string stored at (x, z)."""
+    return [_XZ_TO_LETTER[((x >> q) & 1, (z >> q) & 1)] for q in range(n)]
+
+
+def label(x: int, z: int, n: int) -> str:
+    """Label s_{n-1} ... s_0 (leftmost character is qubit n-1)."""
+    return "".join(reversed(letters(x, z, n)))
+
+
+def pauli_matrix(lab: str) -> np.ndarray:
+    """Dense P for a label s_{n-1}...s_0 by Kronecker products (Sec. II-A)."""
+    M = np.array([[1.0 + 0j]])
+    for ch in lab:
+        M = np.kron(M, PAULI_MATRICES[ch])
+    return M
+
+
+# --------------------------------------------------------------------------
+# the sparse form of P (Sec. II-B)
+
+def pauli_sparse(lab: str, method: str = "composer"):
+    """(k, m) of P for a label: k[j] = column of row j's nonzero, m[j] its value."""
+    n = len(lab)
+    lets = np.array([_LETTER_CODE[ch] for ch in reversed(lab)], dtype=np.uint8)  # lets[q] = s_q
+    N = 1 << n
+    col = np.zeros(N, dtype=np.uint64)
+    mre = np.zeros(N, dtype=np.int8)
+    mim = np.zeros(N, dtype=np.int8)
+    fn = _load().oracle_pauli_sparse if method == "composer" else _load().oracle_pauli_sparse_kron
+    fn(n, _ptr(lets), _ptr(col), _ptr(mre), _ptr(mim))
+    return col.astype(np.int64), mre.astype(np.float64) + 1j * mim.astype(np.float64)
+
+
+# --------------------------------------------------------------------------
+# decompositions
+
+def decompose_textbook(A: np.ndarray) -> np.ndarray:
+    """c[x, z] = trace(P @ A) / 2^n with P from np.kron (Sec. II-A).  Tiny n only."""
+    A = np.asarray(A, dtype=np.complex128)
+    n = _nqubits(A)
+    if n > 6:
+        raise ValueError("textbook oracle is O(2^{4n}); n <= 6 only")
+    N = 1 << n
+    c = np.empty((N, N), dtype=np.complex128)
+    for x in range(N):
+        for z in range(N):
+            P = pauli_matrix(label(x, z, n))
+            c[x, z] = np.trace(P @ A) / N
+    return c
+
+
+def reconstruct_textbook(c: np.ndarray) -> np.ndarray:
+    """A = sum_P c_P P with P from np.kron (the expansion of Sec. II-A)."""
+    c = np.asarray(c, dtype=np.complex128)
+    n = _nqubits(c)
+    N = 1 << n
+    A = np.zeros((N, N), dtype=np.complex128)
+    for x in range(N):
+        for z in range(N):
+            A += c[x, z] * pauli_matrix(label(x, z, n))
+    return A
+
+
+def decompose(A: np.ndarray, nthreads: int | None = None) -> np.ndarray:
+    """All 4^n coefficients, c[x, z], accumulated in float64 (C oracle)."""
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    n = _nqubits(A)
+    N = 1 << n
+    out = np.empty((N, N), dtype=np.complex128)
+    rc = _load().oracle_decompose_f64(n, _ptr(A), _ptr(out), nthreads or default_threads())
+    if rc != 0:
+        raise RuntimeError("oracle_decompose_f64 failed (%d)" % rc)
+    return out
+
+
+def decompose_int(A_re: np.ndarray, A_im: np.ndarray, nthreads: int | None = None):
+    """Exact 2^n c[x, z] for a Gaussian-integer A, as two int64 arrays (re, im)."""
+    A_re = np.asarray(A_re, dtype=np.int64)
+    A_im = np.asarray(A_im, dtype=np.int64)
+    n = _nqubits(A_re)
+    N = 1 << n
+    inter = np.empty((N, N, 2), dtype=np.int64)
+    inter[..., 0] = A_re
+    inter[..., 1] = A_im
+    out = np.empty((N, N, 2), dtype=np.int64)
+    rc = _load().oracle_decompose_i64(n, _ptr(inter), _ptr(out), nthreads or default_threads())
+    if rc != 0:
+        raise RuntimeError("oracle_decompose_i64 failed (%d)" % rc)
+    return out[..., 0].copy(), out[..., 1].copy()
+
+
+def coeffs(A: np.ndarray, xs, zs, nthreads: int | None = None) -> np.ndarray:
+    """Coefficients of the strings (xs[i], zs[i]) only (float64)."""
+    A = np.ascontiguousarray(A)
+    if A.dtype != np.complex128:
+        A = A.astype(np.complex128)
+    n = _nqubits(A)
+    xs = np.ascontiguousarray(xs, dtype=np.uint32)
+    zs = np.ascontiguousarray(zs, dtype=np.uint32)
+    if xs.shape != zs.shape or xs.ndim != 1:
+        raise ValueError("xs and zs must be 1-D arrays of equal length")
+    out = np.empty(xs.shape[0], dtype=np.complex128)
+    rc = _load().oracle_coeffs_f64(n, _ptr(A), xs.shape[0], _ptr(xs), _ptr(zs), _ptr(out),
+                                   nthreads or default_threads())
+    if rc != 0:
+        raise RuntimeError("oracle_coeffs_f64 failed (%d)" % rc)
+    return out
+
+
+def reconstruct(c: np.ndarray) -> np.ndarray:
+    """A = sum_P c_P P from a dense c[x, z] (C oracle, single thread)."""
+    c = np.ascontiguousarray(c, dtype=np.complex128)
+    n = _nqubits(c)
+    N = 1 << n
+    A = np.empty((N, N), dtype=np.complex128)
+    rc = _load().oracle_reconstruct_f64(n, _ptr(c), _ptr(A))
+    if rc != 0:
+        raise RuntimeError("oracle_reconstruct_f64 failed (%d)" % rc)
+    return A
+
+
+# --------------------------------------------------------------------------
+# norms for the Parseval check (Theorem 1: the strings are orthogonal with
+# <P, P> = Tr(P^* P) = 2^n, so ||A||_F^2 = 2^n sum_P |c_P|^2)
+
+def frobenius_sq(A: np.ndarray) -> float:
+    A = np.asarray(A)
+    return float(np.sum(A.real.astype(np.float64) ** 2) + np.sum(A.imag.astype(np.float64) ** 2))
+
+
+def coeff_energy(c: np.ndarray, n: int) -> float:
+    c = np.asarray(c)
+    return float(2.0 ** n * (np.sum(c.real.astype(np.float64) ** 2) + np.sum(c.imag.astype(np.float64) ** 2)))
+
+
+# --------------------------------------------------------------------------
+# structured supports (Sec. IV-A), by brute force over the matrix entries
+
+def nonempty_x_bruteforce(n: int, s: int) -> list[int]:
+    """X-patterns x with at least one in-band entry (k, k^x), |(k^x) - k| <= s.
+
+    Only those x can carry a nonzero coefficient of a band matrix with
+    half-bandwidth s, because the strings with d-bits x read exactly the
+    entries A[k, k^x].  s = 0 is the diagonal case, s = 1 tridiagonal.
+    """
+    N = 1 << n
+    k = np.arange(N, dtype=np.int64)
+    out = []
+    for x in range(N):
+        if np.any(np.abs((k ^ x) - k) <= s):
+            out.append(x)
+    return out
+
+
+def band_term_bound(n: int, s: int) -> int:
+    """The paper's bound (s n - c(s)) 2^n on the number of nonzero terms of a
+    band matrix of width 2s+1, c(s) = s(floor(log2 s) + 1) - 2^{floor(log2 s)+1}
+    (Sec. IV-A, band-diagonal theorem)."""
+    L = int(np.floor(np.log2(s)))
+    c = s * (L + 1) - 2 ** (L + 1)
+    return (s * n - c) * (1 << n)

@@ -1,0 +1,294 @@
+"""Pins for the CPU oracle: values and identities fixed by the paper and by
+mathematics, independent of the oracle's own code.  CPU only.
+
+Each test names the passage of the paper it follows.  Together they catch the
+plausible slips: a wrong letter table or Y sign (n=1 closed forms, worked
+examples), a transposed operand in the trace (worked example with an
+asymmetric corner entry, textbook comparison), a wrong qubit order (Kronecker
+factorisation, direct sum, labels), a dropped or mis-scaled term (Parseval,
+one-hot, reconstruction) and a wrong structured support (diagonal,
+tridiagonal and band tests).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")
+
+
+def _index_of_label(lab):
+    n = len(lab)
+    x = z = 0
+    for j, ch in enumerate(lab):
+        q = n - 1 - j
+        xb, zb = {"I": (0, 0), "X": (1, 0), "Y": (1, 1), "Z": (0, 1)}[ch]
+        x |= xb << q
+        z |= zb << q
+    return x, z
+
+
+# -- Sec. I letter matrices and the Sec. II-A formula, by hand ---------------
+
+def test_worked_examples(oracle_mod):
+    data = json.load(open(GOLDEN))
+    for ex in data["examples"]:
+        M = np.array(ex["matrix"], dtype=np.float64)
+        A = M[..., 0] + 1j * M[..., 1]
+        n = A.shape[0].bit_length() - 1
+        want = np.zeros((1 << n, 1 << n), dtype=np.complex128)
+        for lab, (re, im) in ex["coefficients"].items():
+            x, z = _index_of_label(lab)
+            want[x, z] = re + 1j * im
+        got = oracle_mod.decompose(A, nthreads=1)
+        np.testing.assert_array_equal(got, want, err_msg=ex["name"])
+        np.testing.assert_allclose(oracle_mod.decompose_textbook(A), want, atol=0, rtol=0,
+                                   err_msg=ex["name"])
+
+
+def test_n1_closed_forms(oracle_mod):
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        a, b, c, d = rng.standard_normal(4) + 1j * rng.standard_normal(4)
+        A = np.array([[a, b], [c, d]])
+        got = oracle_mod.decompose(A, nthreads=1)
+        # c[x, z]: I=(0,0), Z=(0,1), X=(1,0), Y=(1,1)
+        np.testing.assert_allclose(got[0, 0], (a + d) / 2, rtol=1e-15, atol=1e-15)
+        np.testing.assert_allclose(got[0, 1], (a - d) / 2, rtol=1e-15, atol=1e-15)
+        np.testing.assert_allclose(got[1, 0], (b + c) / 2, rtol=1e-15, atol=1e-15)
+        np.testing.assert_allclose(got[1, 1], 1j * (b - c) / 2, rtol=1e-15, atol=1e-15)
+
+
+def test_labels():
+    from oracle import oracle as O
+
+    assert O.label(1, 3, 2) == "ZY"
+    assert O.label(0, 0, 3) == "III"
+    assert O.label(4, 0, 3) == "XII"
+    assert O.label(1, 1, 3) == "IIY"
+    for n in (1, 2, 3):
+        for x in range(1 << n):
+            for z in range(1 << n):
+                assert _index_of_label(O.label(x, z, n)) == (x, z)
+
+
+# -- Sec. II-B PauliComposer vs the Kronecker definition ---------------------
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_composer_matches_kron(oracle_mod, n):
+    N = 1 << n
+    for x in range(N):
+        for z in range(N):
+            lab = oracle_mod.label(x, z, n)
+            k1, m1 = oracle_mod.pauli_sparse(lab, "composer")
+            k2, m2 = oracle_mod.pauli_sparse(lab, "kron")
+            np.testing.assert_array_equal(k1, k2)
+            np.testing.assert_array_equal(m1, m2)
+            P = oracle_mod.pauli_matrix(lab)
+            rows = np.arange(N)
+            np.testing.assert_array_equal(P[rows, k1], m1)
+            assert np.count_nonzero(P) == N
+            # every row's nonzero sits at column j ^ x (the d-bits of the string)
+            np.testing.assert_array_equal(k1, rows ^ x)
+
+
+# -- the C oracle against np.kron + np.trace (Sec. II-A straightforward) -----
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_oracle_vs_textbook(oracle_mod, n):
+    A = synth.dense(n, seed=10 + n)
+    got = oracle_mod.decompose(A)
+    want = oracle_mod.decompose_textbook(A)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-14)
+
+
+# -- Theorem 1: orthogonality -> one-hot, reconstruction, Parseval ----------
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_one_hot(oracle_mod, n):
+    N = 1 << n
+    for x in range(N):
+        for z in range(N):
+            P = oracle_mod.pauli_matrix(oracle_mod.label(x, z, n))
+            c = oracle_mod.decompose(P, nthreads=1)
+            want = np.zeros((N, N), dtype=np.complex128)
+            want[x, z] = 1.0
+            np.testing.assert_array_equal(c, want)
+
+
+def test_reconstruction(oracle_mod):
+    for n in (2, 3, 5):
+        A = synth.dense(n, seed=20 + n)
+        c = oracle_mod.decompose(A)
+        np.testing.assert_allclose(oracle_mod.reconstruct(c), A, rtol=0, atol=1e-13)
+    A = synth.dense(2, seed=3)
+    c = oracle_mod.decompose(A)
+    np.testing.assert_allclose(oracle_mod.reconstruct_textbook(c), A, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(oracle_mod.reconstruct(c), oracle_mod.reconstruct_textbook(c),
+                               rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("n", [4, 7])
+def test_parseval(oracle_mod, n):
+    A = synth.dense(n, seed=30 + n)
+    c = oracle_mod.decompose(A)
+    lhs = oracle_mod.frobenius_sq(A)
+    rhs = oracle_mod.coeff_energy(c, n)
+    assert abs(lhs - rhs) <= 1e-12 * lhs
+
+
+# -- Theorem 2: Hermitian -> real coefficients -------------------------------
+
+def test_hermitian_real(oracle_mod):
+    n = 6
+    A = synth.hermitian(n, seed=0)
+    c = oracle_mod.decompose(A)
+    # sequential float64 sums: |Im c| bounded by 2^-n * N * eps * sum|A| per row
+    bound = 2.0 ** -n * (1 << n) * np.finfo(np.float64).eps * np.abs(A).sum()
+    assert np.max(np.abs(c.imag)) <= bound
+    assert np.max(np.abs(c.real)) > 0.01
+
+
+def test_hermitian_int_exact(oracle_mod):
+    n = 5
+    re, im = synth.gaussian_int_hermitian(n, seed=1)
+    A = synth.int_to_complex(re, im)
+    np.testing.assert_array_equal(A, A.conj().T)
+    cre, cim = oracle_mod.decompose_int(re, im)
+    assert np.all(cim == 0)
+    np.testing.assert_array_equal(cre.astype(np.float64), np.round(oracle_mod.decompose(A).real * (1 << n)))
+
+
+def test_real_symmetric_odd_y_vanish(oracle_mod):
+    # a real symmetric matrix has no strings with an odd number of Y letters
+    n = 5
+    rng = np.random.default_rng(4)
+    B = rng.standard_normal((1 << n, 1 << n))
+    A = (B + B.T).astype(np.complex128)
+    c = oracle_mod.decompose(A)
+    N = 1 << n
+    odd = np.array([[bin(x & z).count("1") & 1 for z in range(N)] for x in range(N)], dtype=bool)
+    assert np.max(np.abs(c[odd])) <= 1e-13
+    assert np.max(np.abs(c[~odd].imag)) <= 1e-13
+
+
+# -- integer mode ------------------------------------------------------------
+
+def test_integer_mode_matches_float(oracle_mod):
+    n = 6
+    re, im = synth.gaussian_int(n, seed=7)
+    cre, cim = oracle_mod.decompose_int(re, im)
+    c = oracle_mod.decompose(synth.int_to_complex(re, im))
+    np.testing.assert_array_equal(cre, np.round(c.real * (1 << n)).astype(np.int64))
+    np.testing.assert_array_equal(cim, np.round(c.imag * (1 << n)).astype(np.int64))
+    # the float result is itself exact here (small integers, power-of-two scale)
+    np.testing.assert_array_equal(c.real * (1 << n), cre.astype(np.float64))
+
+
+def test_sampled_mode(oracle_mod):
+    n = 6
+    A = synth.dense(n, seed=8)
+    full = oracle_mod.decompose(A)
+    xs, zs = synth.sample_strings(n, 500, seed=2)
+    got = oracle_mod.coeffs(A, xs, zs)
+    np.testing.assert_array_equal(got, full[xs, zs])
+    # unsorted, repeated order
+    perm = np.random.default_rng(1).permutation(len(xs))
+    got2 = oracle_mod.coeffs(A, xs[perm], zs[perm])
+    np.testing.assert_array_equal(got2, full[xs[perm], zs[perm]])
+
+
+# -- Sec. IV-A structured supports ------------------------------------------
+
+def test_diagonal_is_walsh_hadamard(oracle_mod):
+    n = 6
+    d = synth.diagonal_real(n, seed=0)
+    A = np.diag(d).astype(np.complex128)
+    c = oracle_mod.decompose(A)
+    N = 1 << n
+    assert np.all(c[1:, :] == 0)
+    H = scipy.linalg.hadamard(N)  # H[i, j] = (-1)^{popcount(i & j)}
+    np.testing.assert_allclose(c[0, :], H @ d / N, rtol=0, atol=1e-14)
+
+
+def test_tridiagonal_support(oracle_mod):
+    n = 6
+    a, b = synth.tridiag_real_sym(n, seed=1)
+    A = synth.dense_from_bands(synth.bands_from_tridiag(a, b))
+    c = oracle_mod.decompose(A)
+    N = 1 << n
+    nz_rows = sorted(set(np.nonzero(np.abs(c) > 1e-13)[0].tolist()))
+    # Gamma_n: I/Z on the high qubits, X/Y on a block of low qubits -> x = 2^m - 1
+    assert nz_rows == [(1 << m) - 1 for m in range(n + 1)]
+    assert len(nz_rows) * N == (n + 1) * N  # at most (n+1) 2^n terms
+    assert np.count_nonzero(np.abs(c) > 1e-13) <= (n + 1) * N
+
+
+@pytest.mark.parametrize("n,s", [(5, 1), (6, 2), (6, 3), (7, 5), (8, 8)])
+def test_band_support(oracle_mod, n, s):
+    band = synth.banded_complex(n, s, seed=2)
+    A = synth.dense_from_bands(band)
+    c = oracle_mod.decompose(A)
+    allowed = oracle_mod.nonempty_x_bruteforce(n, s)
+    nz_rows = sorted(set(np.nonzero(np.abs(c) > 1e-13)[0].tolist()))
+    assert set(nz_rows) <= set(allowed)
+    # generic entries: every allowed x carries a nonzero coefficient
+    assert nz_rows == allowed
+    # the paper's bound (s n - c(s)) 2^n is attained by the support size
+    assert len(allowed) * (1 << n) == oracle_mod.band_term_bound(n, s)
+
+
+# -- Sec. IV-B combinations --------------------------------------------------
+
+def test_kronecker_factorisation(oracle_mod):
+    # Tr(A1^* B1 (x) ...) factorises (proof of Theorem 1): c(A (x) B) = c(A) (x) c(B)
+    A = synth.dense(2, seed=40)
+    B = synth.dense(3, seed=41)
+    cA = oracle_mod.decompose(A)
+    cB = oracle_mod.decompose(B)
+    cAB = oracle_mod.decompose(np.kron(A, B))
+    np.testing.assert_allclose(cAB, np.kron(cA, cB), rtol=0, atol=1e-14)
+
+
+def test_direct_sum(oracle_mod):
+    n = 3
+    A = synth.dense(n, seed=42)
+    B = synth.dense(n, seed=43)
+    N = 1 << n
+    C = np.zeros((2 * N, 2 * N), dtype=np.complex128)
+    C[:N, :N] = A
+    C[N:, N:] = B
+    cA, cB, cC = (oracle_mod.decompose(M) for M in (A, B, C))
+    # I (x) (a+b)/2 + Z (x) (a-b)/2; the new qubit is the most significant one
+    np.testing.assert_allclose(cC[:N, :N], (cA + cB) / 2, atol=1e-15)
+    np.testing.assert_allclose(cC[:N, N:], (cA - cB) / 2, atol=1e-15)
+    assert np.all(cC[N:, :] == 0)
+
+
+def test_hermitian_augmentation(oracle_mod):
+    n = 3
+    A = synth.dense(n, seed=44)
+    N = 1 << n
+    At = np.zeros((2 * N, 2 * N), dtype=np.complex128)
+    At[:N, N:] = A.conj().T
+    At[N:, :N] = A
+    cA = oracle_mod.decompose(A)
+    cT = oracle_mod.decompose(At)
+    # X (x) Re(alpha) + Y (x) Im(alpha)
+    np.testing.assert_allclose(cT[N:, :N], cA.real, atol=1e-15)
+    np.testing.assert_allclose(cT[N:, N:], cA.imag, atol=1e-15)
+    assert np.all(cT[:N, :] == 0)
+
+
+def test_linearity(oracle_mod):
+    n = 4
+    A = synth.dense(n, seed=45)
+    B = synth.dense(n, seed=46)
+    mu = 0.3 - 1.7j
+    np.testing.assert_allclose(oracle_mod.decompose(mu * A + B),
+                               mu * oracle_mod.decompose(A) + oracle_mod.decompose(B),
+                               rtol=0, atol=1e-13)
