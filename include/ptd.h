@@ -1,0 +1,156 @@
+/*
+ * ptd.h -- C ABI of the MI355X (gfx950) Pauli decomposition library.
+ *
+ * The library computes the coefficients of a 2^n x 2^n complex matrix A in
+ * the Pauli operator basis P_n = { s_{n-1} (x) ... (x) s_0 : s_q in {I,X,Y,Z} }
+ * (paper, Sec. II-A, Theorem 1 and the decomposition formula):
+ *
+ *     c_P = 2^-n * Tr(P A),        A = sum_P c_P P.
+ *
+ * Conventions (the paper leaves them open):
+ *   - qubit q is bit q of the row and column index, so s_{n-1} is the most
+ *     significant (leftmost) Kronecker factor, as in P = s_{n-1} (x) ... (x) s_0
+ *     of Sec. II-B; a label's leftmost character is qubit n-1;
+ *   - a string is indexed by its X-pattern x and Z-pattern z, with
+ *     (x_q, z_q) = (0,0) I, (1,0) X, (1,1) Y, (0,1) Z on qubit q; the dense
+ *     coefficient array stores c[x * 2^n + z].
+ *
+ * Memory: A, coeff and ws are DEVICE pointers owned by the caller; the
+ * library neither allocates nor frees them.  Complex data is interleaved
+ * (re, im): PTD_C128 = two doubles (16 B), PTD_C64 = two floats (8 B).  A
+ * dense matrix has element (r, c) at A + r*lda + c (lda in elements).
+ *
+ * Execution: every compute entry point validates its arguments on the host
+ * BEFORE any HIP call (argument errors are returned synchronously and need
+ * no GPU), then enqueues kernels on `stream` and returns without waiting.
+ * Device-side failures surface as PTD_EHIP; ptd_last_hip_error() gives the
+ * HIP error code.  Functions never print and never throw.  Concurrent calls
+ * on different streams are safe; the batch plans below are not thread-safe
+ * objects.
+ */
+#ifndef PTD_H
+#define PTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int ptd_status;
+#define PTD_OK 0
+#define PTD_EINVAL (-1) /* bad argument: n out of [1,16], null pointer, lda < 2^n, bad flag mix, s < 0 ... */
+#define PTD_ENOSPC (-2) /* workspace smaller than ptd_workspace_bytes() */
+#define PTD_EUNSUP (-3) /* valid request this build does not support (e.g. compensated FP64) */
+#define PTD_EHIP (-4)   /* HIP runtime or launch error, see ptd_last_hip_error() */
+#define PTD_ENOMEM (-5) /* a batch plan could not allocate its own descriptors */
+
+typedef enum { PTD_C128 = 0, PTD_C64 = 1 } ptd_dtype;
+
+/* A hipStream_t; NULL means the null stream. */
+typedef void *ptd_stream;
+
+/* Flags (bitwise OR). */
+/* A is Hermitian (Theorem 2: real coefficients).  The output is REAL: doubles
+ * for PTD_C128, floats for PTD_C64, one per string.  The caller guarantees
+ * A == A^*; the kernels read the whole matrix and drop the imaginary part,
+ * which is exactly zero in their butterfly network. */
+#define PTD_HERMITIAN (1u << 0)
+/* A is diagonal (Sec. IV-A, diagonal matrices): only x = 0 can be nonzero. */
+#define PTD_DIAGONAL (1u << 1)
+/* A is banded with half-bandwidth s >= 1: a[r][c] = 0 when |r - c| > s
+ * (Sec. IV-A, band-diagonal matrices; s = 1 is tridiagonal).  Only the
+ * X-patterns with an in-band entry are computed (ptd_nonempty_x). */
+#define PTD_BANDED (1u << 2)
+/* With PTD_DIAGONAL or PTD_BANDED: A is given as row-indexed bands,
+ * band[d + s][k] = A[k][k + d] for d in [-s, s] (s = 0 for diagonal), the
+ * band rows lda elements apart; slots whose column falls outside [0, 2^n)
+ * are ignored. */
+#define PTD_BANDS_IN (1u << 3)
+/* With PTD_DIAGONAL or PTD_BANDED: write only the nonempty X-patterns, as
+ * rows [i][z] in ascending x order (row i belongs to the i-th entry of
+ * ptd_nonempty_x).  Without it the output is the dense [x][z] array with
+ * the empty rows written as zeros. */
+#define PTD_COMPACT (1u << 4)
+/* PTD_C64 only: Walsh-Hadamard butterflies with compensated (TwoSum)
+ * float32 arithmetic; results are rounded to float32 at every pass
+ * boundary. */
+#define PTD_COMPENSATED (1u << 5)
+/* pauli_reconstruct only: multiply the result by 2^-n, which makes the call
+ * the adjoint (vector-Jacobian product) of pauli_decompose. */
+#define PTD_ADJOINT (1u << 6)
+
+/* Workspace (device bytes) a call with these arguments needs; 0 for every
+ * decompose/reconstruct variant of this build.  Host-only, pure. */
+size_t ptd_workspace_bytes(int n, ptd_dtype dtype, unsigned flags, int s);
+
+/* Number of X-patterns x that can carry a nonzero coefficient: 2^n for a
+ * dense matrix, 1 for PTD_DIAGONAL, and for PTD_BANDED
+ * 1 + sum_{h<n} min(s, 2^h) = s n - c(s), c(s) = s(floor(log2 s)+1) - 2^{floor(log2 s)+1}
+ * (Sec. IV-A band-diagonal theorem: (s n - c(s)) 2^n terms at most).  x is
+ * nonempty when some entry (k, k ^ x) lies in the band, i.e. x = 0 or
+ * x = 2^h + y with 0 <= y < 2^h and 2^h - y <= s.  Host-only, pure; returns
+ * -1 on bad arguments. */
+int ptd_num_nonempty_x(int n, unsigned flags, int s);
+
+/* Writes those X-patterns in ascending order to xs_host (host memory,
+ * ptd_num_nonempty_x entries). */
+ptd_status ptd_nonempty_x(int n, unsigned flags, int s, uint32_t *xs_host);
+
+/*
+ * pauli_decompose: coeff = { c_P } for the 2^n x 2^n matrix A.
+ *
+ *   n        number of qubits, 1..16
+ *   dtype    element type of A (and of coeff unless PTD_HERMITIAN)
+ *   flags    PTD_HERMITIAN | PTD_DIAGONAL | PTD_BANDED | PTD_BANDS_IN |
+ *            PTD_COMPACT | PTD_COMPENSATED
+ *   s        half-bandwidth for PTD_BANDED (>= 1), else ignored
+ *   A, lda   input matrix (or bands with PTD_BANDS_IN), lda >= 2^n elements
+ *   coeff    output, 4^n values (complex, or real with PTD_HERMITIAN; with
+ *            PTD_COMPACT ptd_num_nonempty_x * 2^n values); must not overlap A
+ *   ws       workspace of ws_bytes >= ptd_workspace_bytes(...) (may be NULL
+ *            when that is 0)
+ *
+ * Diagonal and banded calls read only the entries inside the band.
+ */
+ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const void *A, int64_t lda,
+                           void *coeff, void *ws, size_t ws_bytes, ptd_stream stream);
+
+/*
+ * pauli_reconstruct: A = sum_P c_P P (the expansion of Sec. II-A), the
+ * inverse of pauli_decompose; with PTD_ADJOINT, A = 2^-n sum_P c_P P.
+ *
+ *   coeff    dense [x][z] coefficients (complex of dtype; real with
+ *            PTD_HERMITIAN, giving a Hermitian A)
+ *   A, lda   output matrix, lda >= 2^n; all 4^n entries are written
+ *   flags    PTD_HERMITIAN | PTD_ADJOINT
+ */
+ptd_status pauli_reconstruct(int n, ptd_dtype dtype, unsigned flags, const void *coeff, void *A,
+                             int64_t lda, void *ws, size_t ws_bytes, ptd_stream stream);
+
+/*
+ * Parseval check (Theorem 1: the strings are orthogonal with Tr(P^* P) = 2^n,
+ * so ||A||_F^2 = 2^n sum_P |c_P|^2).  Reduces both sides in float64 on the
+ * device (also for PTD_C64 data) and copies them to out_host[0] =
+ * ||A||_F^2, out_host[1] = 2^n sum |c|^2, out_host[2] = |out[0] - out[1]| /
+ * out[0].  flags: PTD_HERMITIAN means coeff is real.  Synchronises `stream`.
+ * ws must hold ptd_reduce_workspace_bytes() bytes.
+ */
+size_t ptd_reduce_workspace_bytes(void);
+ptd_status ptd_parseval_residual(int n, ptd_dtype dtype, unsigned flags, const void *A, int64_t lda,
+                                 const void *coeff, double *out_host, void *ws, size_t ws_bytes,
+                                 ptd_stream stream);
+
+/* Human-readable name of a status code (static string). */
+const char *ptd_status_str(ptd_status st);
+/* HIP error code of the most recent PTD_EHIP on this thread (0 if none). */
+int ptd_last_hip_error(void);
+/* gfx architecture the library was built for, e.g. "gfx950". */
+const char *ptd_build_arch(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTD_H */

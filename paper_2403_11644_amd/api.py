@@ -1,0 +1,241 @@
+"""PyTorch-facing wrappers around the C ABI (argument marshalling only).
+
+Tensors must live on a ROCm device; PyTorch supplies device memory (outputs
+are allocated with ``torch.empty``) and the current stream.  Every step of
+the computation runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _native
+
+C128 = 0
+C64 = 1
+
+HERMITIAN = 1 << 0
+DIAGONAL = 1 << 1
+BANDED = 1 << 2
+BANDS_IN = 1 << 3
+COMPACT = 1 << 4
+COMPENSATED = 1 << 5
+ADJOINT = 1 << 6
+
+
+def _dtype_code(t: torch.dtype) -> int:
+    if t == torch.complex128:
+        return C128
+    if t == torch.complex64:
+        return C64
+    raise TypeError("expected complex128 or complex64, got %s" % t)
+
+
+def _real_dtype(code: int) -> torch.dtype:
+    return torch.float64 if code == C128 else torch.float32
+
+
+def _complex_dtype(code: int) -> torch.dtype:
+    return torch.complex128 if code == C128 else torch.complex64
+
+
+def _nqubits(N: int) -> int:
+    if N < 2 or N & (N - 1):
+        raise ValueError("matrix size must be a power of two >= 2 (use pad=True), got %d" % N)
+    return N.bit_length() - 1
+
+
+def _stream_handle(device: torch.device, stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _require_device(t: torch.Tensor, name: str) -> None:
+    if not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor (the library has no CPU path)" % name)
+
+
+def _rows(t: torch.Tensor, name: str) -> int:
+    """Row pitch in elements of a 2-D tensor whose rows are contiguous."""
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("%s must be 2-D with contiguous rows" % name)
+    return t.stride(0)
+
+
+def pad_to_power_of_two(A: torch.Tensor) -> torch.Tensor:
+    """Embed A top-left in the smallest 2^n x 2^n zero matrix (n >= 1).
+
+    The paper allows zero padding to reach a power-of-two size (Sec. II-A)
+    without fixing where A goes; this library puts it in the top-left block.
+    """
+    r, c = A.shape
+    N = 2
+    while N < max(r, c):
+        N *= 2
+    if (r, c) == (N, N):
+        return A
+    out = torch.zeros((N, N), dtype=A.dtype, device=A.device)
+    out[:r, :c] = A
+    return out
+
+
+def num_nonempty_x(n: int, structure: str | None = None, s: int = 0) -> int:
+    flags = {None: 0, "diagonal": DIAGONAL, "banded": BANDED}[structure]
+    v = _native.lib().ptd_num_nonempty_x(n, flags, s)
+    if v < 0:
+        raise ValueError("bad (n, structure, s) = (%d, %r, %d)" % (n, structure, s))
+    return v
+
+
+def nonempty_x(n: int, structure: str | None = None, s: int = 0) -> list[int]:
+    """X-patterns that can carry a nonzero coefficient, ascending (Sec. IV-A)."""
+    import numpy as np
+
+    flags = {None: 0, "diagonal": DIAGONAL, "banded": BANDED}[structure]
+    cnt = num_nonempty_x(n, structure, s)
+    buf = np.empty(cnt, dtype=np.uint32)
+    _native.check(_native.lib().ptd_nonempty_x(n, flags, s, ctypes.c_void_p(buf.ctypes.data)), "ptd_nonempty_x")
+    return buf.tolist()
+
+
+def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None = None, s: int | None = None,
+              bands: bool = False, compact: bool = False, compensated: bool = False, pad: bool = False,
+              out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Pauli coefficients of A, as a (2^n, 2^n) tensor c[x, z].
+
+    hermitian   A == A^*: return the (real) coefficients as float64/float32.
+    structure   None, 'diagonal' or 'banded' (with half-bandwidth s).
+    bands       A is the row-indexed band array band[d + s][k] = A[k][k + d].
+    compact     structured only: return rows of the nonempty X-patterns only.
+    compensated complex64 only: TwoSum butterflies.
+    pad         zero-pad a non-power-of-two A (top-left embedding).
+    """
+    _require_device(A, "A")
+    code = _dtype_code(A.dtype)
+    flags = 0
+    sv = 0
+    if structure == "diagonal":
+        flags |= DIAGONAL
+    elif structure == "banded":
+        if s is None or s < 1:
+            raise ValueError("banded structure needs s >= 1")
+        flags |= BANDED
+        sv = int(s)
+    elif structure is not None:
+        raise ValueError("structure must be None, 'diagonal' or 'banded'")
+    if bands:
+        if structure is None:
+            raise ValueError("bands=True needs a structure")
+        flags |= BANDS_IN
+        N = A.shape[1]
+        if A.shape[0] != 2 * sv + 1:
+            raise ValueError("band array must have 2s+1 rows")
+    else:
+        if pad:
+            A = pad_to_power_of_two(A)
+        if A.dim() != 2 or A.shape[0] != A.shape[1]:
+            raise ValueError("A must be square")
+        N = A.shape[0]
+    n = _nqubits(N)
+    if hermitian:
+        flags |= HERMITIAN
+    if compact:
+        if structure is None:
+            raise ValueError("compact=True needs a structure")
+        flags |= COMPACT
+    if compensated:
+        flags |= COMPENSATED
+    lda = _rows(A, "A")
+    rows = num_nonempty_x(n, structure, sv) if compact else N
+    odt = _real_dtype(code) if hermitian else _complex_dtype(code)
+    if out is None:
+        out = torch.empty((rows, N), dtype=odt, device=A.device)
+    elif out.shape != (rows, N) or out.dtype != odt or not out.is_contiguous():
+        raise ValueError("out must be a contiguous %s tensor of shape %r" % (odt, (rows, N)))
+    L = _native.lib()
+    wsb = L.ptd_workspace_bytes(n, code, flags, sv)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=A.device) if wsb else None
+    st = L.pauli_decompose(n, code, flags, sv, _ptr(A), lda, _ptr(out), _ptr(ws) if ws is not None else None,
+                           wsb, _stream_handle(A.device, stream))
+    _native.check(st, "pauli_decompose")
+    return out
+
+
+def reconstruct(c: torch.Tensor, *, hermitian: bool = False, adjoint: bool = False, dtype: torch.dtype | None = None,
+                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """A = sum_P c_P P from dense coefficients c[x, z] (adjoint: times 2^-n).
+
+    With hermitian=True, c is real (float64/float32) and A is Hermitian.
+    """
+    _require_device(c, "c")
+    if hermitian:
+        if c.dtype == torch.float64:
+            code = C128
+        elif c.dtype == torch.float32:
+            code = C64
+        else:
+            raise TypeError("hermitian reconstruct takes real float64/float32 coefficients")
+    else:
+        code = _dtype_code(c.dtype)
+    if c.dim() != 2 or c.shape[0] != c.shape[1] or not c.is_contiguous():
+        raise ValueError("c must be a contiguous square (2^n, 2^n) tensor")
+    N = c.shape[0]
+    n = _nqubits(N)
+    flags = (HERMITIAN if hermitian else 0) | (ADJOINT if adjoint else 0)
+    adt = _complex_dtype(code)
+    if out is None:
+        out = torch.empty((N, N), dtype=adt, device=c.device)
+    elif out.dim() != 2 or out.shape != (N, N) or out.dtype != adt or out.stride(1) != 1:
+        raise ValueError("out must be a (2^n, 2^n) %s tensor with contiguous rows" % adt)
+    L = _native.lib()
+    st = L.pauli_reconstruct(n, code, flags, _ptr(c), _ptr(out), out.stride(0), None, 0,
+                             _stream_handle(c.device, stream))
+    _native.check(st, "pauli_reconstruct")
+    return out
+
+
+def parseval(A: torch.Tensor, c: torch.Tensor, *, hermitian: bool = False, stream=None):
+    """(||A||_F^2, 2^n sum|c|^2, relative residual), reduced in float64 on the GPU."""
+    import numpy as np
+
+    _require_device(A, "A")
+    code = _dtype_code(A.dtype)
+    n = _nqubits(A.shape[0])
+    L = _native.lib()
+    wsb = L.ptd_reduce_workspace_bytes()
+    ws = torch.empty(wsb, dtype=torch.uint8, device=A.device)
+    res = np.zeros(3, dtype=np.float64)
+    st = L.ptd_parseval_residual(n, code, HERMITIAN if hermitian else 0, _ptr(A), _rows(A, "A"), _ptr(c),
+                                 ctypes.c_void_p(res.ctypes.data), _ptr(ws), wsb, _stream_handle(A.device, stream))
+    _native.check(st, "ptd_parseval_residual")
+    return float(res[0]), float(res[1]), float(res[2])
+
+
+def _debug_decompose_path(A: torch.Tensor, path: int, hermitian: bool = False) -> torch.Tensor:
+    """Run a specific dense schedule (1 = single pass, 2 = two passes); for tests."""
+    code = _dtype_code(A.dtype)
+    n = _nqubits(A.shape[0])
+    odt = _real_dtype(code) if hermitian else _complex_dtype(code)
+    out = torch.empty((A.shape[0], A.shape[0]), dtype=odt, device=A.device)
+    st = _native.lib().ptd_debug_decompose_path(n, code, HERMITIAN if hermitian else 0, _ptr(A), _rows(A, "A"),
+                                                _ptr(out), path, _stream_handle(A.device, None))
+    _native.check(st, "ptd_debug_decompose_path")
+    return out
+
+
+def _debug_reconstruct_path(c: torch.Tensor, path: int, hermitian: bool = False, adjoint: bool = False):
+    code = (C128 if c.dtype == torch.float64 else C64) if hermitian else _dtype_code(c.dtype)
+    N = c.shape[0]
+    n = _nqubits(N)
+    out = torch.empty((N, N), dtype=_complex_dtype(code), device=c.device)
+    flags = (HERMITIAN if hermitian else 0) | (ADJOINT if adjoint else 0)
+    st = _native.lib().ptd_debug_reconstruct_path(n, code, flags, _ptr(c), _ptr(out), N, path,
+                                                  _stream_handle(c.device, None))
+    _native.check(st, "ptd_debug_reconstruct_path")
+    return out

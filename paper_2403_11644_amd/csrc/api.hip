@@ -1,0 +1,170 @@
+// api.hip -- the C ABI (include/ptd.h): argument validation first, then
+// dispatch to the kernel launchers.  Nothing here touches the GPU before the
+// arguments have been checked, so every argument error is testable on a
+// machine without one.
+#include <stdint.h>
+#include <string.h>
+
+#include "internal.hpp"
+
+namespace {
+
+thread_local int g_last_hip_error = 0;
+
+constexpr unsigned kAllFlags = PTD_HERMITIAN | PTD_DIAGONAL | PTD_BANDED | PTD_BANDS_IN | PTD_COMPACT |
+                               PTD_COMPENSATED | PTD_ADJOINT;
+
+ptd_status hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return PTD_OK;
+    g_last_hip_error = (int)e;
+    return PTD_EHIP;
+}
+
+bool valid_dtype(ptd_dtype dt) { return dt == PTD_C128 || dt == PTD_C64; }
+
+// Structured-flag checks shared by the decompose entry points.
+ptd_status check_structure(int n, unsigned flags, int s)
+{
+    const bool diag = flags & PTD_DIAGONAL, band = flags & PTD_BANDED;
+    if (diag && band) return PTD_EINVAL;
+    if ((flags & (PTD_BANDS_IN | PTD_COMPACT)) && !(diag || band)) return PTD_EINVAL;
+    if (band && (s < 1 || s >= (1 << n))) return PTD_EINVAL;
+    return PTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ptd_status_str(ptd_status st)
+{
+    switch (st) {
+        case PTD_OK: return "PTD_OK";
+        case PTD_EINVAL: return "PTD_EINVAL: invalid argument";
+        case PTD_ENOSPC: return "PTD_ENOSPC: workspace too small";
+        case PTD_EUNSUP: return "PTD_EUNSUP: unsupported request";
+        case PTD_EHIP: return "PTD_EHIP: HIP runtime error";
+        case PTD_ENOMEM: return "PTD_ENOMEM: allocation failed";
+        default: return "PTD_E?: unknown status";
+    }
+}
+
+int ptd_last_hip_error(void) { return g_last_hip_error; }
+
+const char* ptd_build_arch(void) { return "gfx950"; }
+
+size_t ptd_workspace_bytes(int n, ptd_dtype dtype, unsigned flags, int s)
+{
+    (void)n;
+    (void)dtype;
+    (void)flags;
+    (void)s;
+    return 0;
+}
+
+int ptd_num_nonempty_x(int n, unsigned flags, int s)
+{
+    if (n < 1 || n > 16 || (flags & ~kAllFlags)) return -1;
+    if (flags & PTD_DIAGONAL) return (flags & PTD_BANDED) ? -1 : 1;
+    if (flags & PTD_BANDED) {
+        if (s < 1 || s >= (1 << n)) return -1;
+        int count = 1;
+        for (int h = 0; h < n; ++h) count += (s < (1 << h)) ? s : (1 << h);
+        return count;
+    }
+    return 1 << n;
+}
+
+ptd_status ptd_nonempty_x(int n, unsigned flags, int s, uint32_t* xs_host)
+{
+    const int cnt = ptd_num_nonempty_x(n, flags, s);
+    if (cnt < 0 || !xs_host) return PTD_EINVAL;
+    if (!(flags & (PTD_DIAGONAL | PTD_BANDED))) {
+        for (int i = 0; i < cnt; ++i) xs_host[i] = (uint32_t)i;
+        return PTD_OK;
+    }
+    int i = 0;
+    xs_host[i++] = 0;
+    if (flags & PTD_BANDED) {
+        // x = 2^h + y, 0 <= y < 2^h, with min_k |(k ^ x) - k| = 2^h - y <= s
+        for (int h = 0; h < n; ++h) {
+            const int top = 2 << h;
+            const int lo = (top - s > (1 << h)) ? top - s : (1 << h);
+            for (int x = lo; x < top; ++x) xs_host[i++] = (uint32_t)x;
+        }
+    }
+    return PTD_OK;
+}
+
+ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const void* A, int64_t lda, void* coeff,
+                           void* ws, size_t ws_bytes, ptd_stream stream)
+{
+    if (n < 1 || n > 16 || !valid_dtype(dtype) || !A || !coeff) return PTD_EINVAL;
+    if (flags & ~kAllFlags) return PTD_EINVAL;
+    if (flags & PTD_ADJOINT) return PTD_EINVAL;
+    const ptd_status sst = check_structure(n, flags, s);
+    if (sst != PTD_OK) return sst;
+    if (lda < ((int64_t)1 << n)) return PTD_EINVAL;
+    if ((flags & PTD_COMPENSATED) && dtype != PTD_C64) return PTD_EUNSUP;
+    if (ws_bytes < ptd_workspace_bytes(n, dtype, flags, s)) return PTD_ENOSPC;
+    (void)ws;
+    if (A == coeff) return PTD_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const bool herm = flags & PTD_HERMITIAN;
+    if (flags & (PTD_DIAGONAL | PTD_BANDED | PTD_COMPENSATED)) return PTD_EUNSUP;
+    return hip_status(ptd::launch_dense_fwd(n, dtype, herm, A, lda, coeff, 0, st));
+}
+
+ptd_status pauli_reconstruct(int n, ptd_dtype dtype, unsigned flags, const void* coeff, void* A, int64_t lda,
+                             void* ws, size_t ws_bytes, ptd_stream stream)
+{
+    if (n < 1 || n > 16 || !valid_dtype(dtype) || !A || !coeff) return PTD_EINVAL;
+    if (flags & ~(PTD_HERMITIAN | PTD_ADJOINT)) return PTD_EINVAL;
+    if (lda < ((int64_t)1 << n)) return PTD_EINVAL;
+    if (ws_bytes < ptd_workspace_bytes(n, dtype, flags, 0)) return PTD_ENOSPC;
+    (void)ws;
+    if (A == coeff) return PTD_EINVAL;
+    return hip_status(ptd::launch_dense_rec(n, dtype, flags & PTD_HERMITIAN, flags & PTD_ADJOINT, coeff, A, lda, 0,
+                                            (hipStream_t)stream));
+}
+
+size_t ptd_reduce_workspace_bytes(void) { return ptd::reduce_workspace_bytes(); }
+
+ptd_status ptd_parseval_residual(int n, ptd_dtype dtype, unsigned flags, const void* A, int64_t lda, const void* coeff,
+                                 double* out_host, void* ws, size_t ws_bytes, ptd_stream stream)
+{
+    if (n < 1 || n > 16 || !valid_dtype(dtype) || !A || !coeff || !out_host) return PTD_EINVAL;
+    if (flags & ~PTD_HERMITIAN) return PTD_EINVAL;
+    if (lda < ((int64_t)1 << n)) return PTD_EINVAL;
+    if (!ws || ws_bytes < ptd::reduce_workspace_bytes()) return PTD_ENOSPC;
+    return hip_status(ptd::launch_parseval(n, dtype, flags & PTD_HERMITIAN, A, lda, coeff, ws, out_host,
+                                           (hipStream_t)stream));
+}
+
+// Testing hook: force the single-pass (path 1) or two-pass (path 2) schedule.
+ptd_status ptd_debug_decompose_path(int n, ptd_dtype dtype, unsigned flags, const void* A, int64_t lda,
+                                    void* coeff, int path, ptd_stream stream)
+{
+    if (n < 1 || n > 16 || !valid_dtype(dtype) || !A || !coeff || lda < ((int64_t)1 << n)) return PTD_EINVAL;
+    if (flags & ~PTD_HERMITIAN) return PTD_EINVAL;
+    if (path == 1 && n > 10) return PTD_EINVAL;
+    if (path == 2 && n < 7) return PTD_EINVAL;
+    if (path < 0 || path > 2) return PTD_EINVAL;
+    return hip_status(ptd::launch_dense_fwd(n, dtype, flags & PTD_HERMITIAN, A, lda, coeff, path,
+                                            (hipStream_t)stream));
+}
+
+ptd_status ptd_debug_reconstruct_path(int n, ptd_dtype dtype, unsigned flags, const void* coeff, void* A,
+                                      int64_t lda, int path, ptd_stream stream)
+{
+    if (n < 1 || n > 16 || !valid_dtype(dtype) || !A || !coeff || lda < ((int64_t)1 << n)) return PTD_EINVAL;
+    if (flags & ~(PTD_HERMITIAN | PTD_ADJOINT)) return PTD_EINVAL;
+    if (path == 1 && n > 10) return PTD_EINVAL;
+    if (path == 2 && n < 7) return PTD_EINVAL;
+    if (path < 0 || path > 2) return PTD_EINVAL;
+    return hip_status(ptd::launch_dense_rec(n, dtype, flags & PTD_HERMITIAN, flags & PTD_ADJOINT, coeff, A, lda,
+                                            path, (hipStream_t)stream));
+}
+
+}  // extern "C"

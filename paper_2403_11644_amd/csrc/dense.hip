@@ -1,0 +1,466 @@
+// dense.hip -- dense Pauli decomposition and reconstruction kernels (gfx950).
+//
+// Forward map, per X-pattern x (see engine.hpp):
+//   c[x][z] = 2^-n i^popcount(x&z) WHT_z( d_x ),  d_x[k] = A[k][k ^ x].
+//
+// Two schedules:
+//
+//  * single pass, n <= 10 ("group" kernel): one workgroup owns T = 2^t
+//    consecutive X-patterns x = g*T + x_lo.  For row k those patterns read the
+//    T contiguous columns ((k >> t) ^ g) * T + [0, T): one 128-byte segment
+//    per row (T = 16 complex64 / 8 complex128).  The whole band (2^n rows x T)
+//    sits in LDS (<= 128 KiB), the length-2^n WHTs run as radix-16 rounds,
+//    and T full output rows are written once.
+//
+//  * two passes, n >= 11: a 64 x 64 tile (R, C) of A holds d_x[R*64 + k_lo]
+//    for the 64 patterns x = (R ^ C)*64 + x_lo.  Pass 1 ("tile") applies the
+//    six low WHT bits to every tile and writes the partial transform to
+//    coeff[x][R*64 + z_lo] (in place in the output buffer, no workspace).
+//    Pass 2 ("high") applies the remaining n-6 bits along each output row
+//    (stride 64), then the phase i^popcount(x&z) and the 2^-n scale.
+//
+// Hermitian input, real output: the partial transform W1 of the two tiles
+// (R, C) and (C, R) is related by W1[x][C][z_lo] =
+// (-1)^popcount(z_lo & x_lo) * conj(W1[x][R][z_lo]), so pass 1 stores only
+// one real number per slot (the real part in the lower block of the pair,
+// the imaginary part in the upper one; the single nonzero part when R == C)
+// and pass 2 rebuilds both complex values from the pair of slots.
+//
+// Reconstruction runs the inverse: the phase (-i)^popcount(x&z) first, the
+// same WHTs, and a scatter of d_x back to A[k][k ^ x].  For n >= 11 pass 1
+// transforms 64 x 64 coefficient tiles over z_lo and places them in A's
+// tiles (z_hi, z_hi ^ x_hi); pass 2 runs the WHT over the block index in
+// place on A (the WHT over z_hi and the one over z_lo act on different bits
+// and commute).
+#include "engine.hpp"
+#include "internal.hpp"
+
+namespace ptd {
+
+namespace {
+
+constexpr int GROUP_THREADS = 512;
+constexpr int TILE_THREADS = 256;
+constexpr int HIGH_THREADS = 256;
+
+template <class V>
+constexpr int group_logt(int logn)
+{
+    // 128-byte row segments: 16 complex64 or 8 complex128
+    return logn < (sizeof(V) == 4 ? 4 : 3) ? logn : (sizeof(V) == 4 ? 4 : 3);
+}
+
+template <class V>
+constexpr int high_logw()
+{
+    return sizeof(V) == 4 ? 4 : 3;
+}
+
+// ------------------------------------------------------------------------
+// single pass, n <= 10
+
+template <class V, int LOGN, int LOGT, bool REAL_OUT>
+__device__ __forceinline__ void group_fwd(const cplx<V>* __restrict__ A, int64_t lda, void* __restrict__ out,
+                                          int64_t ldo, int g, cplx<V>* lds)
+{
+    constexpr int NT = GROUP_THREADS;
+    const uint32_t xg = (uint32_t)g << LOGT;
+    const V scale = exp2_neg<V>(LOGN);
+    auto gather = [&](int vec, int pos, V& re, V& im) {
+        const cplx<V> v = A[(int64_t)pos * lda + (pos ^ (int)(xg | vec))];
+        re = v.re;
+        im = v.im;
+    };
+    auto store = [&](int vec, int pos, V re, V im) {
+        const uint32_t x = xg | (uint32_t)vec;
+        mul_ipow(__popc(x & (uint32_t)pos) & 3, re, im);
+        re *= scale;
+        im *= scale;
+        if constexpr (REAL_OUT) {
+            ((V*)out)[(int64_t)x * ldo + pos] = re;
+        } else {
+            cplx<V> c;
+            c.re = re;
+            c.im = im;
+            ((cplx<V>*)out)[(int64_t)x * ldo + pos] = c;
+        }
+    };
+    LdsVecs<V, LOGN> lr{lds};
+    LdsVecsW<V, LOGN> lw{lds};
+    if constexpr (LOGN <= 4) {
+        wht_round<V, LOGT, LOGN, 0, LOGN, NT, true>(gather, store);
+    } else if constexpr (LOGN <= 8) {
+        wht_round<V, LOGT, LOGN, 0, 4, NT, true>(gather, lw);
+        __syncthreads();
+        wht_round<V, LOGT, LOGN, 4, LOGN - 4, NT, false>(lr, store);
+    } else {
+        wht_round<V, LOGT, LOGN, 0, 4, NT, true>(gather, lw);
+        __syncthreads();
+        wht_round<V, LOGT, LOGN, 4, 4, NT, false>(lr, lw);
+        __syncthreads();
+        wht_round<V, LOGT, LOGN, 8, LOGN - 8, NT, false>(lr, store);
+    }
+}
+
+template <class V, int LOGN, bool REAL_OUT>
+__global__ __launch_bounds__(GROUP_THREADS) void k_group_fwd(const cplx<V>* __restrict__ A, int64_t lda,
+                                                             void* __restrict__ out, int64_t ldo)
+{
+    constexpr int LOGT = group_logt<V>(LOGN);
+    __shared__ cplx<V> lds[(1 << LOGT) * ((1 << LOGN) + 1)];
+    group_fwd<V, LOGN, LOGT, REAL_OUT>(A, lda, out, ldo, blockIdx.x, lds);
+}
+
+template <class V, int LOGN, int LOGT, bool REAL_IN>
+__device__ __forceinline__ void group_rec(const void* __restrict__ coeff, cplx<V>* __restrict__ A, int64_t lda,
+                                          V scale, int g, cplx<V>* lds)
+{
+    constexpr int NT = GROUP_THREADS;
+    const uint32_t xg = (uint32_t)g << LOGT;
+    auto load = [&](int vec, int pos, V& re, V& im) {
+        const uint32_t x = xg | (uint32_t)vec;
+        const int64_t o = (int64_t)x * (1 << LOGN) + pos;
+        if constexpr (REAL_IN) {
+            re = ((const V*)coeff)[o];
+            im = (V)0;
+        } else {
+            const cplx<V> c = ((const cplx<V>*)coeff)[o];
+            re = c.re;
+            im = c.im;
+        }
+        // (-i)^p = i^{-p}
+        mul_ipow((4 - (__popc(x & (uint32_t)pos) & 3)) & 3, re, im);
+    };
+    auto scatter = [&](int vec, int pos, V re, V im) {
+        cplx<V> c;
+        c.re = re * scale;
+        c.im = im * scale;
+        A[(int64_t)pos * lda + (pos ^ (int)(xg | vec))] = c;
+    };
+    LdsVecs<V, LOGN> lr{lds};
+    LdsVecsW<V, LOGN> lw{lds};
+    if constexpr (LOGN <= 4) {
+        wht_round<V, LOGT, LOGN, 0, LOGN, NT, true>(load, scatter);
+    } else if constexpr (LOGN <= 8) {
+        wht_round<V, LOGT, LOGN, LOGN - 4, 4, NT, false>(load, lw);
+        __syncthreads();
+        wht_round<V, LOGT, LOGN, 0, LOGN - 4, NT, true>(lr, scatter);
+    } else {
+        wht_round<V, LOGT, LOGN, LOGN - 4, 4, NT, false>(load, lw);
+        __syncthreads();
+        wht_round<V, LOGT, LOGN, LOGN - 8, 4, NT, false>(lr, lw);
+        __syncthreads();
+        wht_round<V, LOGT, LOGN, 0, LOGN - 8, NT, true>(lr, scatter);
+    }
+}
+
+template <class V, int LOGN, bool REAL_IN>
+__global__ __launch_bounds__(GROUP_THREADS) void k_group_rec(const void* __restrict__ coeff,
+                                                             cplx<V>* __restrict__ A, int64_t lda, V scale)
+{
+    constexpr int LOGT = group_logt<V>(LOGN);
+    __shared__ cplx<V> lds[(1 << LOGT) * ((1 << LOGN) + 1)];
+    group_rec<V, LOGN, LOGT, REAL_IN>(coeff, A, lda, scale, blockIdx.x, lds);
+}
+
+// ------------------------------------------------------------------------
+// two passes, pass 1: 64 x 64 tiles, low six WHT bits
+
+template <class V, bool HERM>
+__global__ __launch_bounds__(TILE_THREADS) void k_tile_fwd(const cplx<V>* __restrict__ A, int64_t lda,
+                                                           void* __restrict__ out, int64_t ldo)
+{
+    __shared__ cplx<V> lds[64 * 65];
+    const int R = blockIdx.y, C = blockIdx.x;
+    const int xh = R ^ C;
+    const cplx<V>* tile = A + (int64_t)R * 64 * lda + (int64_t)C * 64;
+    auto gather = [&](int vec, int pos, V& re, V& im) {
+        const cplx<V> v = tile[(int64_t)pos * lda + (pos ^ vec)];
+        re = v.re;
+        im = v.im;
+    };
+    auto store = [&](int vec, int pos, V re, V im) {
+        const int64_t o = (int64_t)((xh << 6) | vec) * ldo + ((int64_t)R << 6) + pos;
+        if constexpr (HERM) {
+            const bool sneg = __popc((uint32_t)(pos & vec)) & 1;
+            V val;
+            if (R < C)
+                val = re;
+            else if (R > C)
+                val = sneg ? im : -im;
+            else
+                val = sneg ? im : re;
+            ((V*)out)[o] = val;
+        } else {
+            cplx<V> c;
+            c.re = re;
+            c.im = im;
+            ((cplx<V>*)out)[o] = c;
+        }
+    };
+    LdsVecs<V, 6> lr{lds};
+    LdsVecsW<V, 6> lw{lds};
+    wht_round<V, 6, 6, 0, 4, TILE_THREADS, true>(gather, lw);
+    __syncthreads();
+    wht_round<V, 6, 6, 4, 2, TILE_THREADS, false>(lr, store);
+}
+
+// pass 2: WHT over the block index (stride 64) of each output row chunk,
+// then the phase and the scale.
+template <class V, int LOGM, bool HERM>
+__global__ __launch_bounds__(HIGH_THREADS) void k_high_fwd(void* __restrict__ out, int64_t ldo)
+{
+    constexpr int LOGW = high_logw<V>();
+    constexpr int CH = 6 - LOGW;
+    constexpr int NT = HIGH_THREADS;
+    __shared__ cplx<V> lds[(1 << LOGW) * ((1 << LOGM) + 1)];
+    const int x = blockIdx.x >> CH;
+    const int z0 = (blockIdx.x & ((1 << CH) - 1)) << LOGW;
+    const int xh = x >> 6, xl = x & 63;
+    V* rowr = (V*)out + (int64_t)x * ldo;
+    cplx<V>* rowc = (cplx<V>*)out + (int64_t)x * ldo;
+    const V scale = exp2_neg<V>(LOGM + 6);
+    auto load = [&](int vec, int pos, V& re, V& im) {
+        const int zl = z0 + vec;
+        if constexpr (HERM) {
+            const int pp = pos ^ xh;
+            const V a = rowr[(pos << 6) + zl];
+            const bool sneg = __popc((uint32_t)(zl & xl)) & 1;
+            if (pos < pp) {
+                re = a;
+                im = rowr[(pp << 6) + zl];
+            } else if (pos > pp) {
+                const V b = rowr[(pp << 6) + zl];
+                re = sneg ? -b : b;
+                im = sneg ? a : -a;
+            } else {
+                re = sneg ? (V)0 : a;
+                im = sneg ? a : (V)0;
+            }
+        } else {
+            const cplx<V> v = rowc[(pos << 6) + zl];
+            re = v.re;
+            im = v.im;
+        }
+    };
+    auto store = [&](int vec, int pos, V re, V im) {
+        const int z = (pos << 6) + z0 + vec;
+        mul_ipow(__popc((uint32_t)(x & z)) & 3, re, im);
+        if constexpr (HERM) {
+            rowr[z] = re * scale;
+        } else {
+            cplx<V> c;
+            c.re = re * scale;
+            c.im = im * scale;
+            rowc[z] = c;
+        }
+    };
+    LdsVecs<V, LOGM> lr{lds};
+    LdsVecsW<V, LOGM> lw{lds};
+    if constexpr (LOGM <= 4) {
+        wht_round<V, LOGW, LOGM, 0, LOGM, NT, true>(load, store);
+    } else if constexpr (LOGM <= 8) {
+        wht_round<V, LOGW, LOGM, 0, 4, NT, true>(load, lw);
+        __syncthreads();
+        wht_round<V, LOGW, LOGM, 4, LOGM - 4, NT, true>(lr, store);
+    } else {
+        wht_round<V, LOGW, LOGM, 0, 4, NT, true>(load, lw);
+        __syncthreads();
+        wht_round<V, LOGW, LOGM, 4, 4, NT, true>(lr, lw);
+        __syncthreads();
+        wht_round<V, LOGW, LOGM, 8, LOGM - 8, NT, true>(lr, store);
+    }
+}
+
+// reconstruction pass 1: coefficient tile (x_hi, zb) -> A tile (zb, zb ^ x_hi)
+template <class V, bool REAL_IN>
+__global__ __launch_bounds__(TILE_THREADS) void k_tile_rec(const void* __restrict__ coeff, int64_t ldc,
+                                                           cplx<V>* __restrict__ A, int64_t lda)
+{
+    __shared__ cplx<V> lds[64 * 65];
+    const int xh = blockIdx.y, zb = blockIdx.x;
+    auto load = [&](int vec, int pos, V& re, V& im) {
+        const uint32_t x = (uint32_t)((xh << 6) | vec);
+        const uint32_t z = (uint32_t)((zb << 6) | pos);
+        const int64_t o = (int64_t)x * ldc + z;
+        if constexpr (REAL_IN) {
+            re = ((const V*)coeff)[o];
+            im = (V)0;
+        } else {
+            const cplx<V> c = ((const cplx<V>*)coeff)[o];
+            re = c.re;
+            im = c.im;
+        }
+        mul_ipow((4 - (__popc(x & z) & 3)) & 3, re, im);
+    };
+    cplx<V>* tile = A + (int64_t)zb * 64 * lda + (int64_t)(zb ^ xh) * 64;
+    auto scatter = [&](int vec, int pos, V re, V im) {
+        cplx<V> c;
+        c.re = re;
+        c.im = im;
+        tile[(int64_t)pos * lda + (pos ^ vec)] = c;
+    };
+    LdsVecs<V, 6> lr{lds};
+    LdsVecsW<V, 6> lw{lds};
+    wht_round<V, 6, 6, 0, 4, TILE_THREADS, false>(load, lw);
+    __syncthreads();
+    wht_round<V, 6, 6, 4, 2, TILE_THREADS, true>(lr, scatter);
+}
+
+// reconstruction pass 2: WHT over the block index along the x_hi band of A,
+// in place.  Workgroup = (x_hi, k_lo, chunk of x_lo).
+template <class V, int LOGM>
+__global__ __launch_bounds__(HIGH_THREADS) void k_high_rec(cplx<V>* __restrict__ A, int64_t lda, V scale)
+{
+    constexpr int LOGW = high_logw<V>();
+    constexpr int CH = 6 - LOGW;
+    constexpr int NT = HIGH_THREADS;
+    __shared__ cplx<V> lds[(1 << LOGW) * ((1 << LOGM) + 1)];
+    const int id = blockIdx.x;
+    const int x0 = (id & ((1 << CH) - 1)) << LOGW;
+    const int klo = (id >> CH) & 63;
+    const int xh = id >> (CH + 6);
+    auto addr = [&](int vec, int pos) -> int64_t {
+        return ((int64_t)pos * 64 + klo) * lda + (int64_t)(pos ^ xh) * 64 + (klo ^ (x0 + vec));
+    };
+    auto load = [&](int vec, int pos, V& re, V& im) {
+        const cplx<V> v = A[addr(vec, pos)];
+        re = v.re;
+        im = v.im;
+    };
+    auto store = [&](int vec, int pos, V re, V im) {
+        cplx<V> c;
+        c.re = re * scale;
+        c.im = im * scale;
+        A[addr(vec, pos)] = c;
+    };
+    LdsVecs<V, LOGM> lr{lds};
+    LdsVecsW<V, LOGM> lw{lds};
+    if constexpr (LOGM <= 4) {
+        wht_round<V, LOGW, LOGM, 0, LOGM, NT, true>(load, store);
+    } else if constexpr (LOGM <= 8) {
+        wht_round<V, LOGW, LOGM, 0, 4, NT, true>(load, lw);
+        __syncthreads();
+        wht_round<V, LOGW, LOGM, 4, LOGM - 4, NT, true>(lr, store);
+    } else {
+        wht_round<V, LOGW, LOGM, 0, 4, NT, true>(load, lw);
+        __syncthreads();
+        wht_round<V, LOGW, LOGM, 4, 4, NT, true>(lr, lw);
+        __syncthreads();
+        wht_round<V, LOGW, LOGM, 8, LOGM - 8, NT, true>(lr, store);
+    }
+}
+
+// ------------------------------------------------------------------------
+// dispatch over n (compile-time sizes)
+
+template <class V, bool HERM>
+hipError_t fwd_group(int n, const void* A, int64_t lda, void* out, hipStream_t st)
+{
+    const cplx<V>* a = (const cplx<V>*)A;
+    const int64_t ldo = (int64_t)1 << n;
+    const int logt = group_logt<V>(n);
+    const dim3 grid(1u << (n - logt)), block(GROUP_THREADS);
+    switch (n) {
+#define PTD_CASE(NN) \
+    case NN: hipLaunchKernelGGL((k_group_fwd<V, NN, HERM>), grid, block, 0, st, a, lda, out, ldo); break;
+        PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5)
+        PTD_CASE(6) PTD_CASE(7) PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
+#undef PTD_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <class V, bool HERM>
+hipError_t fwd_two_pass(int n, const void* A, int64_t lda, void* out, hipStream_t st)
+{
+    const cplx<V>* a = (const cplx<V>*)A;
+    const int64_t ldo = (int64_t)1 << n;
+    const int nb = 1 << (n - 6);
+    hipLaunchKernelGGL((k_tile_fwd<V, HERM>), dim3(nb, nb), dim3(TILE_THREADS), 0, st, a, lda, out, ldo);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 g2((unsigned)(((int64_t)1 << n) << (6 - high_logw<V>())));
+    switch (n - 6) {
+#define PTD_CASE(MM) \
+    case MM: hipLaunchKernelGGL((k_high_fwd<V, MM, HERM>), g2, dim3(HIGH_THREADS), 0, st, out, ldo); break;
+        PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5)
+        PTD_CASE(6) PTD_CASE(7) PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
+#undef PTD_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <class V, bool HERM>
+hipError_t rec_group(int n, const void* coeff, void* A, int64_t lda, V scale, hipStream_t st)
+{
+    cplx<V>* a = (cplx<V>*)A;
+    const int logt = group_logt<V>(n);
+    const dim3 grid(1u << (n - logt)), block(GROUP_THREADS);
+    switch (n) {
+#define PTD_CASE(NN) \
+    case NN: hipLaunchKernelGGL((k_group_rec<V, NN, HERM>), grid, block, 0, st, coeff, a, lda, scale); break;
+        PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5)
+        PTD_CASE(6) PTD_CASE(7) PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
+#undef PTD_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <class V, bool HERM>
+hipError_t rec_two_pass(int n, const void* coeff, void* A, int64_t lda, V scale, hipStream_t st)
+{
+    cplx<V>* a = (cplx<V>*)A;
+    const int64_t ldc = (int64_t)1 << n;
+    const int nb = 1 << (n - 6);
+    hipLaunchKernelGGL((k_tile_rec<V, HERM>), dim3(nb, nb), dim3(TILE_THREADS), 0, st, coeff, ldc, a, lda);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 g2((unsigned)(((int64_t)1 << n) << (6 - high_logw<V>())));
+    switch (n - 6) {
+#define PTD_CASE(MM) \
+    case MM: hipLaunchKernelGGL((k_high_rec<V, MM>), g2, dim3(HIGH_THREADS), 0, st, a, lda, scale); break;
+        PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5)
+        PTD_CASE(6) PTD_CASE(7) PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
+#undef PTD_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_dense_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out, int path,
+                            hipStream_t st)
+{
+    const bool two = path == 2 ? true : path == 1 ? false : n > 10;
+    if (two && n < 7) return hipErrorInvalidValue;
+    if (!two && n > 10) return hipErrorInvalidValue;
+    if (dt == PTD_C128) {
+        if (two) return herm ? fwd_two_pass<double, true>(n, A, lda, out, st) : fwd_two_pass<double, false>(n, A, lda, out, st);
+        return herm ? fwd_group<double, true>(n, A, lda, out, st) : fwd_group<double, false>(n, A, lda, out, st);
+    }
+    if (two) return herm ? fwd_two_pass<float, true>(n, A, lda, out, st) : fwd_two_pass<float, false>(n, A, lda, out, st);
+    return herm ? fwd_group<float, true>(n, A, lda, out, st) : fwd_group<float, false>(n, A, lda, out, st);
+}
+
+hipError_t launch_dense_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const void* coeff, void* A, int64_t lda,
+                            int path, hipStream_t st)
+{
+    const bool two = path == 2 ? true : path == 1 ? false : n > 10;
+    if (two && n < 7) return hipErrorInvalidValue;
+    if (!two && n > 10) return hipErrorInvalidValue;
+    if (dt == PTD_C128) {
+        const double sc = adjoint ? 1.0 / (double)(1u << n) : 1.0;
+        if (two) return herm ? rec_two_pass<double, true>(n, coeff, A, lda, sc, st) : rec_two_pass<double, false>(n, coeff, A, lda, sc, st);
+        return herm ? rec_group<double, true>(n, coeff, A, lda, sc, st) : rec_group<double, false>(n, coeff, A, lda, sc, st);
+    }
+    const float sc = adjoint ? 1.0f / (float)(1u << n) : 1.0f;
+    if (two) return herm ? rec_two_pass<float, true>(n, coeff, A, lda, sc, st) : rec_two_pass<float, false>(n, coeff, A, lda, sc, st);
+    return herm ? rec_group<float, true>(n, coeff, A, lda, sc, st) : rec_group<float, false>(n, coeff, A, lda, sc, st);
+}
+
+}  // namespace ptd

@@ -1,0 +1,142 @@
+// engine.hpp -- device building blocks shared by the gfx950 kernels.
+//
+// The Pauli coefficients of a 2^n x 2^n matrix A are, for every X-pattern x
+// and Z-pattern z (qubit q = bit q; letter (x_q, z_q) = (0,0) I, (1,0) X,
+// (1,1) Y, (0,1) Z),
+//
+//     c[x][z] = 2^-n * i^popcount(x & z) * sum_k (-1)^popcount(z & k) * A[k][k ^ x].
+//
+// This is the definition c_P = 2^-n Tr(P A) (paper, Sec. II-A) with P's single
+// nonzero per row (Sec. II-A, first optimization of the trace) written in
+// closed form: P[r][r ^ x] = (-i)^popcount(x & z) * (-1)^popcount(z & r), and
+// the Y phase P = (-i)^{n_Y} P~ of Sec. II-B collected into one power of i.
+// For each x the inner sum is a length-2^n Walsh-Hadamard transform (WHT)
+// of the generalised diagonal d_x[k] = A[k][k ^ x].
+//
+// Kernels here hold a small set of vectors in LDS and run the WHT as rounds:
+// each round applies the radix-2 butterflies of up to 4 consecutive index
+// bits in registers (a radix-16 step per work item), reading its operands
+// from a source functor and writing results to a destination functor (global
+// gather, LDS, or global store with the fused phase and scale).
+//
+// Floating point: butterflies are plain adds and subtracts, one radix-2 stage
+// per index bit, so the network is invariant under XOR-permuting its input
+// (fl(b + a) = fl(a + b), fl(b - a) = -fl(a - b)).  For a Hermitian A this
+// makes the imaginary part of every phased coefficient exactly zero.  The
+// phase is a swap/negation and the scale an exact power of two.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ptd {
+
+template <class V>
+struct alignas(2 * sizeof(V)) cplx {
+    V re, im;
+};
+
+// In-place radix-2^NB WHT of (re[m], im[m]), m < 2^NB, natural order.
+template <class V, int NB>
+__device__ __forceinline__ void wht_reg(V* re, V* im)
+{
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int m = 0; m < (1 << NB); ++m) {
+            if (!(m & (1 << b))) {
+                const int p = m | (1 << b);
+                const V ur = re[m], ui = im[m], vr = re[p], vi = im[p];
+                re[m] = ur + vr;
+                im[m] = ui + vi;
+                re[p] = ur - vr;
+                im[p] = ui - vi;
+            }
+        }
+    }
+}
+
+// v with NB zero bits inserted at bit position B0.
+__device__ __forceinline__ int insert_zero_bits(int v, int b0, int nb)
+{
+    const int low = v & ((1 << b0) - 1);
+    return low | ((v >> b0) << (b0 + nb));
+}
+
+// (re, im) *= i^p for p in 0..3 (swaps and negations only: exact).
+template <class V>
+__device__ __forceinline__ void mul_ipow(int p, V& re, V& im)
+{
+    const V r = re, i = im;
+    const V nr = (p & 1) ? i : r;
+    const V ni = (p & 1) ? r : i;
+    re = (p == 1 || p == 2) ? -nr : nr;
+    im = (p >= 2) ? -ni : ni;
+}
+
+// One WHT round over index bits [B0, B0 + NB) of 2^LOG_NV vectors of length
+// 2^LOG_L.  Work items enumerate (vector, position with the round bits
+// cleared); VEC_FAST puts the vector index in the fastest-varying lanes (so
+// lanes of one wave read one matrix row in a gather), otherwise the free
+// position bits vary fastest (contiguous positions per wave).
+template <class V, int LOG_NV, int LOG_L, int B0, int NB, int NTHR, bool VEC_FAST, class Src, class Dst>
+__device__ __forceinline__ void wht_round(const Src& src, const Dst& dst)
+{
+    static_assert(NB >= 1 && NB <= 4, "radix 2..16 per round");
+    static_assert(B0 + NB <= LOG_L, "round bits inside the vector");
+    constexpr int R = 1 << NB;
+    constexpr int NITEMS = 1 << (LOG_NV + LOG_L - NB);
+    for (int it = threadIdx.x; it < NITEMS; it += NTHR) {
+        int vec, base;
+        if constexpr (VEC_FAST) {
+            vec = it & ((1 << LOG_NV) - 1);
+            base = insert_zero_bits(it >> LOG_NV, B0, NB);
+        } else {
+            constexpr int PB = LOG_L - NB;
+            base = insert_zero_bits(it & ((1 << PB) - 1), B0, NB);
+            vec = it >> PB;
+        }
+        V re[R], im[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) src(vec, base + (m << B0), re[m], im[m]);
+        wht_reg<V, NB>(re, im);
+#pragma unroll
+        for (int m = 0; m < R; ++m) dst(vec, base + (m << B0), re[m], im[m]);
+    }
+}
+
+// LDS vector storage: element (vec, pos) at p[vec * (2^LOG_L + 1) + pos].  The
+// one-element pad keeps lanes that differ in vec on different banks.
+template <class V, int LOG_L>
+struct LdsVecs {
+    static constexpr int PITCH = (1 << LOG_L) + 1;
+    cplx<V>* p;
+    __device__ __forceinline__ void operator()(int vec, int pos, V& re, V& im) const
+    {
+        const cplx<V> v = p[vec * PITCH + pos];
+        re = v.re;
+        im = v.im;
+    }
+};
+
+template <class V, int LOG_L>
+struct LdsVecsW {
+    static constexpr int PITCH = (1 << LOG_L) + 1;
+    cplx<V>* p;
+    __device__ __forceinline__ void operator()(int vec, int pos, V re, V im) const
+    {
+        cplx<V> v;
+        v.re = re;
+        v.im = im;
+        p[vec * PITCH + pos] = v;
+    }
+};
+
+template <class V>
+__device__ __forceinline__ V exp2_neg(int n)
+{
+    // 2^-n exactly (n <= 30 keeps it a normal number in both precisions)
+    return (V)1 / (V)(1u << n);
+}
+
+}  // namespace ptd

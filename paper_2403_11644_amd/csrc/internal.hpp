@@ -1,0 +1,26 @@
+// internal.hpp -- launchers shared between the host API and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ptd.h"
+
+namespace ptd {
+
+// Dense decompose: coeff[x][z] (complex, or real when herm) for n in 1..16.
+// path: 0 = automatic, 1 = force the single-pass group kernel (n <= 10),
+// 2 = force the two-pass tile + high kernels (n >= 7).
+hipError_t launch_dense_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out,
+                            int path, hipStream_t st);
+
+// Dense reconstruct: A = scale_log2 ... A = 2^-adj_n * sum_P c_P P.
+hipError_t launch_dense_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const void* coeff, void* A,
+                            int64_t lda, int path, hipStream_t st);
+
+// Parseval residual: out_host[0] = ||A||_F^2, [1] = 2^n sum|c|^2, [2] = relative gap.
+size_t reduce_workspace_bytes();
+hipError_t launch_parseval(int n, ptd_dtype dt, bool real_coeff, const void* A, int64_t lda, const void* coeff,
+                           void* ws, double* out_host, hipStream_t st);
+
+}  // namespace ptd

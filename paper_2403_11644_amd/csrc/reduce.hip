@@ -1,0 +1,120 @@
+// reduce.hip -- float64 norm reductions for the Parseval residual.
+//
+// Theorem 1 of the paper makes the Pauli strings orthogonal with
+// Tr(P^* P) = 2^n, hence ||A||_F^2 = 2^n sum_P |c_P|^2.  Both sides are summed
+// here in float64 (also for complex64 data) with a fixed two-level tree, so
+// the result is deterministic for a given input.
+#include "engine.hpp"
+#include "internal.hpp"
+
+namespace ptd {
+
+namespace {
+
+constexpr int RED_BLOCKS = 1024;
+constexpr int RED_THREADS = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// sum of |A[r][c]|^2 over the 2^n x 2^n matrix with row pitch lda
+template <class V>
+__global__ __launch_bounds__(RED_THREADS) void k_sumsq_matrix(const cplx<V>* __restrict__ A, int64_t lda, int n,
+                                                               double* __restrict__ partial)
+{
+    __shared__ double sh[RED_THREADS];
+    const int64_t N = (int64_t)1 << n;
+    const int64_t total = N * N;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * RED_THREADS) {
+        const int64_t r = i >> n, c = i & (N - 1);
+        const cplx<V> v = A[r * lda + c];
+        const double a = (double)v.re, b = (double)v.im;
+        acc += a * a;
+        acc += b * b;
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// sum of squares of `count` real values
+template <class V>
+__global__ __launch_bounds__(RED_THREADS) void k_sumsq_vec(const V* __restrict__ v, int64_t count,
+                                                            double* __restrict__ partial)
+{
+    __shared__ double sh[RED_THREADS];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * RED_THREADS) {
+        const double a = (double)v[i];
+        acc += a * a;
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_finish(const double* __restrict__ pa, const double* __restrict__ pc,
+                                                        int nblk, double* __restrict__ out2)
+{
+    __shared__ double sh[RED_THREADS];
+    double a = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += RED_THREADS) {
+        a += pa[i];
+        c += pc[i];
+    }
+    const double sa = block_sum(a, sh);
+    __syncthreads();
+    const double sc = block_sum(c, sh);
+    if (threadIdx.x == 0) {
+        out2[0] = sa;
+        out2[1] = sc;
+    }
+}
+
+}  // namespace
+
+size_t reduce_workspace_bytes() { return (size_t)(2 * RED_BLOCKS + 2) * sizeof(double); }
+
+hipError_t launch_parseval(int n, ptd_dtype dt, bool real_coeff, const void* A, int64_t lda, const void* coeff,
+                           void* ws, double* out_host, hipStream_t st)
+{
+    double* pa = (double*)ws;
+    double* pc = pa + RED_BLOCKS;
+    double* fin = pc + RED_BLOCKS;
+    const int64_t count = ((int64_t)1 << (2 * n)) * (real_coeff ? 1 : 2);
+    if (dt == PTD_C128) {
+        hipLaunchKernelGGL(k_sumsq_matrix<double>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st,
+                           (const cplx<double>*)A, lda, n, pa);
+        hipLaunchKernelGGL(k_sumsq_vec<double>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, (const double*)coeff,
+                           count, pc);
+    } else {
+        hipLaunchKernelGGL(k_sumsq_matrix<float>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st,
+                           (const cplx<float>*)A, lda, n, pa);
+        hipLaunchKernelGGL(k_sumsq_vec<float>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, (const float*)coeff,
+                           count, pc);
+    }
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(RED_THREADS), 0, st, pa, pc, RED_BLOCKS, fin);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    double h[2];
+    e = hipMemcpyAsync(h, fin, sizeof h, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    out_host[0] = h[0];
+    out_host[1] = h[1] * (double)((int64_t)1 << n);
+    const double d = out_host[0] - out_host[1];
+    out_host[2] = (d < 0 ? -d : d) / (out_host[0] > 0 ? out_host[0] : 1.0);
+    return hipSuccess;
+}
+
+}  // namespace ptd

@@ -1,0 +1,37 @@
+"""Pauli-string labels <-> (x, z) indices.
+
+A string is stored at coeff[x][z] (x = X-pattern, z = Z-pattern) with
+(x_q, z_q) = (0,0) I, (1,0) X, (1,1) Y, (0,1) Z on qubit q; qubit q is bit q
+of the matrix index, so the leftmost label character is qubit n-1
+(P = s_{n-1} (x) ... (x) s_0, paper Sec. II-B).
+"""
+from __future__ import annotations
+
+_TO_LETTER = {(0, 0): "I", (1, 0): "X", (1, 1): "Y", (0, 1): "Z"}
+_FROM_LETTER = {v: k for k, v in _TO_LETTER.items()}
+
+
+def label(x: int, z: int, n: int) -> str:
+    if not (0 <= x < (1 << n) and 0 <= z < (1 << n)):
+        raise ValueError("x and z must lie in [0, 2^n)")
+    return "".join(_TO_LETTER[((x >> q) & 1, (z >> q) & 1)] for q in range(n - 1, -1, -1))
+
+
+def index(lab: str) -> tuple[int, int]:
+    """(x, z) of a label such as 'XIZY'."""
+    x = z = 0
+    n = len(lab)
+    for j, ch in enumerate(lab.upper()):
+        try:
+            xb, zb = _FROM_LETTER[ch]
+        except KeyError:
+            raise ValueError("bad Pauli letter %r" % ch) from None
+        q = n - 1 - j
+        x |= xb << q
+        z |= zb << q
+    return x, z
+
+
+def flat_index(lab: str) -> int:
+    x, z = index(lab)
+    return (x << len(lab)) | z

@@ -1,0 +1,116 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/ptd.h, and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ptd.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", src)
+    skip = {"if", "defined", "sizeof"}
+    return sorted({n for n in names if n not in skip and (n.startswith("ptd_") or n.startswith("pauli_"))})
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2403_11644_amd import _native
+
+    return _native.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared_functions()
+    assert "pauli_decompose" in names and "pauli_reconstruct" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings(lib):
+    for st in (0, -1, -2, -3, -4, -5, -99):
+        assert lib.ptd_status_str(st)
+    assert lib.ptd_build_arch() == b"gfx950"
+
+
+def test_workspace_is_zero(lib):
+    for n in (1, 8, 14, 16):
+        for dt in (0, 1):
+            assert lib.ptd_workspace_bytes(n, dt, 0, 0) == 0
+
+
+def test_nonempty_counts_match_bruteforce(lib, oracle_mod):
+    from paper_2403_11644_amd import api
+
+    for n, s in [(3, 1), (5, 1), (6, 2), (6, 3), (7, 5), (8, 8), (9, 7), (10, 8)]:
+        got = api.nonempty_x(n, "banded", s)
+        assert got == oracle_mod.nonempty_x_bruteforce(n, s)
+        assert len(got) * (1 << n) == oracle_mod.band_term_bound(n, s)
+    assert api.nonempty_x(6, "diagonal") == [0]
+    assert api.num_nonempty_x(14, "banded", 8) == 96
+    assert api.num_nonempty_x(14, "banded", 1) == 15
+    assert api.num_nonempty_x(5) == 32
+
+
+def _dec(lib, n=4, dt=0, flags=0, s=0, A=1, lda=16, C=2, ws=None, wsb=0):
+    return lib.pauli_decompose(n, dt, flags, s, ctypes.c_void_p(A), lda, ctypes.c_void_p(C),
+                               ctypes.c_void_p(ws) if ws else None, wsb, None)
+
+
+def test_decompose_argument_errors(lib):
+    EINVAL, EUNSUP = -1, -3
+    # fake non-null "device" pointers: validation must reject before touching them
+    assert _dec(lib, n=0) == EINVAL
+    assert _dec(lib, n=17, lda=1 << 17) == EINVAL
+    assert _dec(lib, dt=2) == EINVAL
+    assert _dec(lib, A=0) == EINVAL
+    assert _dec(lib, C=0) == EINVAL
+    assert _dec(lib, lda=15) == EINVAL
+    assert _dec(lib, flags=1 << 12) == EINVAL
+    assert _dec(lib, flags=(1 << 1) | (1 << 2), s=1) == EINVAL  # diagonal + banded
+    assert _dec(lib, flags=(1 << 2), s=0) == EINVAL  # banded needs s >= 1
+    assert _dec(lib, flags=(1 << 2), s=16) == EINVAL  # s < 2^n
+    assert _dec(lib, flags=(1 << 3)) == EINVAL  # bands-in without structure
+    assert _dec(lib, flags=(1 << 4)) == EINVAL  # compact without structure
+    assert _dec(lib, flags=(1 << 6)) == EINVAL  # adjoint is a reconstruct flag
+    assert _dec(lib, flags=(1 << 5), dt=0) == EUNSUP  # compensated is complex64 only
+    assert _dec(lib, A=5, C=5) == EINVAL  # in place is not allowed
+
+
+def test_reconstruct_argument_errors(lib):
+    EINVAL = -1
+
+    def rec(n=4, dt=0, flags=0, C=1, A=2, lda=16):
+        return lib.pauli_reconstruct(n, dt, flags, ctypes.c_void_p(C), ctypes.c_void_p(A), lda, None, 0, None)
+
+    assert rec(n=0) == EINVAL
+    assert rec(C=0) == EINVAL
+    assert rec(A=0) == EINVAL
+    assert rec(lda=8) == EINVAL
+    assert rec(flags=1 << 1) == EINVAL
+    assert rec(dt=3) == EINVAL
+
+
+def test_nonempty_x_errors(lib):
+    buf = np.zeros(4, dtype=np.uint32)
+    assert lib.ptd_nonempty_x(4, 1 << 2, 0, ctypes.c_void_p(buf.ctypes.data)) == -1
+    assert lib.ptd_nonempty_x(4, 1 << 2, 1, None) == -1
+    assert lib.ptd_num_nonempty_x(0, 0, 0) == -1
+
+
+def test_labels():
+    from paper_2403_11644_amd import labels
+
+    assert labels.label(1, 3, 2) == "ZY"
+    for n in (1, 3, 5):
+        for x in range(1 << n):
+            for z in range(0, 1 << n, 3):
+                assert labels.index(labels.label(x, z, n)) == (x, z)
+    with pytest.raises(ValueError):
+        labels.index("XQ")
