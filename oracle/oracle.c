@@ -151,6 +151,7 @@ typedef struct {
     int64_t count;
     const uint32_t *xs, *zs;
     const uint64_t *keys; /* (x << 40) | sample index, sorted */
+    const uint32_t *rows; /* row mode: the X-patterns to evaluate */
     int nthreads, tid;
 } job_t;
 
@@ -289,6 +290,42 @@ static void *sample_worker(void *arg)
     return NULL;
 }
 
+/* Whole rows: every string of each listed X-pattern, out[i][z]. */
+static void *rows_worker(void *arg)
+{
+    job_t *jb = (job_t *)arg;
+    int n = jb->n;
+    uint64_t N = (uint64_t)1 << n;
+    uint64_t *col = malloc(N * sizeof(uint64_t));
+    int8_t *mre = malloc(N), *mim = malloc(N);
+    double *walk = malloc(N * 2 * sizeof(double));
+    uint8_t letters[64];
+    double scale = 1.0;
+    for (int q = 0; q < n; ++q) scale *= 0.5;
+    for (int64_t i = jb->tid; i < jb->count; i += jb->nthreads) {
+        uint64_t x = jb->rows[i];
+        letters_of(n, x, 0, letters);
+        oracle_pauli_sparse(n, letters, col, mre, mim);
+        for (uint64_t j = 0; j < N; ++j) {
+            walk[2 * j] = jb->Ad[2 * (col[j] * N + j)];
+            walk[2 * j + 1] = jb->Ad[2 * (col[j] * N + j) + 1];
+        }
+        for (uint64_t z = 0; z < N; ++z) {
+            letters_of(n, x, z, letters);
+            oracle_pauli_sparse(n, letters, col, mre, mim);
+            double re, im;
+            trace_d_hoisted(n, walk, mre, mim, &re, &im);
+            jb->outd[2 * ((uint64_t)i * N + z)] = re * scale;
+            jb->outd[2 * ((uint64_t)i * N + z) + 1] = im * scale;
+        }
+    }
+    free(col);
+    free(mre);
+    free(mim);
+    free(walk);
+    return NULL;
+}
+
 static int cmp_u64(const void *a, const void *b)
 {
     uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
@@ -397,4 +434,21 @@ int oracle_reconstruct_f64(int n, const double *coeff, double *A)
     free(mre);
     free(mim);
     return 0;
+}
+
+/* Every coefficient of the listed X-patterns: out[i * 2^n + z] (complex,
+ * interleaved) for x = xs[i]. */
+int oracle_rows_f64(int n, const double *A, int64_t count, const uint32_t *xs, double *out, int nthreads)
+{
+    if (n < 1 || n > 20 || !A || !out || count < 0 || (count > 0 && !xs)) return -1;
+    for (int64_t i = 0; i < count; ++i)
+        if (xs[i] >= ((uint64_t)1 << n)) return -1;
+    job_t jb;
+    memset(&jb, 0, sizeof jb);
+    jb.n = n;
+    jb.Ad = A;
+    jb.outd = out;
+    jb.count = count;
+    jb.rows = xs;
+    return run_threads(&jb, nthreads, rows_worker);
 }

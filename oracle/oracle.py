@@ -78,6 +78,8 @@ def _load():
             lib.oracle_decompose_i64.restype = ctypes.c_int
             lib.oracle_coeffs_f64.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P, P, ctypes.c_int]
             lib.oracle_coeffs_f64.restype = ctypes.c_int
+            lib.oracle_rows_f64.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P, ctypes.c_int]
+            lib.oracle_rows_f64.restype = ctypes.c_int
             lib.oracle_reconstruct_f64.argtypes = [ctypes.c_int, P, P]
             lib.oracle_reconstruct_f64.restype = ctypes.c_int
             _lib = lib
@@ -209,6 +211,20 @@ def coeffs(A: np.ndarray, xs, zs, nthreads: int | None = None) -> np.ndarray:
                                    nthreads or default_threads())
     if rc != 0:
         raise RuntimeError("oracle_coeffs_f64 failed (%d)" % rc)
+    return out
+
+
+def rows(A: np.ndarray, xs, nthreads: int | None = None) -> np.ndarray:
+    """Every coefficient of the X-patterns xs: out[i, z] = c[xs[i], z] (float64)."""
+    A = np.ascontiguousarray(A)
+    if A.dtype != np.complex128:
+        A = A.astype(np.complex128)
+    n = _nqubits(A)
+    xs = np.ascontiguousarray(xs, dtype=np.uint32)
+    out = np.empty((xs.shape[0], 1 << n), dtype=np.complex128)
+    rc = _load().oracle_rows_f64(n, _ptr(A), xs.shape[0], _ptr(xs), _ptr(out), nthreads or default_threads())
+    if rc != 0:
+        raise RuntimeError("oracle_rows_f64 failed (%d)" % rc)
     return out
 
 

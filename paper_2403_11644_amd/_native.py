@@ -37,6 +37,7 @@ SIGNATURES = {
     # testing hooks (not part of ptd.h)
     "ptd_debug_decompose_path": (I, [I, I, U, P, I64, P, I, P]),
     "ptd_debug_reconstruct_path": (I, [I, I, U, P, P, I64, I, P]),
+    "ptd_debug_decompose_stage": (I, [I, I, U, P, I64, P, I, P]),
 }
 
 

@@ -167,4 +167,14 @@ ptd_status ptd_debug_reconstruct_path(int n, ptd_dtype dtype, unsigned flags, co
                                             path, (hipStream_t)stream));
 }
 
+// Timing hook: launch one pass of the two-pass dense schedule (n >= 7).
+ptd_status ptd_debug_decompose_stage(int n, ptd_dtype dtype, unsigned flags, const void* A, int64_t lda,
+                                     void* coeff, int stage, ptd_stream stream)
+{
+    if (n < 7 || n > 16 || !valid_dtype(dtype) || !A || !coeff || lda < ((int64_t)1 << n)) return PTD_EINVAL;
+    if ((flags & ~PTD_HERMITIAN) || stage < 1 || stage > 3) return PTD_EINVAL;
+    return hip_status(ptd::launch_dense_fwd_stage(n, dtype, flags & PTD_HERMITIAN, A, lda, coeff, stage,
+                                                  (hipStream_t)stream));
+}
+
 }  // extern "C"

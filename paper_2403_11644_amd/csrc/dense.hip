@@ -372,15 +372,19 @@ hipError_t fwd_group(int n, const void* A, int64_t lda, void* out, hipStream_t s
     return hipGetLastError();
 }
 
+// stage: 3 = both passes, 1 = tile pass only, 2 = row pass only (timing)
 template <class V, bool HERM>
-hipError_t fwd_two_pass(int n, const void* A, int64_t lda, void* out, hipStream_t st)
+hipError_t fwd_two_pass(int n, const void* A, int64_t lda, void* out, hipStream_t st, int stage = 3)
 {
     const cplx<V>* a = (const cplx<V>*)A;
     const int64_t ldo = (int64_t)1 << n;
     const int nb = 1 << (n - 6);
-    hipLaunchKernelGGL((k_tile_fwd<V, HERM>), dim3(nb, nb), dim3(TILE_THREADS), 0, st, a, lda, out, ldo);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (stage & 1) {
+        hipLaunchKernelGGL((k_tile_fwd<V, HERM>), dim3(nb, nb), dim3(TILE_THREADS), 0, st, a, lda, out, ldo);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (!(stage & 2)) return hipSuccess;
     const dim3 g2((unsigned)(((int64_t)1 << n) << (6 - high_logw<V>())));
     switch (n - 6) {
 #define PTD_CASE(MM) \
@@ -445,6 +449,17 @@ hipError_t launch_dense_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64
     }
     if (two) return herm ? fwd_two_pass<float, true>(n, A, lda, out, st) : fwd_two_pass<float, false>(n, A, lda, out, st);
     return herm ? fwd_group<float, true>(n, A, lda, out, st) : fwd_group<float, false>(n, A, lda, out, st);
+}
+
+hipError_t launch_dense_fwd_stage(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out, int stage,
+                                  hipStream_t st)
+{
+    if (n < 7 || stage < 1 || stage > 3) return hipErrorInvalidValue;
+    if (dt == PTD_C128)
+        return herm ? fwd_two_pass<double, true>(n, A, lda, out, st, stage)
+                    : fwd_two_pass<double, false>(n, A, lda, out, st, stage);
+    return herm ? fwd_two_pass<float, true>(n, A, lda, out, st, stage)
+                : fwd_two_pass<float, false>(n, A, lda, out, st, stage);
 }
 
 hipError_t launch_dense_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const void* coeff, void* A, int64_t lda,

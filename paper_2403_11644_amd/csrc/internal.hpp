@@ -14,6 +14,10 @@ namespace ptd {
 hipError_t launch_dense_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out,
                             int path, hipStream_t st);
 
+// One pass of the two-pass dense schedule (1 = tile, 2 = row, 3 = both); timing hook.
+hipError_t launch_dense_fwd_stage(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out, int stage,
+                                  hipStream_t st);
+
 // Dense reconstruct: A = scale_log2 ... A = 2^-adj_n * sum_P c_P P.
 hipError_t launch_dense_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const void* coeff, void* A,
                             int64_t lda, int path, hipStream_t st);

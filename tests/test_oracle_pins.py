@@ -202,6 +202,14 @@ def test_sampled_mode(oracle_mod):
     np.testing.assert_array_equal(got2, full[xs[perm], zs[perm]])
 
 
+def test_row_mode(oracle_mod):
+    n = 5
+    A = synth.dense(n, seed=9)
+    full = oracle_mod.decompose(A)
+    xs = np.array([3, 0, 31, 3], dtype=np.uint32)
+    np.testing.assert_array_equal(oracle_mod.rows(A, xs), full[xs])
+
+
 # -- Sec. IV-A structured supports ------------------------------------------
 
 def test_diagonal_is_walsh_hadamard(oracle_mod):
