@@ -38,6 +38,8 @@ SIGNATURES = {
     "ptd_debug_decompose_path": (I, [I, I, U, P, I64, P, I, P]),
     "ptd_debug_reconstruct_path": (I, [I, I, U, P, P, I64, I, P]),
     "ptd_debug_decompose_stage": (I, [I, I, U, P, I64, P, I, P]),
+    "ptd_debug_decompose_fused": (I, [I, I, U, P, I64, P, P, SZ, I, I, P]),
+    "ptd_debug_copy": (I, [P, P, SZ, P]),
 }
 
 

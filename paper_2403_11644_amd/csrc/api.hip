@@ -33,6 +33,20 @@ ptd_status check_structure(int n, unsigned flags, int s)
     return PTD_OK;
 }
 
+// Dense decompositions of n = 11..15 run as one persistent launch (fused.hip)
+// except at n = 15 for complex128 or Hermitian input (the 32-point row
+// transform is built for complex64 values only); those and n = 16 use the
+// two-pass schedule.
+bool use_fused(int n, ptd_dtype dt, unsigned flags)
+{
+    if (flags & (PTD_DIAGONAL | PTD_BANDED | PTD_COMPENSATED)) return false;
+    if (n < 11 || n > 15) return false;
+    if (n == 15 && (dt == PTD_C128 || (flags & PTD_HERMITIAN))) return false;
+    return true;
+}
+
+constexpr int kFusedLookahead = 3;
+
 }  // namespace
 
 extern "C" {
@@ -56,10 +70,10 @@ const char* ptd_build_arch(void) { return "gfx950"; }
 
 size_t ptd_workspace_bytes(int n, ptd_dtype dtype, unsigned flags, int s)
 {
-    (void)n;
-    (void)dtype;
-    (void)flags;
     (void)s;
+    if (n < 1 || n > 16 || !valid_dtype(dtype)) return 0;
+    if (flags & (PTD_DIAGONAL | PTD_BANDED | PTD_ADJOINT)) return 0;
+    if (use_fused(n, dtype, flags)) return ptd::fused_workspace_bytes(n, dtype);
     return 0;
 }
 
@@ -113,6 +127,10 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
     hipStream_t st = (hipStream_t)stream;
     const bool herm = flags & PTD_HERMITIAN;
     if (flags & (PTD_DIAGONAL | PTD_BANDED | PTD_COMPENSATED)) return PTD_EUNSUP;
+    if (use_fused(n, dtype, flags)) {
+        if (!ws) return PTD_ENOSPC;
+        return hip_status(ptd::launch_fused_fwd(n, dtype, herm, A, lda, coeff, ws, kFusedLookahead, 0, st));
+    }
     return hip_status(ptd::launch_dense_fwd(n, dtype, herm, A, lda, coeff, 0, st));
 }
 
@@ -167,12 +185,33 @@ ptd_status ptd_debug_reconstruct_path(int n, ptd_dtype dtype, unsigned flags, co
                                             path, (hipStream_t)stream));
 }
 
+// Testing hook: the single-launch schedule with an explicit lookahead.
+ptd_status ptd_debug_decompose_fused(int n, ptd_dtype dtype, unsigned flags, const void* A, int64_t lda, void* coeff,
+                                     void* ws, size_t ws_bytes, int lookahead, int cfg, ptd_stream stream)
+{
+    if (n < 11 || n > 15 || !valid_dtype(dtype) || !A || !coeff || lda < ((int64_t)1 << n)) return PTD_EINVAL;
+    if ((flags & ~PTD_HERMITIAN) || lookahead < 1) return PTD_EINVAL;
+    if (!use_fused(n, dtype, flags)) return PTD_EUNSUP;
+    if (!ws || ws_bytes < ptd::fused_workspace_bytes(n, dtype)) return PTD_ENOSPC;
+    if (cfg < 0 || cfg > 31) return PTD_EINVAL;
+    return hip_status(ptd::launch_fused_fwd(n, dtype, flags & PTD_HERMITIAN, A, lda, coeff, ws, lookahead, cfg,
+                                            (hipStream_t)stream));
+}
+
+// Bandwidth reference: a plain 16-byte-per-lane device copy of `bytes` bytes.
+ptd_status ptd_debug_copy(const void* src, void* dst, size_t bytes, ptd_stream stream)
+{
+    if (!src || !dst || (bytes & 15)) return PTD_EINVAL;
+    return hip_status(ptd::launch_copy(src, dst, bytes, (hipStream_t)stream));
+}
+
 // Timing hook: launch one pass of the two-pass dense schedule (n >= 7).
 ptd_status ptd_debug_decompose_stage(int n, ptd_dtype dtype, unsigned flags, const void* A, int64_t lda,
                                      void* coeff, int stage, ptd_stream stream)
 {
     if (n < 7 || n > 16 || !valid_dtype(dtype) || !A || !coeff || lda < ((int64_t)1 << n)) return PTD_EINVAL;
-    if ((flags & ~PTD_HERMITIAN) || stage < 1 || stage > 3) return PTD_EINVAL;
+    // stage bits 0..1: passes; bits 2..: chunk size in X-pattern groups (0 = whole)
+    if ((flags & ~PTD_HERMITIAN) || (stage & 3) == 0 || (stage >> 2) > (1 << (n - 6))) return PTD_EINVAL;
     return hip_status(ptd::launch_dense_fwd_stage(n, dtype, flags & PTD_HERMITIAN, A, lda, coeff, stage,
                                                   (hipStream_t)stream));
 }

@@ -166,12 +166,17 @@ __global__ __launch_bounds__(GROUP_THREADS) void k_group_rec(const void* __restr
 // ------------------------------------------------------------------------
 // two passes, pass 1: 64 x 64 tiles, low six WHT bits
 
+// grid (nb, nb): tile (R, C) = (blockIdx.y, blockIdx.x).  With xh_count > 0
+// the grid is (nb, xh_count) instead and covers the tiles of the X-pattern
+// groups x_hi = xh0 + blockIdx.y only (R = blockIdx.x, C = R ^ x_hi).
 template <class V, bool HERM>
 __global__ __launch_bounds__(TILE_THREADS) void k_tile_fwd(const cplx<V>* __restrict__ A, int64_t lda,
-                                                           void* __restrict__ out, int64_t ldo)
+                                                           void* __restrict__ out, int64_t ldo, int xh0,
+                                                           int xh_count)
 {
     __shared__ cplx<V> lds[64 * 65];
-    const int R = blockIdx.y, C = blockIdx.x;
+    const int R = xh_count ? (int)blockIdx.x : (int)blockIdx.y;
+    const int C = xh_count ? (R ^ (xh0 + (int)blockIdx.y)) : (int)blockIdx.x;
     const int xh = R ^ C;
     const cplx<V>* tile = A + (int64_t)R * 64 * lda + (int64_t)C * 64;
     auto gather = [&](int vec, int pos, V& re, V& im) {
@@ -208,13 +213,13 @@ __global__ __launch_bounds__(TILE_THREADS) void k_tile_fwd(const cplx<V>* __rest
 // pass 2: WHT over the block index (stride 64) of each output row chunk,
 // then the phase and the scale.
 template <class V, int LOGM, bool HERM>
-__global__ __launch_bounds__(HIGH_THREADS) void k_high_fwd(void* __restrict__ out, int64_t ldo)
+__global__ __launch_bounds__(HIGH_THREADS) void k_high_fwd(void* __restrict__ out, int64_t ldo, int x0)
 {
     constexpr int LOGW = high_logw<V>();
     constexpr int CH = 6 - LOGW;
     constexpr int NT = HIGH_THREADS;
     __shared__ cplx<V> lds[(1 << LOGW) * ((1 << LOGM) + 1)];
-    const int x = blockIdx.x >> CH;
+    const int x = x0 + (int)(blockIdx.x >> CH);
     const int z0 = (blockIdx.x & ((1 << CH) - 1)) << LOGW;
     const int xh = x >> 6, xl = x & 63;
     V* rowr = (V*)out + (int64_t)x * ldo;
@@ -379,22 +384,37 @@ hipError_t fwd_two_pass(int n, const void* A, int64_t lda, void* out, hipStream_
     const cplx<V>* a = (const cplx<V>*)A;
     const int64_t ldo = (int64_t)1 << n;
     const int nb = 1 << (n - 6);
-    if (stage & 1) {
-        hipLaunchKernelGGL((k_tile_fwd<V, HERM>), dim3(nb, nb), dim3(TILE_THREADS), 0, st, a, lda, out, ldo);
+    // chunk > 0: alternate the passes over chunks of `chunk` X-pattern groups
+    const int chunk = stage >> 2;
+    const int nchunks = chunk ? (nb + chunk - 1) / chunk : 1;
+    for (int c = 0; c < nchunks; ++c) {
+        const int xh0 = chunk ? c * chunk : 0;
+        const int cnt = chunk ? (nb - xh0 < chunk ? nb - xh0 : chunk) : nb;
+        if (stage & 1) {
+            if (chunk)
+                hipLaunchKernelGGL((k_tile_fwd<V, HERM>), dim3(nb, cnt), dim3(TILE_THREADS), 0, st, a, lda, out, ldo,
+                                   xh0, cnt);
+            else
+                hipLaunchKernelGGL((k_tile_fwd<V, HERM>), dim3(nb, nb), dim3(TILE_THREADS), 0, st, a, lda, out, ldo,
+                                   0, 0);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (!(stage & 2)) continue;
+        const dim3 g2((unsigned)(((int64_t)cnt * 64) << (6 - high_logw<V>())));
+        const int x0 = xh0 * 64;
+        switch (n - 6) {
+#define PTD_CASE(MM) \
+    case MM: hipLaunchKernelGGL((k_high_fwd<V, MM, HERM>), g2, dim3(HIGH_THREADS), 0, st, out, ldo, x0); break;
+            PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5)
+            PTD_CASE(6) PTD_CASE(7) PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
+#undef PTD_CASE
+            default: return hipErrorInvalidValue;
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (!(stage & 2)) return hipSuccess;
-    const dim3 g2((unsigned)(((int64_t)1 << n) << (6 - high_logw<V>())));
-    switch (n - 6) {
-#define PTD_CASE(MM) \
-    case MM: hipLaunchKernelGGL((k_high_fwd<V, MM, HERM>), g2, dim3(HIGH_THREADS), 0, st, out, ldo); break;
-        PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5)
-        PTD_CASE(6) PTD_CASE(7) PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
-#undef PTD_CASE
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 template <class V, bool HERM>
@@ -454,7 +474,7 @@ hipError_t launch_dense_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64
 hipError_t launch_dense_fwd_stage(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out, int stage,
                                   hipStream_t st)
 {
-    if (n < 7 || stage < 1 || stage > 3) return hipErrorInvalidValue;
+    if (n < 7 || stage < 1 || (stage & 3) == 0) return hipErrorInvalidValue;
     if (dt == PTD_C128)
         return herm ? fwd_two_pass<double, true>(n, A, lda, out, st, stage)
                     : fwd_two_pass<double, false>(n, A, lda, out, st, stage);

@@ -22,6 +22,15 @@ hipError_t launch_dense_fwd_stage(int n, ptd_dtype dt, bool herm, const void* A,
 hipError_t launch_dense_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const void* coeff, void* A,
                             int64_t lda, int path, hipStream_t st);
 
+// Single-launch dense decompose for n = 11..15 (fused.hip); ws holds
+// fused_workspace_bytes() bytes of queue and group counters; la = lookahead.
+size_t fused_workspace_bytes(int n, ptd_dtype dt);
+// cfg 0 = default shape; see fused.hip for the others.
+hipError_t launch_fused_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out, void* ws, int la,
+                            int cfg, hipStream_t st);
+// Plain 16-byte-per-lane device copy (bandwidth reference).
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
+
 // Parseval residual: out_host[0] = ||A||_F^2, [1] = 2^n sum|c|^2, [2] = relative gap.
 size_t reduce_workspace_bytes();
 hipError_t launch_parseval(int n, ptd_dtype dt, bool real_coeff, const void* A, int64_t lda, const void* coeff,

@@ -39,10 +39,18 @@ def test_status_strings(lib):
     assert lib.ptd_build_arch() == b"gfx950"
 
 
-def test_workspace_is_zero(lib):
-    for n in (1, 8, 14, 16):
+def test_workspace_sizes(lib):
+    # single-pass and two-pass schedules need none; the single-launch schedule
+    # (n = 11..15) needs its queue and group counters
+    for n in (1, 8, 10, 16):
         for dt in (0, 1):
             assert lib.ptd_workspace_bytes(n, dt, 0, 0) == 0
+    # queue words + one counter per group of the narrowest group width
+    assert lib.ptd_workspace_bytes(14, 0, 0, 0) == 4 * (32 + (1 << 12))
+    assert lib.ptd_workspace_bytes(14, 1, 0, 0) == 4 * (32 + (1 << 11))
+    assert lib.ptd_workspace_bytes(15, 0, 0, 0) == 0
+    assert lib.ptd_workspace_bytes(14, 0, 1 << 1, 0) == 0  # structured
+    assert lib.ptd_workspace_bytes(13, 0, 1, 0) > 0  # Hermitian
 
 
 def test_nonempty_counts_match_bruteforce(lib, oracle_mod):
@@ -81,6 +89,8 @@ def test_decompose_argument_errors(lib):
     assert _dec(lib, flags=(1 << 6)) == EINVAL  # adjoint is a reconstruct flag
     assert _dec(lib, flags=(1 << 5), dt=0) == EUNSUP  # compensated is complex64 only
     assert _dec(lib, A=5, C=5) == EINVAL  # in place is not allowed
+    ENOSPC = -2
+    assert _dec(lib, n=12, lda=4096, ws=0, wsb=0) == ENOSPC  # single-launch schedule needs counters
 
 
 def test_reconstruct_argument_errors(lib):

@@ -204,3 +204,93 @@ def test_large_sampled(ptd, oracle_mod, dt, n):
     _, _, res = ptd.parseval(Ad, c)
     assert res <= (1e-12 if dt == "c128" else 1e-5)
     del c, Ad
+
+
+# --------------------------------------------------------------------------
+# the single-launch schedule (n = 11..15): parity, error flag, lookahead
+
+def _fused(A, hermitian=False, lookahead=1, cfg=0):
+    import torch
+
+    from paper_2403_11644_amd import _native, api
+
+    code = api._dtype_code(A.dtype)
+    n = A.shape[0].bit_length() - 1
+    odt = api._real_dtype(code) if hermitian else api._complex_dtype(code)
+    out = torch.empty(A.shape, dtype=odt, device=A.device)
+    L = _native.lib()
+    wsb = L.ptd_workspace_bytes(n, code, api.HERMITIAN if hermitian else 0, 0)
+    assert wsb > 0
+    ws = torch.zeros(wsb, dtype=torch.uint8, device=A.device)
+    st = L.ptd_debug_decompose_fused(n, code, api.HERMITIAN if hermitian else 0, api._ptr(A), A.stride(0),
+                                     api._ptr(out), api._ptr(ws), wsb, lookahead, cfg,
+                                     api._stream_handle(A.device, None))
+    _native.check(st, "fused")
+    torch.cuda.synchronize()
+    words = ws.view(torch.int32).cpu().numpy()
+    assert words[17] == 0, "a bounded wait ran out"
+    return out
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n,la,cfg", [(11, 1, 0), (11, 3, 1), (11, 2, 3), (12, 2, 7), (12, 4, 14), (13, 1, 1),
+                                      (13, 4, 0), (13, 2, 3)])
+def test_fused_vs_oracle(ptd, oracle_mod, dt, n, la, cfg):
+    A = synth.dense(n, seed=500 + n, dtype=_np_dtype(dt))
+    got = to_host(_fused(to_dev(A), lookahead=la, cfg=cfg))
+    if n <= 11:
+        want = oracle_mod.decompose(A.astype(np.complex128))
+        assert rel_err(got, want) <= TOL[dt]
+    else:
+        xs, zs = synth.sample_strings(n, 3000, seed=n)
+        want = oracle_mod.coeffs(A, xs, zs)
+        assert rel_err(got[xs, zs], want) <= TOL[dt]
+    # the public entry point takes the same butterfly network: bit-identical
+    np.testing.assert_array_equal(to_host(ptd.decompose(to_dev(A))), got)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n", [11, 12, 13])
+def test_fused_integer_exact(ptd, oracle_mod, dt, n):
+    from paper_2403_11644_amd import api
+
+    re, im = synth.gaussian_int(n, seed=600 + n)
+    A = to_dev(synth.int_to_complex(re, im, _np_dtype(dt)))
+    got = to_host(_fused(A))
+    # equal to the two-pass schedule bit for bit (both exact)
+    two = to_host(api._debug_decompose_path(A, 2))
+    np.testing.assert_array_equal(got, two)
+    if n == 11:
+        cre, cim = oracle_mod.decompose_int(re, im)
+        np.testing.assert_array_equal((got.real * (1 << n)).astype(np.int64), cre)
+        np.testing.assert_array_equal((got.imag * (1 << n)).astype(np.int64), cim)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n,cfg", [(11, 0), (11, 3), (13, 0), (13, 1), (14, 0), (14, 7)])
+def test_fused_hermitian(ptd, oracle_mod, dt, n, cfg):
+    re, im = synth.gaussian_int_hermitian(n, seed=1)
+    A = to_dev(synth.int_to_complex(re, im, _np_dtype(dt)))
+    full = to_host(_fused(A, cfg=cfg))
+    assert np.all(full.imag == 0.0)
+    real = to_host(_fused(A, hermitian=True, cfg=cfg))
+    np.testing.assert_array_equal(real, full.real)
+    if n == 11:
+        cre, _ = oracle_mod.decompose_int(re, im)
+        np.testing.assert_array_equal((real * (1 << n)).astype(np.int64), cre)
+    else:
+        A_h = synth.int_to_complex(re, im)
+        xs, zs = synth.sample_strings(n, 2000, seed=3)
+        want = oracle_mod.coeffs(A_h, xs, zs)
+        np.testing.assert_array_equal(real[xs, zs], want.real)
+
+
+def test_fused_n15_c64(ptd, oracle_mod):
+    n = 15
+    A = synth.dense(n, seed=0, dtype=np.complex64)
+    Ad = to_dev(A)
+    got = _fused(Ad)
+    xs, zs = synth.sample_strings(n, 3000, seed=2)
+    want = oracle_mod.coeffs(A, xs, zs)
+    g = to_host(got[to_dev(xs.astype(np.int64)), to_dev(zs.astype(np.int64))])
+    assert rel_err(g, want) <= 1e-5
