@@ -126,7 +126,15 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
     if (A == coeff) return PTD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     const bool herm = flags & PTD_HERMITIAN;
-    if (flags & (PTD_DIAGONAL | PTD_BANDED | PTD_COMPENSATED)) return PTD_EUNSUP;
+    if (flags & (PTD_DIAGONAL | PTD_BANDED)) {
+        if (flags & PTD_COMPENSATED) return PTD_EUNSUP;
+        const int se = (flags & PTD_DIAGONAL) ? 0 : s;
+        const int count = ptd_num_nonempty_x(n, flags, s);
+        if (count < 1) return PTD_EINVAL;
+        return hip_status(ptd::launch_structured(n, dtype, herm, flags & PTD_BANDS_IN, flags & PTD_COMPACT, se, count,
+                                                 A, lda, coeff, st));
+    }
+    if (flags & PTD_COMPENSATED) return PTD_EUNSUP;
     if (use_fused(n, dtype, flags)) {
         if (!ws) return PTD_ENOSPC;
         return hip_status(ptd::launch_fused_fwd(n, dtype, herm, A, lda, coeff, ws, kFusedLookahead, 0, st));

@@ -22,6 +22,10 @@ hipError_t launch_dense_fwd_stage(int n, ptd_dtype dt, bool herm, const void* A,
 hipError_t launch_dense_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const void* coeff, void* A,
                             int64_t lda, int path, hipStream_t st);
 
+// Diagonal (s = 0) and banded decompose over the `count` nonempty X-patterns.
+hipError_t launch_structured(int n, ptd_dtype dt, bool herm, bool bands, bool compact, int s, int count,
+                             const void* A, int64_t lda, void* out, hipStream_t st);
+
 // Single-launch dense decompose for n = 11..15 (fused.hip); ws holds
 // fused_workspace_bytes() bytes of queue and group counters; la = lookahead.
 size_t fused_workspace_bytes(int n, ptd_dtype dt);

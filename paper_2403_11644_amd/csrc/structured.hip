@@ -1,0 +1,300 @@
+// structured.hip -- diagonal and banded inputs: only nonempty X-patterns.
+//
+// For a band matrix with half-bandwidth s (a[r][c] = 0 when |r - c| > s;
+// s = 0 diagonal, s = 1 tridiagonal; paper Sec. IV-A) the strings with
+// X-pattern x read only the entries (k, k ^ x), so x can carry nonzero
+// coefficients only if some entry (k, k ^ x) lies in the band:
+// x = 0, or x = 2^h + y with 0 <= y < 2^h and 2^h - y <= s (the smallest
+// |(k ^ x) - k| over k is 2^h - y).  There are 1 + sum_{h<n} min(s, 2^h)
+// such x, the paper's (s n - c(s)) per 2^n terms, listed in ascending order
+// as: 0, then for h = 0, 1, ... the interval [2^(h+1) - min(s, 2^h), 2^(h+1)).
+//
+// Each listed x gets d_x[k] = A[k][k ^ x] for in-band entries and 0 outside
+// the band, read either from the dense matrix (touching only in-band
+// entries) or from the row-indexed bands band[d + s][k] = A[k][k + d], then
+// one length-2^n WHT and the fused phase/scale.  n <= 10: one pass, several
+// X-patterns per workgroup in LDS.  n >= 11: a 1024-position pass and a
+// strided pass over the remaining bits, in place in the output rows.
+#include "engine.hpp"
+#include "internal.hpp"
+
+namespace ptd {
+
+namespace {
+
+constexpr int SM_THREADS = 256;
+constexpr int SM_VECS = 4;  // X-patterns per workgroup for n <= 10
+constexpr int SP_KAP = 10;  // positions per first-pass item for n >= 11
+
+// i-th nonempty X-pattern (ascending); s = 0 means diagonal.
+__device__ __forceinline__ uint32_t listed_x(int i, int n, int s)
+{
+    if (i == 0) return 0u;
+    int r = i - 1;
+    for (int h = 0; h < n; ++h) {
+        const int cnt = s < (1 << h) ? s : (1 << h);
+        if (r < cnt) return (uint32_t)((2 << h) - cnt + r);
+        r -= cnt;
+    }
+    return 0u;  // unreachable for i < count
+}
+
+__device__ __forceinline__ bool is_listed(uint32_t x, int s)
+{
+    if (x == 0u) return true;
+    const int h = 31 - __clz(x);
+    const int y = (int)x - (1 << h);
+    return (1 << h) - y <= s;
+}
+
+// d_x[k] from the dense matrix or from the row-indexed bands; 0 off band.
+template <class V, bool BANDS>
+__device__ __forceinline__ void band_entry(const cplx<V>* __restrict__ A, int64_t lda, int s, int k, uint32_t x,
+                                           V& re, V& im)
+{
+    const int c = k ^ (int)x;
+    const int d = c - k;
+    if (d > s || d < -s) {
+        re = (V)0;
+        im = (V)0;
+        return;
+    }
+    const cplx<V> v = BANDS ? A[(int64_t)(d + s) * lda + k] : A[(int64_t)k * lda + c];
+    re = v.re;
+    im = v.im;
+}
+
+template <class V, bool HERM>
+__device__ __forceinline__ void put_final(void* __restrict__ out, int64_t o, V re, V im)
+{
+    if constexpr (HERM) {
+        ((V*)out)[o] = re;
+    } else {
+        cplx<V> c;
+        c.re = re;
+        c.im = im;
+        ((cplx<V>*)out)[o] = c;
+    }
+}
+
+// ---------------------------------------------------------------- n <= 10
+
+template <class V, int LOGN, bool BANDS, bool HERM>
+__global__ __launch_bounds__(SM_THREADS) void k_struct_small(const cplx<V>* __restrict__ A, int64_t lda, int s,
+                                                             int count, int compact, void* __restrict__ out)
+{
+    constexpr int N = 1 << LOGN;
+    constexpr int LV = 2;  // log2(SM_VECS)
+    __shared__ cplx<V> lds[SM_VECS * (N + 1)];
+    const int i0 = blockIdx.x * SM_VECS;
+    const V scale = exp2_neg<V>(LOGN);
+    auto gather = [&](int vec, int pos, V& re, V& im) {
+        const int i = i0 + vec;
+        if (i >= count) {
+            re = (V)0;
+            im = (V)0;
+            return;
+        }
+        band_entry<V, BANDS>(A, lda, s, pos, listed_x(i, LOGN, s), re, im);
+    };
+    auto store = [&](int vec, int pos, V re, V im) {
+        const int i = i0 + vec;
+        if (i >= count) return;
+        const uint32_t x = listed_x(i, LOGN, s);
+        mul_ipow(__popc(x & (uint32_t)pos) & 3, re, im);
+        const int64_t row = compact ? i : (int64_t)x;
+        put_final<V, HERM>(out, row * N + pos, re * scale, im * scale);
+    };
+    LdsVecs<V, LOGN> lr{lds};
+    LdsVecsW<V, LOGN> lw{lds};
+    if constexpr (LOGN <= 4) {
+        wht_round<V, LV, LOGN, 0, LOGN, SM_THREADS, true>(gather, store);
+    } else if constexpr (LOGN <= 8) {
+        wht_round<V, LV, LOGN, 0, 4, SM_THREADS, false>(gather, lw);
+        __syncthreads();
+        wht_round<V, LV, LOGN, 4, LOGN - 4, SM_THREADS, false>(lr, store);
+    } else {
+        wht_round<V, LV, LOGN, 0, 4, SM_THREADS, false>(gather, lw);
+        __syncthreads();
+        wht_round<V, LV, LOGN, 4, 4, SM_THREADS, false>(lr, lw);
+        __syncthreads();
+        wht_round<V, LV, LOGN, 8, LOGN - 8, SM_THREADS, false>(lr, store);
+    }
+}
+
+// ---------------------------------------------------------------- n >= 11
+// pass 1, item (i, b): positions [b*1024, (b+1)*1024) of d_x, low ten bits.
+// Hermitian real output stores one real per slot: blocks b and b ^ (x >> 10)
+// of one row are conjugate-symmetric partners (see dense.hip).
+template <class V, bool BANDS, bool HERM>
+__global__ __launch_bounds__(SM_THREADS) void k_struct_p1(const cplx<V>* __restrict__ A, int64_t lda, int s, int n,
+                                                          int compact, void* __restrict__ out)
+{
+    __shared__ cplx<V> lds[(1 << SP_KAP) + 1];
+    const int i = blockIdx.x;
+    const int b = blockIdx.y;
+    const uint32_t x = listed_x(i, n, s);
+    const int k0 = b << SP_KAP;
+    const int64_t N = (int64_t)1 << n;
+    const int64_t row = compact ? i : (int64_t)x;
+    const int bp = b ^ (int)(x >> SP_KAP);
+    auto gather = [&](int, int pos, V& re, V& im) { band_entry<V, BANDS>(A, lda, s, k0 + pos, x, re, im); };
+    auto store = [&](int, int pos, V re, V im) {
+        const int64_t o = row * N + k0 + pos;
+        if constexpr (HERM) {
+            const bool sneg = __popc((uint32_t)pos & (x & ((1u << SP_KAP) - 1))) & 1;
+            V val;
+            if (b < bp)
+                val = re;
+            else if (b > bp)
+                val = sneg ? im : -im;
+            else
+                val = sneg ? im : re;
+            ((V*)out)[o] = val;
+        } else {
+            cplx<V> c;
+            c.re = re;
+            c.im = im;
+            ((cplx<V>*)out)[o] = c;
+        }
+    };
+    LdsVecs<V, SP_KAP> lr{lds};
+    LdsVecsW<V, SP_KAP> lw{lds};
+    wht_round<V, 0, SP_KAP, 0, 4, SM_THREADS, false>(gather, lw);
+    __syncthreads();
+    wht_round<V, 0, SP_KAP, 4, 4, SM_THREADS, false>(lr, lw);
+    __syncthreads();
+    wht_round<V, 0, SP_KAP, 8, 2, SM_THREADS, false>(lr, store);
+}
+
+// pass 2, item (i, chunk of 16 positions z_lo): WHT over the 2^(n-10)
+// positions z_lo + 1024 j, then phase and scale.
+template <class V, int LOGM, bool HERM>
+__global__ __launch_bounds__(SM_THREADS) void k_struct_p2(int s, int n, int compact, void* __restrict__ out)
+{
+    constexpr int LOGW = 4;
+    constexpr int NT = SM_THREADS;
+    __shared__ cplx<V> lds[(1 << LOGW) * ((1 << LOGM) + 1)];
+    const int i = blockIdx.x;
+    const int z0 = blockIdx.y << LOGW;
+    const uint32_t x = listed_x(i, n, s);
+    const int64_t N = (int64_t)1 << n;
+    const int64_t row = compact ? i : (int64_t)x;
+    const int xh = (int)(x >> SP_KAP);
+    const uint32_t xl = x & ((1u << SP_KAP) - 1);
+    V* rowr = (V*)out + row * N;
+    cplx<V>* rowc = (cplx<V>*)out + row * N;
+    const V scale = exp2_neg<V>(n);
+    auto load = [&](int vec, int pos, V& re, V& im) {
+        const int zl = z0 + vec;
+        if constexpr (HERM) {
+            const int pp = pos ^ xh;
+            const V a = rowr[((int64_t)pos << SP_KAP) + zl];
+            const bool sneg = __popc((uint32_t)zl & xl) & 1;
+            if (pos < pp) {
+                re = a;
+                im = rowr[((int64_t)pp << SP_KAP) + zl];
+            } else if (pos > pp) {
+                const V bq = rowr[((int64_t)pp << SP_KAP) + zl];
+                re = sneg ? -bq : bq;
+                im = sneg ? a : -a;
+            } else {
+                re = sneg ? (V)0 : a;
+                im = sneg ? a : (V)0;
+            }
+        } else {
+            const cplx<V> v = rowc[((int64_t)pos << SP_KAP) + zl];
+            re = v.re;
+            im = v.im;
+        }
+    };
+    auto store = [&](int vec, int pos, V re, V im) {
+        const uint32_t z = ((uint32_t)pos << SP_KAP) | (uint32_t)(z0 + vec);
+        mul_ipow(__popc(x & z) & 3, re, im);
+        put_final<V, HERM>(out, row * N + z, re * scale, im * scale);
+    };
+    LdsVecs<V, LOGM> lr{lds};
+    LdsVecsW<V, LOGM> lw{lds};
+    if constexpr (LOGM <= 4) {
+        wht_round<V, LOGW, LOGM, 0, LOGM, NT, true>(load, store);
+    } else {
+        static_assert(LOGM <= 6, "n <= 16");
+        wht_round<V, LOGW, LOGM, 0, 4, NT, true>(load, lw);
+        __syncthreads();
+        wht_round<V, LOGW, LOGM, 4, LOGM - 4, NT, true>(lr, store);
+    }
+}
+
+// zero rows of the dense output whose X-pattern is not listed
+template <class V, bool HERM>
+__global__ void k_zero_unlisted(void* __restrict__ out, int n, int s)
+{
+    const int64_t N = (int64_t)1 << n;
+    const int64_t total = N * N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t x = (uint32_t)(e >> n);
+        if (!is_listed(x, s)) put_final<V, HERM>(out, e, (V)0, (V)0);
+    }
+}
+
+template <class V, bool BANDS, bool HERM>
+hipError_t struct_launch(int n, int s, int count, bool compact, const void* A, int64_t lda, void* out, hipStream_t st)
+{
+    const cplx<V>* a = (const cplx<V>*)A;
+    if (!compact) {
+        hipLaunchKernelGGL((k_zero_unlisted<V, HERM>), dim3(2048), dim3(256), 0, st, out, n, s);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int cp = compact ? 1 : 0;
+    if (n <= 10) {
+        const dim3 grid((count + SM_VECS - 1) / SM_VECS);
+        switch (n) {
+#define PTD_CASE(NN)                                                                                        \
+    case NN:                                                                                                \
+        hipLaunchKernelGGL((k_struct_small<V, NN, BANDS, HERM>), grid, dim3(SM_THREADS), 0, st, a, lda, s, \
+                           count, cp, out);                                                                 \
+        break;
+            PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5)
+            PTD_CASE(6) PTD_CASE(7) PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
+#undef PTD_CASE
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_struct_p1<V, BANDS, HERM>), dim3(count, 1u << (n - SP_KAP)), dim3(SM_THREADS), 0, st, a,
+                       lda, s, n, cp, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 g2(count, 1u << (SP_KAP - 4));
+    switch (n - SP_KAP) {
+#define PTD_CASE(MM) \
+    case MM: hipLaunchKernelGGL((k_struct_p2<V, MM, HERM>), g2, dim3(SM_THREADS), 0, st, s, n, cp, out); break;
+        PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5) PTD_CASE(6)
+#undef PTD_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_structured(int n, ptd_dtype dt, bool herm, bool bands, bool compact, int s, int count,
+                             const void* A, int64_t lda, void* out, hipStream_t st)
+{
+    if (dt == PTD_C128) {
+        if (bands)
+            return herm ? struct_launch<double, true, true>(n, s, count, compact, A, lda, out, st)
+                        : struct_launch<double, true, false>(n, s, count, compact, A, lda, out, st);
+        return herm ? struct_launch<double, false, true>(n, s, count, compact, A, lda, out, st)
+                    : struct_launch<double, false, false>(n, s, count, compact, A, lda, out, st);
+    }
+    if (bands)
+        return herm ? struct_launch<float, true, true>(n, s, count, compact, A, lda, out, st)
+                    : struct_launch<float, true, false>(n, s, count, compact, A, lda, out, st);
+    return herm ? struct_launch<float, false, true>(n, s, count, compact, A, lda, out, st)
+                : struct_launch<float, false, false>(n, s, count, compact, A, lda, out, st);
+}
+
+}  // namespace ptd

@@ -1,0 +1,121 @@
+"""GPU parity of the structured (diagonal / banded) paths against the oracle.
+
+Only the nonempty X-patterns are computed (paper Sec. IV-A); the oracle
+evaluates the same rows from the definition on the dense matrix, and the
+rows it proves empty must come out exactly zero.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.helpers import rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL = {np.complex128: 1e-12, np.complex64: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def ptd():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_11644_amd as p
+
+    return p
+
+
+def _cases():
+    # (name, n, s, builder) -> (bands array, dense matrix)
+    def diag(n):
+        d = synth.diagonal_real(n, seed=0)
+        return synth.bands_from_diag(d), 0
+
+    def tri(n):
+        a, b = synth.tridiag_real_sym(n, seed=1)
+        return synth.bands_from_tridiag(a, b), 1
+
+    def band8(n):
+        return synth.banded_complex(n, 8, seed=2), 8
+
+    return {"diagonal": diag, "tridiagonal": tri, "band8": band8}
+
+
+@pytest.mark.parametrize("dt", [np.complex128, np.complex64])
+@pytest.mark.parametrize("kind,n", [("diagonal", 3), ("diagonal", 10), ("diagonal", 12), ("tridiagonal", 5),
+                                    ("tridiagonal", 9), ("tridiagonal", 11), ("band8", 6), ("band8", 10),
+                                    ("band8", 12), ("band8", 14), ("diagonal", 14), ("tridiagonal", 14)])
+def test_structured_vs_oracle(ptd, oracle_mod, dt, kind, n):
+    band, s = _cases()[kind](n)
+    band = band.astype(dt)
+    A = synth.dense_from_bands(band)
+    structure = "diagonal" if s == 0 else "banded"
+    xs = ptd.nonempty_x(n, structure, s if s else 0)
+    Ad = to_dev(A)
+    bd = to_dev(band)
+    sv = None if s == 0 else s
+    comp_dense_in = to_host(ptd.decompose(Ad, structure=structure, s=sv, compact=True))
+    comp_bands_in = to_host(ptd.decompose(bd, structure=structure, s=sv, bands=True, compact=True))
+    np.testing.assert_array_equal(comp_dense_in, comp_bands_in)
+    assert comp_dense_in.shape == (len(xs), 1 << n)
+    want = oracle_mod.rows(A.astype(np.complex128), np.array(xs, dtype=np.uint32))
+    assert rel_err(comp_dense_in, want) <= TOL[dt]
+    full = to_host(ptd.decompose(bd, structure=structure, s=sv, bands=True))
+    np.testing.assert_array_equal(full[xs], comp_dense_in)
+    mask = np.ones(1 << n, dtype=bool)
+    mask[xs] = False
+    assert np.all(full[mask] == 0)
+    if n <= 12:
+        # the general dense path agrees on the listed rows
+        dense = to_host(ptd.decompose(Ad))
+        assert rel_err(dense[xs], comp_dense_in) <= TOL[dt]
+        assert np.max(np.abs(dense[mask])) == 0.0
+
+
+@pytest.mark.parametrize("n,s", [(6, 1), (8, 3), (11, 5), (12, 8)])
+def test_structured_integer_exact(ptd, oracle_mod, n, s):
+    rng = np.random.default_rng(n)
+    band = (rng.integers(-8, 9, size=(2 * s + 1, 1 << n)) + 1j * rng.integers(-8, 9, size=(2 * s + 1, 1 << n)))
+    k = np.arange(1 << n)
+    for d in range(-s, s + 1):
+        band[d + s][(k + d < 0) | (k + d >= (1 << n))] = 0
+    A = synth.dense_from_bands(band)
+    xs = ptd.nonempty_x(n, "banded", s)
+    got = to_host(ptd.decompose(to_dev(band), structure="banded", s=s, bands=True, compact=True)) * (1 << n)
+    if n <= 11:
+        cre, cim = oracle_mod.decompose_int(A.real.astype(np.int64), A.imag.astype(np.int64))
+        np.testing.assert_array_equal(got.real, cre[xs].astype(np.float64))
+        np.testing.assert_array_equal(got.imag, cim[xs].astype(np.float64))
+    else:
+        want = oracle_mod.rows(A, np.array(xs, dtype=np.uint32)) * (1 << n)
+        np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("dt", [np.complex128, np.complex64])
+@pytest.mark.parametrize("n", [7, 12, 14])
+def test_structured_hermitian(ptd, oracle_mod, dt, n):
+    # real symmetric tridiagonal is Hermitian: real coefficients
+    a, b = synth.tridiag_real_sym(n, seed=4)
+    band = synth.bands_from_tridiag(a, b).astype(dt)
+    bd = to_dev(band)
+    cplx = to_host(ptd.decompose(bd, structure="banded", s=1, bands=True, compact=True))
+    assert np.all(cplx.imag == 0.0)
+    real = to_host(ptd.decompose(bd, structure="banded", s=1, bands=True, compact=True, hermitian=True))
+    np.testing.assert_array_equal(real, cplx.real)
+    full = to_host(ptd.decompose(bd, structure="banded", s=1, bands=True, hermitian=True))
+    xs = ptd.nonempty_x(n, "banded", 1)
+    np.testing.assert_array_equal(full[xs], real)
+    assert full.dtype == (np.float64 if dt == np.complex128 else np.float32)
+
+
+def test_large_band_edge(ptd, oracle_mod):
+    # s close to 2^n: nearly every X-pattern is nonempty
+    n, s = 9, 500
+    band = synth.banded_complex(n, s, seed=3)
+    A = synth.dense_from_bands(band)
+    xs = ptd.nonempty_x(n, "banded", s)
+    assert xs == oracle_mod.nonempty_x_bruteforce(n, s)
+    got = to_host(ptd.decompose(to_dev(band), structure="banded", s=s, bands=True, compact=True))
+    want = oracle_mod.decompose(A)[xs]
+    assert rel_err(got, want) <= 1e-12
