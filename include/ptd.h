@@ -80,9 +80,12 @@ typedef void *ptd_stream;
 /* pauli_reconstruct only: multiply the result by 2^-n, which makes the call
  * the adjoint (vector-Jacobian product) of pauli_decompose. */
 #define PTD_ADJOINT (1u << 6)
+/* ptd_batch_plan_create only: the plan reconstructs (coefficients -> matrices). */
+#define PTD_PLAN_RECONSTRUCT (1u << 7)
 
-/* Workspace (device bytes) a call with these arguments needs; 0 for every
- * decompose/reconstruct variant of this build.  Host-only, pure. */
+/* Workspace (device bytes) a pauli_decompose / pauli_reconstruct call with
+ * these arguments needs: a few KiB of queue counters for dense decompositions
+ * with n = 11..15 (one persistent launch), 0 otherwise.  Host-only, pure. */
 size_t ptd_workspace_bytes(int n, ptd_dtype dtype, unsigned flags, int s);
 
 /* Number of X-patterns x that can carry a nonzero coefficient: 2^n for a
@@ -128,6 +131,44 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
  */
 ptd_status pauli_reconstruct(int n, ptd_dtype dtype, unsigned flags, const void *coeff, void *A,
                              int64_t lda, void *ws, size_t ws_bytes, ptd_stream stream);
+
+/*
+ * Batched decomposition: `count` matrices of uneven size in one persistent
+ * launch whose workgroups take (matrix, X-pattern group) items from an
+ * atomic queue, largest matrices first.  Every n_i must lie in 1..10 (one
+ * group of 2^n_i rows fits a workgroup's LDS).  Matrix i is dense with
+ * lda = 2^n_i at in_base + in_off_host[i] elements of dtype; its 4^n_i
+ * coefficients go to out_base + out_off_host[i] elements of the output type
+ * (complex of dtype, or real with PTD_HERMITIAN).  flags: PTD_HERMITIAN.
+ * The descriptors are uploaded into ws with a copy that synchronises
+ * `stream`; a batch plan (below) uploads them once instead.
+ */
+size_t ptd_batched_workspace_bytes(int count, ptd_dtype dtype, const int32_t *n_host);
+ptd_status pauli_decompose_batched(int count, ptd_dtype dtype, unsigned flags, const int32_t *n_host,
+                                   const int64_t *in_off_host, const int64_t *out_off_host, const void *in_base,
+                                   void *out_base, void *ws, size_t ws_bytes, ptd_stream stream);
+/* The batched reconstruction: coefficients at in_base + in_off_host[i]
+ * (complex, or real with PTD_HERMITIAN), matrices written to out_base +
+ * out_off_host[i].  flags: PTD_HERMITIAN | PTD_ADJOINT. */
+ptd_status pauli_reconstruct_batched(int count, ptd_dtype dtype, unsigned flags, const int32_t *n_host,
+                                     const int64_t *in_off_host, const int64_t *out_off_host, const void *in_base,
+                                     void *out_base, void *ws, size_t ws_bytes, ptd_stream stream);
+
+/*
+ * Batch plan: the descriptors of one batched call uploaded once into
+ * plan-owned device memory, and the launch (queue reset + persistent kernel)
+ * captured in a HIP graph.  ptd_batch_plan_launch replays the graph on
+ * `stream` (asynchronous).  Buffers and offsets are fixed at creation; the
+ * plan allocates device memory only in create and frees it in destroy.
+ * flags: PTD_HERMITIAN, PTD_ADJOINT, PTD_PLAN_RECONSTRUCT.  A plan must not
+ * be launched concurrently with itself.
+ */
+typedef struct ptd_plan ptd_plan;
+ptd_status ptd_batch_plan_create(int count, ptd_dtype dtype, unsigned flags, const int32_t *n_host,
+                                 const int64_t *in_off_host, const int64_t *out_off_host, const void *in_base,
+                                 void *out_base, ptd_plan **plan_out);
+ptd_status ptd_batch_plan_launch(ptd_plan *plan, ptd_stream stream);
+void ptd_batch_plan_destroy(ptd_plan *plan);
 
 /*
  * Parseval check (Theorem 1: the strings are orthogonal with Tr(P^* P) = 2^n,

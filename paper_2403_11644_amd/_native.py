@@ -31,6 +31,12 @@ SIGNATURES = {
     "pauli_reconstruct": (I, [I, I, U, P, P, I64, P, SZ, P]),
     "ptd_reduce_workspace_bytes": (SZ, []),
     "ptd_parseval_residual": (I, [I, I, U, P, I64, P, P, P, SZ, P]),
+    "ptd_batched_workspace_bytes": (SZ, [I, I, P]),
+    "pauli_decompose_batched": (I, [I, I, U, P, P, P, P, P, P, SZ, P]),
+    "pauli_reconstruct_batched": (I, [I, I, U, P, P, P, P, P, P, SZ, P]),
+    "ptd_batch_plan_create": (I, [I, I, U, P, P, P, P, P, P]),
+    "ptd_batch_plan_launch": (I, [P, P]),
+    "ptd_batch_plan_destroy": (None, [P]),
     "ptd_status_str": (ctypes.c_char_p, [I]),
     "ptd_last_hip_error": (I, []),
     "ptd_build_arch": (ctypes.c_char_p, []),

@@ -239,3 +239,105 @@ def _debug_reconstruct_path(c: torch.Tensor, path: int, hermitian: bool = False,
                                                   _stream_handle(c.device, None))
     _native.check(st, "ptd_debug_reconstruct_path")
     return out
+
+
+# --------------------------------------------------------------------------
+# batched (many matrices of uneven size, n <= 10 each)
+
+def _batch_layout(mats):
+    """(base pointer, element offsets, n list) for same-dtype square GPU tensors."""
+    import numpy as np
+
+    if not mats:
+        raise ValueError("empty batch")
+    dt = mats[0].dtype
+    esz = mats[0].element_size()
+    ptrs = []
+    ns = []
+    for m in mats:
+        _require_device(m, "batch matrix")
+        if m.dtype != dt:
+            raise TypeError("all batch matrices must share one dtype")
+        if m.dim() != 2 or m.shape[0] != m.shape[1] or not m.is_contiguous():
+            raise ValueError("batch matrices must be contiguous and square")
+        ns.append(_nqubits(m.shape[0]))
+        ptrs.append(m.data_ptr())
+    base = min(ptrs)
+    offs = np.array([(p - base) // esz for p in ptrs], dtype=np.int64)
+    if any((p - base) % esz for p in ptrs):
+        raise ValueError("batch matrices are not element-aligned relative to each other")
+    return base, offs, np.array(ns, dtype=np.int32)
+
+
+def _out_layout(ns, odt, device):
+    import numpy as np
+
+    sizes = np.array([1 << (2 * int(n)) for n in ns], dtype=np.int64)
+    offs = np.zeros(len(ns), dtype=np.int64)
+    offs[1:] = np.cumsum(sizes)[:-1]
+    buf = torch.empty(int(sizes.sum()), dtype=odt, device=device)
+    views = [buf[o:o + s].view(1 << int(n), 1 << int(n)) for o, s, n in zip(offs, sizes, ns)]
+    return buf, offs, views
+
+
+def decompose_batched(mats, *, hermitian: bool = False, stream=None):
+    """Decompose a list of square GPU matrices (n <= 10 each) in one launch.
+
+    Returns a list of coefficient tensors (views of one packed buffer)."""
+    import numpy as np
+
+    base, in_offs, ns = _batch_layout(mats)
+    code = _dtype_code(mats[0].dtype)
+    odt = _real_dtype(code) if hermitian else _complex_dtype(code)
+    obuf, out_offs, views = _out_layout(ns, odt, mats[0].device)
+    L = _native.lib()
+    nsp = ctypes.c_void_p(ns.ctypes.data)
+    wsb = L.ptd_batched_workspace_bytes(len(ns), code, nsp)
+    if wsb == 0:
+        raise ValueError("batched decomposition needs 1 <= n <= 10 for every matrix")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=mats[0].device)
+    st = L.pauli_decompose_batched(len(ns), code, HERMITIAN if hermitian else 0, nsp,
+                                   ctypes.c_void_p(in_offs.ctypes.data), ctypes.c_void_p(out_offs.ctypes.data),
+                                   ctypes.c_void_p(base), _ptr(obuf), _ptr(ws), wsb,
+                                   _stream_handle(mats[0].device, stream))
+    _native.check(st, "pauli_decompose_batched")
+    return views
+
+
+class BatchPlan:
+    """A captured batched launch over fixed buffers (ptd_batch_plan_*).
+
+    in_buf / out_buf are 1-D GPU tensors; ns, in_offsets, out_offsets are
+    per-matrix qubit counts and element offsets into them."""
+
+    def __init__(self, in_buf: torch.Tensor, ns, in_offsets, out_buf: torch.Tensor, out_offsets, *,
+                 dtype_code: int, hermitian: bool = False, reconstruct: bool = False, adjoint: bool = False):
+        import numpy as np
+
+        self._ns = np.ascontiguousarray(ns, dtype=np.int32)
+        self._io = np.ascontiguousarray(in_offsets, dtype=np.int64)
+        self._oo = np.ascontiguousarray(out_offsets, dtype=np.int64)
+        self._keep = (in_buf, out_buf)
+        flags = (HERMITIAN if hermitian else 0) | (ADJOINT if adjoint else 0) | ((1 << 7) if reconstruct else 0)
+        self._plan = ctypes.c_void_p()
+        st = _native.lib().ptd_batch_plan_create(len(self._ns), dtype_code, flags, ctypes.c_void_p(self._ns.ctypes.data),
+                                                 ctypes.c_void_p(self._io.ctypes.data),
+                                                 ctypes.c_void_p(self._oo.ctypes.data), _ptr(in_buf), _ptr(out_buf),
+                                                 ctypes.byref(self._plan))
+        _native.check(st, "ptd_batch_plan_create")
+        self.device = in_buf.device
+
+    def launch(self, stream=None) -> None:
+        _native.check(_native.lib().ptd_batch_plan_launch(self._plan, _stream_handle(self.device, stream)),
+                      "ptd_batch_plan_launch")
+
+    def close(self) -> None:
+        if self._plan:
+            _native.lib().ptd_batch_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

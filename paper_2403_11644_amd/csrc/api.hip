@@ -5,6 +5,9 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <new>
+#include <vector>
+
 #include "internal.hpp"
 
 namespace {
@@ -191,6 +194,132 @@ ptd_status ptd_debug_reconstruct_path(int n, ptd_dtype dtype, unsigned flags, co
     if (path < 0 || path > 2) return PTD_EINVAL;
     return hip_status(ptd::launch_dense_rec(n, dtype, flags & PTD_HERMITIAN, flags & PTD_ADJOINT, coeff, A, lda,
                                             path, (hipStream_t)stream));
+}
+
+// ------------------------------------------------------------------ batched
+
+namespace {
+
+ptd_status check_batch(int count, ptd_dtype dtype, const int32_t* n_host, const int64_t* in_off,
+                       const int64_t* out_off, const void* in_base, const void* out_base)
+{
+    if (count < 1 || !valid_dtype(dtype) || !n_host || !in_off || !out_off || !in_base || !out_base)
+        return PTD_EINVAL;
+    for (int i = 0; i < count; ++i) {
+        if (n_host[i] < 1 || n_host[i] > 10) return PTD_EINVAL;
+        if (in_off[i] < 0 || out_off[i] < 0) return PTD_EINVAL;
+    }
+    if (ptd::batched_item_count(count, dtype, n_host) > (int64_t)0x7fffffff) return PTD_EINVAL;
+    return PTD_OK;
+}
+
+ptd_status batched_common(bool rec, int count, ptd_dtype dtype, unsigned flags, const int32_t* n_host,
+                          const int64_t* in_off, const int64_t* out_off, const void* in_base, void* out_base,
+                          void* ws, size_t ws_bytes, ptd_stream stream)
+{
+    const ptd_status c = check_batch(count, dtype, n_host, in_off, out_off, in_base, out_base);
+    if (c != PTD_OK) return c;
+    const unsigned allowed = rec ? (PTD_HERMITIAN | PTD_ADJOINT) : PTD_HERMITIAN;
+    if (flags & ~allowed) return PTD_EINVAL;
+    if (!ws || ws_bytes < ptd::batched_buffer_bytes(count, dtype, n_host)) return PTD_ENOSPC;
+    std::vector<unsigned char> img;
+    int nitems = 0;
+    ptd::batched_fill(count, dtype, n_host, in_off, out_off, img, &nitems);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync((unsigned char*)ws + 256, img.data(), img.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // img is released on return
+    if (e != hipSuccess) return hip_status(e);
+    return hip_status(ptd::batched_launch(dtype, flags & PTD_HERMITIAN, rec, flags & PTD_ADJOINT, in_base, out_base,
+                                          ws, count, nitems, ptd::device_cu_count(), st));
+}
+
+}  // namespace
+
+struct ptd_plan {
+    void* buf = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+size_t ptd_batched_workspace_bytes(int count, ptd_dtype dtype, const int32_t* n_host)
+{
+    if (count < 1 || !valid_dtype(dtype) || !n_host) return 0;
+    for (int i = 0; i < count; ++i)
+        if (n_host[i] < 1 || n_host[i] > 10) return 0;
+    return ptd::batched_buffer_bytes(count, dtype, n_host);
+}
+
+ptd_status pauli_decompose_batched(int count, ptd_dtype dtype, unsigned flags, const int32_t* n_host,
+                                   const int64_t* in_off_host, const int64_t* out_off_host, const void* in_base,
+                                   void* out_base, void* ws, size_t ws_bytes, ptd_stream stream)
+{
+    return batched_common(false, count, dtype, flags, n_host, in_off_host, out_off_host, in_base, out_base, ws,
+                          ws_bytes, stream);
+}
+
+ptd_status pauli_reconstruct_batched(int count, ptd_dtype dtype, unsigned flags, const int32_t* n_host,
+                                     const int64_t* in_off_host, const int64_t* out_off_host, const void* in_base,
+                                     void* out_base, void* ws, size_t ws_bytes, ptd_stream stream)
+{
+    return batched_common(true, count, dtype, flags, n_host, in_off_host, out_off_host, in_base, out_base, ws,
+                          ws_bytes, stream);
+}
+
+ptd_status ptd_batch_plan_create(int count, ptd_dtype dtype, unsigned flags, const int32_t* n_host,
+                                 const int64_t* in_off_host, const int64_t* out_off_host, const void* in_base,
+                                 void* out_base, ptd_plan** plan_out)
+{
+    if (!plan_out) return PTD_EINVAL;
+    *plan_out = nullptr;
+    const ptd_status c = check_batch(count, dtype, n_host, in_off_host, out_off_host, in_base, out_base);
+    if (c != PTD_OK) return c;
+    if (flags & ~(PTD_HERMITIAN | PTD_ADJOINT | PTD_PLAN_RECONSTRUCT)) return PTD_EINVAL;
+    const bool rec = flags & PTD_PLAN_RECONSTRUCT;
+    if ((flags & PTD_ADJOINT) && !rec) return PTD_EINVAL;
+    std::vector<unsigned char> img;
+    int nitems = 0;
+    ptd::batched_fill(count, dtype, n_host, in_off_host, out_off_host, img, &nitems);
+    ptd_plan* p = new (std::nothrow) ptd_plan;
+    if (!p) return PTD_ENOMEM;
+    const size_t bytes = 256 + img.size();
+    if (hipMalloc(&p->buf, bytes) != hipSuccess) {
+        delete p;
+        return PTD_ENOMEM;
+    }
+    hipError_t e = hipMemcpy((unsigned char*)p->buf + 256, img.data(), img.size(), hipMemcpyHostToDevice);
+    hipStream_t cs = nullptr;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        // the queue counter is reset by a kernel node (no memset node in the graph)
+        hipError_t le = ptd::batched_launch(dtype, flags & PTD_HERMITIAN, rec, flags & PTD_ADJOINT, in_base, out_base,
+                                            p->buf, count, nitems, ptd::device_cu_count(), cs);
+        e = hipStreamEndCapture(cs, &p->graph);
+        if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        ptd_batch_plan_destroy(p);
+        return hip_status(e);
+    }
+    *plan_out = p;
+    return PTD_OK;
+}
+
+ptd_status ptd_batch_plan_launch(ptd_plan* plan, ptd_stream stream)
+{
+    if (!plan || !plan->exec) return PTD_EINVAL;
+    return hip_status(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+}
+
+void ptd_batch_plan_destroy(ptd_plan* plan)
+{
+    if (!plan) return;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->buf) (void)hipFree(plan->buf);
+    delete plan;
 }
 
 // Testing hook: the single-launch schedule with an explicit lookahead.

@@ -33,22 +33,15 @@
 // place on A (the WHT over z_hi and the one over z_lo act on different bits
 // and commute).
 #include "engine.hpp"
+#include "group.hpp"
 #include "internal.hpp"
 
 namespace ptd {
 
 namespace {
 
-constexpr int GROUP_THREADS = 512;
 constexpr int TILE_THREADS = 256;
 constexpr int HIGH_THREADS = 256;
-
-template <class V>
-constexpr int group_logt(int logn)
-{
-    // 128-byte row segments: 16 complex64 or 8 complex128
-    return logn < (sizeof(V) == 4 ? 4 : 3) ? logn : (sizeof(V) == 4 ? 4 : 3);
-}
 
 template <class V>
 constexpr int high_logw()
@@ -59,49 +52,6 @@ constexpr int high_logw()
 // ------------------------------------------------------------------------
 // single pass, n <= 10
 
-template <class V, int LOGN, int LOGT, bool REAL_OUT>
-__device__ __forceinline__ void group_fwd(const cplx<V>* __restrict__ A, int64_t lda, void* __restrict__ out,
-                                          int64_t ldo, int g, cplx<V>* lds)
-{
-    constexpr int NT = GROUP_THREADS;
-    const uint32_t xg = (uint32_t)g << LOGT;
-    const V scale = exp2_neg<V>(LOGN);
-    auto gather = [&](int vec, int pos, V& re, V& im) {
-        const cplx<V> v = A[(int64_t)pos * lda + (pos ^ (int)(xg | vec))];
-        re = v.re;
-        im = v.im;
-    };
-    auto store = [&](int vec, int pos, V re, V im) {
-        const uint32_t x = xg | (uint32_t)vec;
-        mul_ipow(__popc(x & (uint32_t)pos) & 3, re, im);
-        re *= scale;
-        im *= scale;
-        if constexpr (REAL_OUT) {
-            ((V*)out)[(int64_t)x * ldo + pos] = re;
-        } else {
-            cplx<V> c;
-            c.re = re;
-            c.im = im;
-            ((cplx<V>*)out)[(int64_t)x * ldo + pos] = c;
-        }
-    };
-    LdsVecs<V, LOGN> lr{lds};
-    LdsVecsW<V, LOGN> lw{lds};
-    if constexpr (LOGN <= 4) {
-        wht_round<V, LOGT, LOGN, 0, LOGN, NT, true>(gather, store);
-    } else if constexpr (LOGN <= 8) {
-        wht_round<V, LOGT, LOGN, 0, 4, NT, true>(gather, lw);
-        __syncthreads();
-        wht_round<V, LOGT, LOGN, 4, LOGN - 4, NT, false>(lr, store);
-    } else {
-        wht_round<V, LOGT, LOGN, 0, 4, NT, true>(gather, lw);
-        __syncthreads();
-        wht_round<V, LOGT, LOGN, 4, 4, NT, false>(lr, lw);
-        __syncthreads();
-        wht_round<V, LOGT, LOGN, 8, LOGN - 8, NT, false>(lr, store);
-    }
-}
-
 template <class V, int LOGN, bool REAL_OUT>
 __global__ __launch_bounds__(GROUP_THREADS) void k_group_fwd(const cplx<V>* __restrict__ A, int64_t lda,
                                                              void* __restrict__ out, int64_t ldo)
@@ -109,49 +59,6 @@ __global__ __launch_bounds__(GROUP_THREADS) void k_group_fwd(const cplx<V>* __re
     constexpr int LOGT = group_logt<V>(LOGN);
     __shared__ cplx<V> lds[(1 << LOGT) * ((1 << LOGN) + 1)];
     group_fwd<V, LOGN, LOGT, REAL_OUT>(A, lda, out, ldo, blockIdx.x, lds);
-}
-
-template <class V, int LOGN, int LOGT, bool REAL_IN>
-__device__ __forceinline__ void group_rec(const void* __restrict__ coeff, cplx<V>* __restrict__ A, int64_t lda,
-                                          V scale, int g, cplx<V>* lds)
-{
-    constexpr int NT = GROUP_THREADS;
-    const uint32_t xg = (uint32_t)g << LOGT;
-    auto load = [&](int vec, int pos, V& re, V& im) {
-        const uint32_t x = xg | (uint32_t)vec;
-        const int64_t o = (int64_t)x * (1 << LOGN) + pos;
-        if constexpr (REAL_IN) {
-            re = ((const V*)coeff)[o];
-            im = (V)0;
-        } else {
-            const cplx<V> c = ((const cplx<V>*)coeff)[o];
-            re = c.re;
-            im = c.im;
-        }
-        // (-i)^p = i^{-p}
-        mul_ipow((4 - (__popc(x & (uint32_t)pos) & 3)) & 3, re, im);
-    };
-    auto scatter = [&](int vec, int pos, V re, V im) {
-        cplx<V> c;
-        c.re = re * scale;
-        c.im = im * scale;
-        A[(int64_t)pos * lda + (pos ^ (int)(xg | vec))] = c;
-    };
-    LdsVecs<V, LOGN> lr{lds};
-    LdsVecsW<V, LOGN> lw{lds};
-    if constexpr (LOGN <= 4) {
-        wht_round<V, LOGT, LOGN, 0, LOGN, NT, true>(load, scatter);
-    } else if constexpr (LOGN <= 8) {
-        wht_round<V, LOGT, LOGN, LOGN - 4, 4, NT, false>(load, lw);
-        __syncthreads();
-        wht_round<V, LOGT, LOGN, 0, LOGN - 4, NT, true>(lr, scatter);
-    } else {
-        wht_round<V, LOGT, LOGN, LOGN - 4, 4, NT, false>(load, lw);
-        __syncthreads();
-        wht_round<V, LOGT, LOGN, LOGN - 8, 4, NT, false>(lr, lw);
-        __syncthreads();
-        wht_round<V, LOGT, LOGN, 0, LOGN - 8, NT, true>(lr, scatter);
-    }
 }
 
 template <class V, int LOGN, bool REAL_IN>

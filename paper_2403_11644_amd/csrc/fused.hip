@@ -583,6 +583,8 @@ __global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst,
 
 }  // namespace
 
+int device_cu_count() { return device_info().cus; }
+
 size_t fused_workspace_bytes(int n, ptd_dtype dt)
 {
     // enough group counters for the smallest groups any shape uses

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/ptd.h"
 
 namespace ptd {
@@ -34,6 +36,17 @@ hipError_t launch_fused_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64
                             int cfg, hipStream_t st);
 // Plain 16-byte-per-lane device copy (bandwidth reference).
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
+
+// Compute units of the current device (256 on MI355X).
+int device_cu_count();
+
+// Batched single-pass launches over (matrix, group) items, n <= 10 each.
+int64_t batched_item_count(int count, ptd_dtype dt, const int32_t* n_host);
+size_t batched_buffer_bytes(int count, ptd_dtype dt, const int32_t* n_host);
+void batched_fill(int count, ptd_dtype dt, const int32_t* n_host, const int64_t* in_off, const int64_t* out_off,
+                  std::vector<unsigned char>& img, int* nitems_out);
+hipError_t batched_launch(ptd_dtype dt, bool herm, bool rec, bool adjoint, const void* in_base, void* out_base,
+                          void* buf, int count, int nitems, int cus, hipStream_t st);
 
 // Parseval residual: out_host[0] = ||A||_F^2, [1] = 2^n sum|c|^2, [2] = relative gap.
 size_t reduce_workspace_bytes();
