@@ -73,9 +73,11 @@ typedef void *ptd_stream;
  * ptd_nonempty_x).  Without it the output is the dense [x][z] array with
  * the empty rows written as zeros. */
 #define PTD_COMPACT (1u << 4)
-/* PTD_C64 only: Walsh-Hadamard butterflies with compensated (TwoSum)
+/* PTD_C64 dense only: Walsh-Hadamard butterflies with compensated (TwoSum)
  * float32 arithmetic; results are rounded to float32 at every pass
- * boundary. */
+ * boundary (the two-pass schedule is used for n >= 7, so the call moves
+ * twice the bytes of the default path).  PTD_EUNSUP with structure flags;
+ * PTD_EUNSUP for PTD_C128. */
 #define PTD_COMPENSATED (1u << 5)
 /* pauli_reconstruct only: multiply the result by 2^-n, which makes the call
  * the adjoint (vector-Jacobian product) of pauli_decompose. */

@@ -8,3 +8,4 @@ from .api import (  # noqa: F401
     decompose, decompose_batched, nonempty_x, num_nonempty_x, pad_to_power_of_two, parseval, reconstruct,
 )
 from .labels import flat_index, index, label  # noqa: F401
+from .autograd import PauliDecompose, PauliReconstruct, pauli_decompose, pauli_reconstruct  # noqa: F401

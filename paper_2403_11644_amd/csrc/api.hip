@@ -137,7 +137,7 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
         return hip_status(ptd::launch_structured(n, dtype, herm, flags & PTD_BANDS_IN, flags & PTD_COMPACT, se, count,
                                                  A, lda, coeff, st));
     }
-    if (flags & PTD_COMPENSATED) return PTD_EUNSUP;
+    if (flags & PTD_COMPENSATED) return hip_status(ptd::launch_dense_fwd_comp(n, herm, A, lda, coeff, st));
     if (use_fused(n, dtype, flags)) {
         if (!ws) return PTD_ENOSPC;
         return hip_status(ptd::launch_fused_fwd(n, dtype, herm, A, lda, coeff, ws, kFusedLookahead, 0, st));

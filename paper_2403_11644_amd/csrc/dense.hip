@@ -76,12 +76,12 @@ __global__ __launch_bounds__(GROUP_THREADS) void k_group_rec(const void* __restr
 // grid (nb, nb): tile (R, C) = (blockIdx.y, blockIdx.x).  With xh_count > 0
 // the grid is (nb, xh_count) instead and covers the tiles of the X-pattern
 // groups x_hi = xh0 + blockIdx.y only (R = blockIdx.x, C = R ^ x_hi).
-template <class V, bool HERM>
+template <class V, bool HERM, bool COMP>
 __global__ __launch_bounds__(TILE_THREADS) void k_tile_fwd(const cplx<V>* __restrict__ A, int64_t lda,
                                                            void* __restrict__ out, int64_t ldo, int xh0,
                                                            int xh_count)
 {
-    __shared__ cplx<V> lds[64 * 65];
+    __shared__ cplx<V> lds[(COMP ? 2 : 1) * 64 * 65];
     const int R = xh_count ? (int)blockIdx.x : (int)blockIdx.y;
     const int C = xh_count ? (R ^ (xh0 + (int)blockIdx.y)) : (int)blockIdx.x;
     const int xh = R ^ C;
@@ -110,22 +110,39 @@ __global__ __launch_bounds__(TILE_THREADS) void k_tile_fwd(const cplx<V>* __rest
             ((cplx<V>*)out)[o] = c;
         }
     };
-    LdsVecs<V, 6> lr{lds};
-    LdsVecsW<V, 6> lw{lds};
-    wht_round<V, 6, 6, 0, 4, TILE_THREADS, true>(gather, lw);
-    __syncthreads();
-    wht_round<V, 6, 6, 4, 2, TILE_THREADS, false>(lr, store);
+    if constexpr (COMP) {
+        // compensated pairs; the pass boundary keeps hi (= fl(hi + lo))
+        auto gather_c = [&](int vec, int pos, V& rh, V& rl, V& ih, V& il) {
+            gather(vec, pos, rh, ih);
+            rl = (V)0;
+            il = (V)0;
+        };
+        auto store_c = [&](int vec, int pos, V rh, V, V ih, V) { store(vec, pos, rh, ih); };
+        LdsVecsComp<V, 6> cr{lds, lds + 64 * 65};
+        LdsVecsCompW<V, 6> cw{lds, lds + 64 * 65};
+        wht_round_comp<V, 6, 6, 0, 4, TILE_THREADS, true>(gather_c, cw);
+        __syncthreads();
+        wht_round_comp<V, 6, 6, 4, 2, TILE_THREADS, false>(cr, store_c);
+    } else {
+        LdsVecs<V, 6> lr{lds};
+        LdsVecsW<V, 6> lw{lds};
+        wht_round<V, 6, 6, 0, 4, TILE_THREADS, true>(gather, lw);
+        __syncthreads();
+        wht_round<V, 6, 6, 4, 2, TILE_THREADS, false>(lr, store);
+    }
 }
 
 // pass 2: WHT over the block index (stride 64) of each output row chunk,
 // then the phase and the scale.
-template <class V, int LOGM, bool HERM>
+template <class V, int LOGM, bool HERM, bool COMP>
 __global__ __launch_bounds__(HIGH_THREADS) void k_high_fwd(void* __restrict__ out, int64_t ldo, int x0)
 {
-    constexpr int LOGW = high_logw<V>();
+    // compensated mode keeps hi and lo in LDS: half as many columns per block
+    constexpr int LOGW = COMP ? high_logw<V>() - 1 : high_logw<V>();
     constexpr int CH = 6 - LOGW;
     constexpr int NT = HIGH_THREADS;
-    __shared__ cplx<V> lds[(1 << LOGW) * ((1 << LOGM) + 1)];
+    constexpr int PLANE = (1 << LOGW) * ((1 << LOGM) + 1);
+    __shared__ cplx<V> lds[(COMP ? 2 : 1) * PLANE];
     const int x = x0 + (int)(blockIdx.x >> CH);
     const int z0 = (blockIdx.x & ((1 << CH) - 1)) << LOGW;
     const int xh = x >> 6, xl = x & 63;
@@ -167,20 +184,46 @@ __global__ __launch_bounds__(HIGH_THREADS) void k_high_fwd(void* __restrict__ ou
             rowc[z] = c;
         }
     };
-    LdsVecs<V, LOGM> lr{lds};
-    LdsVecsW<V, LOGM> lw{lds};
-    if constexpr (LOGM <= 4) {
-        wht_round<V, LOGW, LOGM, 0, LOGM, NT, true>(load, store);
-    } else if constexpr (LOGM <= 8) {
-        wht_round<V, LOGW, LOGM, 0, 4, NT, true>(load, lw);
-        __syncthreads();
-        wht_round<V, LOGW, LOGM, 4, LOGM - 4, NT, true>(lr, store);
+    if constexpr (COMP) {
+        auto load_c = [&](int vec, int pos, V& rh, V& rl, V& ih, V& il) {
+            load(vec, pos, rh, ih);
+            rl = (V)0;
+            il = (V)0;
+        };
+        // the phase and the power-of-two scale are exact on hi and lo alike;
+        // hi = fl(hi + lo) after the last renormalisation
+        auto store_c = [&](int vec, int pos, V rh, V, V ih, V) { store(vec, pos, rh, ih); };
+        LdsVecsComp<V, LOGM> cr{lds, lds + PLANE};
+        LdsVecsCompW<V, LOGM> cw{lds, lds + PLANE};
+        if constexpr (LOGM <= 4) {
+            wht_round_comp<V, LOGW, LOGM, 0, LOGM, NT, true>(load_c, store_c);
+        } else if constexpr (LOGM <= 8) {
+            wht_round_comp<V, LOGW, LOGM, 0, 4, NT, true>(load_c, cw);
+            __syncthreads();
+            wht_round_comp<V, LOGW, LOGM, 4, LOGM - 4, NT, true>(cr, store_c);
+        } else {
+            wht_round_comp<V, LOGW, LOGM, 0, 4, NT, true>(load_c, cw);
+            __syncthreads();
+            wht_round_comp<V, LOGW, LOGM, 4, 4, NT, true>(cr, cw);
+            __syncthreads();
+            wht_round_comp<V, LOGW, LOGM, 8, LOGM - 8, NT, true>(cr, store_c);
+        }
     } else {
-        wht_round<V, LOGW, LOGM, 0, 4, NT, true>(load, lw);
-        __syncthreads();
-        wht_round<V, LOGW, LOGM, 4, 4, NT, true>(lr, lw);
-        __syncthreads();
-        wht_round<V, LOGW, LOGM, 8, LOGM - 8, NT, true>(lr, store);
+        LdsVecs<V, LOGM> lr{lds};
+        LdsVecsW<V, LOGM> lw{lds};
+        if constexpr (LOGM <= 4) {
+            wht_round<V, LOGW, LOGM, 0, LOGM, NT, true>(load, store);
+        } else if constexpr (LOGM <= 8) {
+            wht_round<V, LOGW, LOGM, 0, 4, NT, true>(load, lw);
+            __syncthreads();
+            wht_round<V, LOGW, LOGM, 4, LOGM - 4, NT, true>(lr, store);
+        } else {
+            wht_round<V, LOGW, LOGM, 0, 4, NT, true>(load, lw);
+            __syncthreads();
+            wht_round<V, LOGW, LOGM, 4, 4, NT, true>(lr, lw);
+            __syncthreads();
+            wht_round<V, LOGW, LOGM, 8, LOGM - 8, NT, true>(lr, store);
+        }
     }
 }
 
@@ -264,6 +307,47 @@ __global__ __launch_bounds__(HIGH_THREADS) void k_high_rec(cplx<V>* __restrict__
 }
 
 // ------------------------------------------------------------------------
+// compensated single pass for n <= 6: every X-pattern of the matrix in one
+// workgroup (2^n vectors of 2^n positions, hi and lo planes in LDS)
+
+template <class V, int LOGN, bool HERM>
+__global__ __launch_bounds__(TILE_THREADS) void k_small_comp(const cplx<V>* __restrict__ A, int64_t lda,
+                                                             void* __restrict__ out)
+{
+    constexpr int N = 1 << LOGN;
+    constexpr int PLANE = N * (N + 1);
+    __shared__ cplx<V> lds[2 * PLANE];
+    const V scale = exp2_neg<V>(LOGN);
+    auto gather = [&](int vec, int pos, V& rh, V& rl, V& ih, V& il) {
+        const cplx<V> v = A[(int64_t)pos * lda + (pos ^ vec)];
+        rh = v.re;
+        ih = v.im;
+        rl = (V)0;
+        il = (V)0;
+    };
+    auto store = [&](int vec, int pos, V re, V, V im, V) {
+        mul_ipow(__popc((uint32_t)(vec & pos)) & 3, re, im);
+        if constexpr (HERM) {
+            ((V*)out)[(int64_t)vec * N + pos] = re * scale;
+        } else {
+            cplx<V> c;
+            c.re = re * scale;
+            c.im = im * scale;
+            ((cplx<V>*)out)[(int64_t)vec * N + pos] = c;
+        }
+    };
+    LdsVecsComp<V, LOGN> cr{lds, lds + PLANE};
+    LdsVecsCompW<V, LOGN> cw{lds, lds + PLANE};
+    if constexpr (LOGN <= 4) {
+        wht_round_comp<V, LOGN, LOGN, 0, LOGN, TILE_THREADS, true>(gather, store);
+    } else {
+        wht_round_comp<V, LOGN, LOGN, 0, 4, TILE_THREADS, true>(gather, cw);
+        __syncthreads();
+        wht_round_comp<V, LOGN, LOGN, 4, LOGN - 4, TILE_THREADS, false>(cr, store);
+    }
+}
+
+// ------------------------------------------------------------------------
 // dispatch over n (compile-time sizes)
 
 template <class V, bool HERM>
@@ -285,7 +369,7 @@ hipError_t fwd_group(int n, const void* A, int64_t lda, void* out, hipStream_t s
 }
 
 // stage: 3 = both passes, 1 = tile pass only, 2 = row pass only (timing)
-template <class V, bool HERM>
+template <class V, bool HERM, bool COMP = false>
 hipError_t fwd_two_pass(int n, const void* A, int64_t lda, void* out, hipStream_t st, int stage = 3)
 {
     const cplx<V>* a = (const cplx<V>*)A;
@@ -299,20 +383,20 @@ hipError_t fwd_two_pass(int n, const void* A, int64_t lda, void* out, hipStream_
         const int cnt = chunk ? (nb - xh0 < chunk ? nb - xh0 : chunk) : nb;
         if (stage & 1) {
             if (chunk)
-                hipLaunchKernelGGL((k_tile_fwd<V, HERM>), dim3(nb, cnt), dim3(TILE_THREADS), 0, st, a, lda, out, ldo,
+                hipLaunchKernelGGL((k_tile_fwd<V, HERM, COMP>), dim3(nb, cnt), dim3(TILE_THREADS), 0, st, a, lda, out, ldo,
                                    xh0, cnt);
             else
-                hipLaunchKernelGGL((k_tile_fwd<V, HERM>), dim3(nb, nb), dim3(TILE_THREADS), 0, st, a, lda, out, ldo,
+                hipLaunchKernelGGL((k_tile_fwd<V, HERM, COMP>), dim3(nb, nb), dim3(TILE_THREADS), 0, st, a, lda, out, ldo,
                                    0, 0);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
         if (!(stage & 2)) continue;
-        const dim3 g2((unsigned)(((int64_t)cnt * 64) << (6 - high_logw<V>())));
+        const dim3 g2((unsigned)(((int64_t)cnt * 64) << (6 - (COMP ? high_logw<V>() - 1 : high_logw<V>()))));
         const int x0 = xh0 * 64;
         switch (n - 6) {
 #define PTD_CASE(MM) \
-    case MM: hipLaunchKernelGGL((k_high_fwd<V, MM, HERM>), g2, dim3(HIGH_THREADS), 0, st, out, ldo, x0); break;
+    case MM: hipLaunchKernelGGL((k_high_fwd<V, MM, HERM, COMP>), g2, dim3(HIGH_THREADS), 0, st, out, ldo, x0); break;
             PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5)
             PTD_CASE(6) PTD_CASE(7) PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
 #undef PTD_CASE
@@ -387,6 +471,25 @@ hipError_t launch_dense_fwd_stage(int n, ptd_dtype dt, bool herm, const void* A,
                     : fwd_two_pass<double, false>(n, A, lda, out, st, stage);
     return herm ? fwd_two_pass<float, true>(n, A, lda, out, st, stage)
                 : fwd_two_pass<float, false>(n, A, lda, out, st, stage);
+}
+
+hipError_t launch_dense_fwd_comp(int n, bool herm, const void* A, int64_t lda, void* out, hipStream_t st)
+{
+    const cplx<float>* a = (const cplx<float>*)A;
+    if (n >= 7) return herm ? fwd_two_pass<float, true, true>(n, A, lda, out, st) : fwd_two_pass<float, false, true>(n, A, lda, out, st);
+    switch (n) {
+#define PTD_CASE(NN)                                                                                               \
+    case NN:                                                                                                       \
+        if (herm)                                                                                                  \
+            hipLaunchKernelGGL((k_small_comp<float, NN, true>), dim3(1), dim3(TILE_THREADS), 0, st, a, lda, out);  \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_small_comp<float, NN, false>), dim3(1), dim3(TILE_THREADS), 0, st, a, lda, out); \
+        break;
+        PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5) PTD_CASE(6)
+#undef PTD_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_dense_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const void* coeff, void* A, int64_t lda,

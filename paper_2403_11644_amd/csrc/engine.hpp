@@ -140,3 +140,125 @@ __device__ __forceinline__ V exp2_neg(int n)
 }
 
 }  // namespace ptd
+
+// ---------------------------------------------------------------------------
+// Compensated butterflies (complex64 accuracy mode).  Every value carries a
+// (hi, lo) pair; each radix-2 step computes hi with the error-free TwoSum
+// transformation (Knuth) and adds the rounding error to the low parts, so a
+// run of stages loses no more than the final rounding of hi + lo.  TwoSum is
+// commutative and odd, which keeps the XOR-permutation symmetry of the plain
+// network (exactly real coefficients for Hermitian input).
+
+namespace ptd {
+
+template <class V>
+__device__ __forceinline__ void two_sum(V a, V b, V& s, V& e)
+{
+    s = a + b;
+    const V bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// In-place radix-2^NB WHT of compensated pairs.
+template <class V, int NB>
+__device__ __forceinline__ void wht_reg_comp(V* rh, V* rl, V* ih, V* il)
+{
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int m = 0; m < (1 << NB); ++m) {
+            if (!(m & (1 << b))) {
+                const int p = m | (1 << b);
+                V s, e, d, f;
+                two_sum(rh[m], rh[p], s, e);
+                two_sum(rh[m], -rh[p], d, f);
+                const V sl = rl[m] + rl[p] + e, dl = rl[m] - rl[p] + f;
+                rh[m] = s;
+                rl[m] = sl;
+                rh[p] = d;
+                rl[p] = dl;
+                two_sum(ih[m], ih[p], s, e);
+                two_sum(ih[m], -ih[p], d, f);
+                const V tl = il[m] + il[p] + e, ul = il[m] - il[p] + f;
+                ih[m] = s;
+                il[m] = tl;
+                ih[p] = d;
+                il[p] = ul;
+            }
+        }
+    }
+    // renormalise: hi takes the rounded sum, lo the remainder
+#pragma unroll
+    for (int m = 0; m < (1 << NB); ++m) {
+        V s, e;
+        two_sum(rh[m], rl[m], s, e);
+        rh[m] = s;
+        rl[m] = e;
+        two_sum(ih[m], il[m], s, e);
+        ih[m] = s;
+        il[m] = e;
+    }
+}
+
+// Compensated round: like wht_round, with src(vec, pos, rh, rl, ih, il) and
+// dst(vec, pos, rh, rl, ih, il).
+template <class V, int LOG_NV, int LOG_L, int B0, int NB, int NTHR, bool VEC_FAST, class Src, class Dst>
+__device__ __forceinline__ void wht_round_comp(const Src& src, const Dst& dst)
+{
+    static_assert(NB >= 1 && NB <= 4, "radix 2..16 per round");
+    constexpr int R = 1 << NB;
+    constexpr int NITEMS = 1 << (LOG_NV + LOG_L - NB);
+    for (int it = threadIdx.x; it < NITEMS; it += NTHR) {
+        int vec, base;
+        if constexpr (VEC_FAST) {
+            vec = it & ((1 << LOG_NV) - 1);
+            base = insert_zero_bits(it >> LOG_NV, B0, NB);
+        } else {
+            constexpr int PB = LOG_L - NB;
+            base = insert_zero_bits(it & ((1 << PB) - 1), B0, NB);
+            vec = it >> PB;
+        }
+        V rh[R], rl[R], ih[R], il[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) src(vec, base + (m << B0), rh[m], rl[m], ih[m], il[m]);
+        wht_reg_comp<V, NB>(rh, rl, ih, il);
+#pragma unroll
+        for (int m = 0; m < R; ++m) dst(vec, base + (m << B0), rh[m], rl[m], ih[m], il[m]);
+    }
+}
+
+// LDS storage of compensated pairs: hi and lo in two arrays of the LdsVecs
+// layout.
+template <class V, int LOG_L>
+struct LdsVecsComp {
+    static constexpr int PITCH = (1 << LOG_L) + 1;
+    cplx<V>* hi;
+    cplx<V>* lo;
+    __device__ __forceinline__ void operator()(int vec, int pos, V& rh, V& rl, V& ih, V& il) const
+    {
+        const cplx<V> a = hi[vec * PITCH + pos], b = lo[vec * PITCH + pos];
+        rh = a.re;
+        ih = a.im;
+        rl = b.re;
+        il = b.im;
+    }
+};
+
+template <class V, int LOG_L>
+struct LdsVecsCompW {
+    static constexpr int PITCH = (1 << LOG_L) + 1;
+    cplx<V>* hi;
+    cplx<V>* lo;
+    __device__ __forceinline__ void operator()(int vec, int pos, V rh, V rl, V ih, V il) const
+    {
+        cplx<V> a, b;
+        a.re = rh;
+        a.im = ih;
+        b.re = rl;
+        b.im = il;
+        hi[vec * PITCH + pos] = a;
+        lo[vec * PITCH + pos] = b;
+    }
+};
+
+}  // namespace ptd

@@ -20,6 +20,10 @@ hipError_t launch_dense_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64
 hipError_t launch_dense_fwd_stage(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out, int stage,
                                   hipStream_t st);
 
+// Dense complex64 decompose with compensated (TwoSum) butterflies: one
+// workgroup for n <= 6, the two-pass schedule otherwise.
+hipError_t launch_dense_fwd_comp(int n, bool herm, const void* A, int64_t lda, void* out, hipStream_t st);
+
 // Dense reconstruct: A = scale_log2 ... A = 2^-adj_n * sum_P c_P P.
 hipError_t launch_dense_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const void* coeff, void* A,
                             int64_t lda, int path, hipStream_t st);
