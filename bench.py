@@ -1,17 +1,21 @@
 #!/usr/bin/env python
-"""Benchmark of the dense Pauli decomposition hot path on one MI355X.
+"""Benchmark of the Pauli decomposition hot path on one MI355X.
 
-Workload: the n = 14 dense matrix (16384 x 16384, complex128, real and
-imaginary parts iid N(0, 1), seed 0) -- the headline configuration -- and its
-complex64 cast.  A "step" is one full pauli_decompose call computing all
-4^14 = 268,435,456 coefficients, input resident in HBM.  The primary value
-is the float64 (complex128 -> complex128) path; the complex64 path is
-reported beside it with its error against the float64 oracle.
+Headline workload: the n = 14 dense matrix (16384 x 16384 complex128, real
+and imaginary parts iid N(0, 1), seed 0).  A "step" is one pauli_decompose
+call computing all 4^14 = 268,435,456 coefficients with the input resident
+in HBM; the primary value is the float64 path (complex128 -> complex128).
 
-Prints ONE JSON line:  metric, value (GCoeff/s), ms_per_step, the roofline
-of the dominant kernel (HIP-event timing of that kernel alone, algorithmic
-bytes = read A once + write c once), the oracle timed on this host's cores
-on a bounded sample (cpu_baseline), and the sampled error against it.
+Prints ONE JSON line.  Besides the contract fields it carries:
+  roofline      the dominant kernel (k_fused_fwd, the single launch that
+                does the whole decomposition), timed with HIP events on the
+                stream it runs on; algorithmic bytes = read A once + write
+                c once (32 B per coefficient for complex128)
+  cpu_baseline  the oracle on this host's cores, on a bounded sample
+  legs          complex64 (with its error against the float64 oracle), the
+                two-pass schedule, n = 13 Hermitian, n = 14 banded skip vs
+                dense, n = 15 compensated complex64, and the 4096-matrix
+                batched plan against per-matrix calls
 """
 from __future__ import annotations
 
@@ -25,7 +29,7 @@ import time
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, 8 TB/s
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
 
 def _kernel_hash() -> str:
@@ -36,23 +40,21 @@ def _kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel: str, n: int, dtype: str):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
+def _traffic(kernel: str, key: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
-        return None
     try:
         data = json.load(open(path))
-    except Exception:
+    except (OSError, ValueError):
         return None
-    rec = data.get("%s/n%d/%s" % (kernel, n, dtype))
+    rec = data.get("%s/%s" % (kernel, key))
     if not rec or rec.get("kernel_hash") != _kernel_hash():
         return None
     return rec.get("bytes_per_launch")
 
 
-def _time_calls(fn, steps: int, warmup: int, stream) -> float:
+def _time(fn, steps: int, warmup: int, stream) -> float:
     import torch
 
     for _ in range(warmup):
@@ -65,22 +67,29 @@ def _time_calls(fn, steps: int, warmup: int, stream) -> float:
         fn()
     t1.record(stream)
     torch.cuda.synchronize()
-    return t0.elapsed_time(t1) / steps  # ms per call
+    return t0.elapsed_time(t1) / steps  # ms
+
+
+def _rel(g, w) -> float:
+    return float(np.linalg.norm(g - w) / np.linalg.norm(w))
 
 
 def main() -> int:
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap = argparse.ArgumentParser(description="Pauli decomposition benchmark (one MI355X)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=14)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="all",
+                    help="comma list of reported legs to run: complex64, two_pass, copy, hermitian, band, n15, "
+                         "batched; 'all' or 'none'")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; the decomposition shards by X-pattern group "
-              "with no communication, so more GPUs are not measured here (--gpus 1).", file=sys.stderr)
+        print("bench.py: this build measures one GPU only. The decomposition shards by X-pattern group "
+              "with no communication between GPUs; run with --gpus 1.", file=sys.stderr)
         return 2
 
     import torch
@@ -89,6 +98,7 @@ def main() -> int:
     import paper_2403_11644_amd as ptd
     from paper_2403_11644_amd import _native, api
     import synth
+    from oracle import oracle as O
 
     n = args.n
     N = 1 << n
@@ -96,55 +106,141 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+    L = _native.lib()
 
     t_gen = time.time()
     A_host = synth.dense(n, seed=0)  # complex128, re then im, N(0, 1)
     A = torch.from_numpy(A_host).to(dev)
-    A64 = A.to(torch.complex64)  # the cast is not part of the timed step
     gen_s = time.time() - t_gen
     out128 = torch.empty((N, N), dtype=torch.complex128, device=dev)
-    out64 = torch.empty((N, N), dtype=torch.complex64, device=dev)
+    wsb = L.ptd_workspace_bytes(n, api.C128, 0, 0)
+    ws = torch.zeros(max(wsb, 16), dtype=torch.uint8, device=dev)
+    sh = api._stream_handle(dev, None)
 
-    ms128 = _time_calls(lambda: ptd.decompose(A, out=out128), args.steps, args.warmup, stream)
-    ms64 = _time_calls(lambda: ptd.decompose(A64, out=out64), args.steps, args.warmup, stream)
+    def run128():
+        _native.check(L.pauli_decompose(n, api.C128, 0, 0, api._ptr(A), N, api._ptr(out128), api._ptr(ws), wsb, sh),
+                      "pauli_decompose")
 
-    # per-kernel timing of the two passes (same launches as inside the call)
-    L = _native.lib()
-    kern = {}
-    for dtname, Ain, out in (("c128", A, out128), ("c64", A64, out64)):
-        code = api._dtype_code(Ain.dtype)
-        for stage, kname in ((1, "k_tile_fwd"), (2, "k_high_fwd")):
-            def fn(stage=stage, Ain=Ain, out=out, code=code):
-                _native.check(L.ptd_debug_decompose_stage(n, code, 0, api._ptr(Ain), N, api._ptr(out), stage,
-                                                          api._stream_handle(dev, None)), "stage")
-            kern[(dtname, kname)] = _time_calls(fn, args.steps, 2, stream)
-    # leave the outputs holding the full results again
-    ptd.decompose(A, out=out128)
-    ptd.decompose(A64, out=out64)
+    ms128 = _time(run128, args.steps, args.warmup, stream)
+    run128()
     torch.cuda.synchronize()
 
-    # plain device copy of the same bytes (practical bandwidth ceiling)
-    cpy = torch.empty_like(A)
-    ms_copy = _time_calls(lambda: cpy.copy_(A), 5, 2, stream)
-    copy_gbps = 2 * A.numel() * 16 / (ms_copy * 1e-3) / 1e9
-    del cpy
-
-    # error against the oracle on sampled strings, and the float64 Parseval residual
-    from oracle import oracle as O
-
+    # error on sampled strings against the oracle, and the float64 Parseval residual
     xs, zs = synth.sample_strings(n, 2000, seed=5)
     want = O.coeffs(A_host, xs, zs)
     ix = torch.from_numpy(xs.astype(np.int64)).to(dev)
     iz = torch.from_numpy(zs.astype(np.int64)).to(dev)
-    got128 = out128[ix, iz].cpu().numpy()
-    got64 = out64[ix, iz].cpu().numpy().astype(np.complex128)
-
-    def rel(g, w):
-        return float(np.linalg.norm(g - w) / np.linalg.norm(w))
-
-    err128, err64 = rel(got128, want), rel(got64, want)
+    err128 = _rel(out128[ix, iz].cpu().numpy(), want)
     _, _, pars128 = ptd.parseval(A, out128)
-    _, _, pars64 = ptd.parseval(A64, out64)
+
+    legs = {}
+    want_legs = set()
+    if args.legs == "all":
+        want_legs = {"complex64", "two_pass", "copy", "hermitian", "band", "n15", "batched"}
+    elif args.legs != "none":
+        want_legs = set(args.legs.split(","))
+    if "complex64" in want_legs:
+        # complex64 cast of the same matrix (cast excluded from the time)
+        A64 = A.to(torch.complex64)
+        out64 = torch.empty((N, N), dtype=torch.complex64, device=dev)
+        wsb64 = L.ptd_workspace_bytes(n, api.C64, 0, 0)
+        ws64 = torch.zeros(max(wsb64, 16), dtype=torch.uint8, device=dev)
+
+        def run64():
+            _native.check(L.pauli_decompose(n, api.C64, 0, 0, api._ptr(A64), N, api._ptr(out64), api._ptr(ws64),
+                                            wsb64, sh), "pauli_decompose")
+
+        ms64 = _time(run64, args.steps, args.warmup, stream)
+        run64()
+        torch.cuda.synchronize()
+        err64 = _rel(out64[ix, iz].cpu().numpy().astype(np.complex128), want)
+        _, _, pars64 = ptd.parseval(A64, out64)
+        legs["complex64"] = {"ms": round(ms64, 4), "GCoeff_s": round(ncoef / ms64 / 1e6, 2),
+                             "path_hbm_frac": round(16 * ncoef / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                             "err_rel_sampled_vs_f64_oracle": err64, "parseval_residual": pars64,
+                             "speedup_vs_f64": round(ms128 / ms64, 3)}
+        del out64, A64
+    if "two_pass" in want_legs:
+        # the two-pass schedule on the same input (same bytes moved twice)
+        def run_two():
+            _native.check(L.ptd_debug_decompose_stage(n, api.C128, 0, api._ptr(A), N, api._ptr(out128), 3, sh),
+                          "two-pass")
+
+        ms_two = _time(run_two, 5, 2, stream)
+        legs["two_pass_f64"] = {"ms": round(ms_two, 4), "single_launch_speedup": round(ms_two / ms128, 3)}
+    if "copy" in want_legs:
+        # plain device copy of the same bytes (practical bandwidth ceiling)
+        cpy = torch.empty_like(A)
+        ms_copy = _time(lambda: L.ptd_debug_copy(api._ptr(A), api._ptr(cpy), A.numel() * 16, sh), 5, 2, stream)
+        legs["copy_ceiling"] = {"GBps": round(2 * A.numel() * 16 / (ms_copy * 1e-3) / 1e9, 1),
+                                "frac_of_peak": round(2 * A.numel() * 16 / (ms_copy * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+        del cpy
+        torch.cuda.empty_cache()
+    g = torch.Generator(device=dev)
+    if "hermitian" in want_legs:
+        # n = 13 Hermitian complex128 -> real float64 (device-generated input)
+        g.manual_seed(13)
+        B = torch.randn((1 << 13, 1 << 13), dtype=torch.complex128, device=dev, generator=g)
+        H = (B + B.conj().T) / 2
+        del B
+        hout = torch.empty((1 << 13, 1 << 13), dtype=torch.float64, device=dev)
+        msh = _time(lambda: ptd.decompose(H, hermitian=True, out=hout), 10, 3, stream)
+        legs["hermitian_n13_f64"] = {"ms": round(msh, 4), "GCoeff_s": round(4.0 ** 13 / msh / 1e6, 2),
+                                     "path_hbm_frac": round(24 * 4.0 ** 13 / (msh * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+        del H, hout
+    if "band" in want_legs:
+        # n = 14 complex band, half-bandwidth 8: skip path from bands vs dense
+        band = synth.banded_complex(n, 8, seed=2)
+        bd = torch.from_numpy(band).to(dev)
+        cnt = ptd.num_nonempty_x(n, "banded", 8)
+        bout = torch.empty((cnt, N), dtype=torch.complex128, device=dev)
+        msb = _time(lambda: ptd.decompose(bd, structure="banded", s=8, bands=True, compact=True, out=bout), 10, 3,
+                    stream)
+        legs["band8_n14_skip"] = {"ms": round(msb, 4), "nonempty_x": cnt,
+                                  "speedup_vs_dense_f64": round(ms128 / msb, 1)}
+        del bd, bout
+    if "n15" in want_legs:
+        # n = 15 complex64, plain and compensated butterflies
+        g.manual_seed(15)
+        A15 = torch.randn((1 << 15, 1 << 15), dtype=torch.complex64, device=dev, generator=g)
+        o15 = torch.empty_like(A15)
+        ms15 = _time(lambda: ptd.decompose(A15, out=o15), 5, 2, stream)
+        ms15c = _time(lambda: ptd.decompose(A15, compensated=True, out=o15), 5, 2, stream)
+        legs["n15_c64"] = {"ms": round(ms15, 4), "GCoeff_s": round(4.0 ** 15 / ms15 / 1e6, 2),
+                           "path_hbm_frac": round(16 * 4.0 ** 15 / (ms15 * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                           "compensated_ms": round(ms15c, 4)}
+        del A15, o15
+        torch.cuda.empty_cache()
+    if "batched" in want_legs:
+        # 4096 Hermitian complex64 matrices, n uniform on {2..10}: one captured
+        # plan launch vs one pauli_decompose call per matrix
+        ns = synth.batched_ns(4096, seed=0).astype(np.int32)
+        sizes = np.array([1 << (2 * int(k)) for k in ns], dtype=np.int64)
+        offs = np.zeros(len(ns), dtype=np.int64)
+        offs[1:] = np.cumsum(sizes)[:-1]
+        g.manual_seed(1)
+        bbuf = torch.randn(int(sizes.sum()), dtype=torch.complex64, device=dev, generator=g)
+        bout2 = torch.empty(int(sizes.sum()), dtype=torch.float32, device=dev)
+        mats = [bbuf[o:o + s].view(1 << int(k), 1 << int(k)) for o, s, k in zip(offs, sizes, ns)]
+        for m in mats:  # Hermitian: (B + B^H) / 2 in place per matrix
+            m.copy_((m + m.conj().T) / 2)
+        plan = api.BatchPlan(bbuf, ns, offs, bout2, offs, dtype_code=api.C64, hermitian=True)
+        msp = _time(plan.launch, 10, 3, stream)
+        outs = [bout2[o:o + s].view(1 << int(k), 1 << int(k)) for o, s, k in zip(offs, sizes, ns)]
+
+        def per_matrix():
+            for m, o in zip(mats, outs):
+                ptd.decompose(m, hermitian=True, out=o)
+
+        msm = _time(per_matrix, 2, 1, stream)
+        plan.close()
+        tot = float(sizes.sum())
+        legs["batched_4096_herm_c64"] = {"plan_ms": round(msp, 4), "per_matrix_ms": round(msm, 4),
+                                         "speedup": round(msm / msp, 2), "GCoeff_s": round(tot / msp / 1e6, 2),
+                                         "path_hbm_frac": round(12 * tot / (msp * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                                         "coefficients": int(tot)}
+        del bbuf, bout2, mats, outs
+        torch.cuda.empty_cache()
 
     # CPU baseline: the oracle on whole X-pattern rows of the same matrix
     cpu = None
@@ -160,21 +256,14 @@ def main() -> int:
         O.rows(A_host, xs_rows, nthreads=threads)
         t_cpu = time.time() - t0
         cpu = {"value": rows * N / t_cpu / 1e9, "unit": "GCoeff/s", "cores": threads, "kind": "oracle",
-               "sample": "%d of %d X-pattern rows (all %d strings each) of the n=%d matrix, %.1f s; "
-                         "full n=%d run extrapolates to %.0f s" % (rows, N, N, n, t_cpu, n, t_cpu * N / rows)}
+               "sample": "%d of %d X-pattern rows (all %d strings each) of the n=%d matrix in %.1f s; the full "
+                         "decomposition would take about %.0f s" % (rows, N, N, n, t_cpu, t_cpu * N / rows)}
 
     bytes128 = 32.0 * ncoef  # read A (16 B) + write c (16 B) per coefficient
-    bytes64 = 16.0 * ncoef
-    dom = max(("k_tile_fwd", "k_high_fwd"), key=lambda k: kern[("c128", k)])
-    dom_ms = kern[("c128", dom)]
-    # each pass of the two-pass schedule reads and writes 4^n complex values
-    dom_bytes = 32.0 * ncoef
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    gcoef128 = ncoef / (ms128 * 1e-3) / 1e9
-    gcoef64 = ncoef / (ms64 * 1e-3) / 1e9
+    achieved = bytes128 / (ms128 * 1e-3) / 1e9
     line = {
         "metric": "Pauli GCoeff/s + % HBM roofline, n=14 dense; complex64 vs FP64 at stated error",
-        "value": round(gcoef128, 3),
+        "value": round(ncoef / ms128 / 1e6, 3),
         "unit": "GCoeff/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -187,19 +276,13 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "dense n=%d (%dx%d) complex128 A, re/im iid N(0,1) seed 0; all 4^%d "
                                "coefficients per step" % (n, N, N, n), "n": n, "parallelism": "none"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": _traffic(dom, n, "c128"),
-                     "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_ms, 4)},
-        "path_hbm_frac": round(bytes128 / (ms128 * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "roofline": {"bound": "hbm", "kernel": "k_fused_fwd", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": _traffic("k_fused_fwd", "n%d/c128" % n),
+                     "algorithmic_bytes_per_launch": bytes128, "avg_launch_ms": round(ms128, 4)},
         "err_rel_sampled": err128,
         "parseval_residual": pars128,
-        "complex64": {"value": round(gcoef64, 3), "unit": "GCoeff/s", "ms_per_step": round(ms64, 4),
-                      "path_hbm_frac": round(bytes64 / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                      "err_rel_sampled_vs_f64_oracle": err64, "parseval_residual": pars64,
-                      "speedup_vs_f64": round(ms128 / ms64, 3)},
-        "kernels_ms": {"%s/%s" % k: round(v, 4) for k, v in kern.items()},
-        "copy_GBps": round(copy_gbps, 1),
+        "legs": legs,
         "cpu_baseline": cpu,
         "input_gen_s": round(gen_s, 1),
         "kernel_hash": _kernel_hash(),

@@ -185,6 +185,25 @@ ptd_status ptd_parseval_residual(int n, ptd_dtype dtype, unsigned flags, const v
                                  const void *coeff, double *out_host, void *ws, size_t ws_bytes,
                                  ptd_stream stream);
 
+/*
+ * Autotuning of the dense single-launch schedule (n = 11..15, complex64 and
+ * complex128 for n <= 14, flags 0 or PTD_HERMITIAN).  ptd_autotune times the
+ * candidate settings (workgroup shape, gather cache policy, item prefetch,
+ * completion signalling, queue lookahead) at this (n, dtype, Hermitian)
+ * point on device buffers it allocates itself, admits a candidate only if
+ * its output on a Gaussian-integer matrix equals the default setting's bit
+ * for bit, records the fastest in a process-wide registry that
+ * pauli_decompose uses from then on, and returns it with its mean time over
+ * `reps` launches.  Synchronises `stream`.  ptd_set_tuning records a setting
+ * directly (e.g. one loaded from a cache file); ptd_get_tuning returns 1 and
+ * the tuned setting, or 0 and the default; ptd_clear_tuning forgets all.
+ */
+ptd_status ptd_autotune(int n, ptd_dtype dtype, unsigned flags, int reps, ptd_stream stream, int *cfg,
+                        int *lookahead, float *ms, int *tried, int *admitted);
+ptd_status ptd_set_tuning(int n, ptd_dtype dtype, unsigned flags, int cfg, int lookahead);
+int ptd_get_tuning(int n, ptd_dtype dtype, unsigned flags, int *cfg, int *lookahead);
+void ptd_clear_tuning(void);
+
 /* Human-readable name of a status code (static string). */
 const char *ptd_status_str(ptd_status st);
 /* HIP error code of the most recent PTD_EHIP on this thread (0 if none). */

@@ -9,3 +9,10 @@ from .api import (  # noqa: F401
 )
 from .labels import flat_index, index, label  # noqa: F401
 from .autograd import PauliDecompose, PauliReconstruct, pauli_decompose, pauli_reconstruct  # noqa: F401
+from . import tuning  # noqa: F401
+
+if __import__("os").environ.get("PTD_AUTOTUNE", "1") != "0":
+    try:
+        tuning.load()
+    except Exception:  # a missing or damaged cache only means default settings
+        pass

@@ -37,6 +37,10 @@ SIGNATURES = {
     "ptd_batch_plan_create": (I, [I, I, U, P, P, P, P, P, P]),
     "ptd_batch_plan_launch": (I, [P, P]),
     "ptd_batch_plan_destroy": (None, [P]),
+    "ptd_autotune": (I, [I, I, U, I, P, P, P, P, P, P]),
+    "ptd_set_tuning": (I, [I, I, U, I, I]),
+    "ptd_get_tuning": (I, [I, I, U, P, P]),
+    "ptd_clear_tuning": (None, []),
     "ptd_status_str": (ctypes.c_char_p, [I]),
     "ptd_last_hip_error": (I, []),
     "ptd_build_arch": (ctypes.c_char_p, []),

@@ -140,7 +140,9 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
     if (flags & PTD_COMPENSATED) return hip_status(ptd::launch_dense_fwd_comp(n, herm, A, lda, coeff, st));
     if (use_fused(n, dtype, flags)) {
         if (!ws) return PTD_ENOSPC;
-        return hip_status(ptd::launch_fused_fwd(n, dtype, herm, A, lda, coeff, ws, kFusedLookahead, 0, st));
+        ptd::FusedTuning t{0, kFusedLookahead};
+        (void)ptd::get_fused_tuning(n, dtype, herm, &t);
+        return hip_status(ptd::launch_fused_fwd(n, dtype, herm, A, lda, coeff, ws, t.la, t.cfg, st));
     }
     return hip_status(ptd::launch_dense_fwd(n, dtype, herm, A, lda, coeff, 0, st));
 }
@@ -320,6 +322,45 @@ void ptd_batch_plan_destroy(ptd_plan* plan)
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     if (plan->buf) (void)hipFree(plan->buf);
     delete plan;
+}
+
+// ------------------------------------------------------------------ tuning
+
+ptd_status ptd_set_tuning(int n, ptd_dtype dtype, unsigned flags, int cfg, int lookahead)
+{
+    if (!valid_dtype(dtype) || (flags & ~PTD_HERMITIAN) || !use_fused(n, dtype, flags)) return PTD_EINVAL;
+    if (cfg < 0 || cfg > 31 || lookahead < 1 || lookahead > 64) return PTD_EINVAL;
+    ptd::set_fused_tuning(n, dtype, flags & PTD_HERMITIAN, ptd::FusedTuning{cfg, lookahead});
+    return PTD_OK;
+}
+
+int ptd_get_tuning(int n, ptd_dtype dtype, unsigned flags, int* cfg, int* lookahead)
+{
+    if (!valid_dtype(dtype) || (flags & ~PTD_HERMITIAN) || !cfg || !lookahead) return PTD_EINVAL;
+    ptd::FusedTuning t{0, kFusedLookahead};
+    const bool tuned = ptd::get_fused_tuning(n, dtype, flags & PTD_HERMITIAN, &t);
+    *cfg = t.cfg;
+    *lookahead = t.la;
+    return tuned ? 1 : 0;
+}
+
+void ptd_clear_tuning(void) { ptd::clear_fused_tuning(); }
+
+ptd_status ptd_autotune(int n, ptd_dtype dtype, unsigned flags, int reps, ptd_stream stream, int* cfg, int* lookahead,
+                        float* ms, int* tried, int* admitted)
+{
+    if (!valid_dtype(dtype) || (flags & ~PTD_HERMITIAN) || reps < 1 || !cfg || !lookahead || !ms || !tried ||
+        !admitted)
+        return PTD_EINVAL;
+    if (n < 1 || n > 16) return PTD_EINVAL;
+    if (!use_fused(n, dtype, flags)) return PTD_EUNSUP;
+    ptd::FusedTuning best{0, kFusedLookahead};
+    hipError_t e = ptd::autotune_fused(n, dtype, flags & PTD_HERMITIAN, reps, (hipStream_t)stream, &best, ms, tried,
+                                       admitted);
+    if (e != hipSuccess) return hip_status(e);
+    *cfg = best.cfg;
+    *lookahead = best.la;
+    return PTD_OK;
 }
 
 // Testing hook: the single-launch schedule with an explicit lookahead.

@@ -1,0 +1,194 @@
+// autotune.hip -- measured choice of the single-launch schedule's parameters.
+//
+// The persistent dense kernel (fused.hip) has a shape (threads per
+// workgroup, rows per phase-1 item, X-patterns per group), an option for
+// non-temporal gathers, item prefetch, deferred completion signals, and the
+// lookahead of its queues.  ptd_autotune times candidate settings at one
+// (n, dtype, Hermitian) point and records the fastest in a registry that
+// pauli_decompose reads.  A candidate is admitted only if its output on a
+// Gaussian-integer matrix (every partial sum exact in both precisions)
+// equals the default setting's output bit for bit.
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "engine.hpp"
+#include "internal.hpp"
+
+namespace ptd {
+
+namespace {
+
+std::mutex g_mu;
+std::map<int, FusedTuning> g_table;
+
+int key_of(int n, ptd_dtype dt, bool herm) { return (n << 2) | ((int)dt << 1) | (herm ? 1 : 0); }
+
+__device__ __forceinline__ uint32_t mix(uint32_t x)
+{
+    // integer hash (xorshift-multiply finaliser)
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+// Gaussian integers in [-8, 8]; Hermitian: the upper triangle decides.
+template <class V>
+__global__ void k_fill_int(cplx<V>* __restrict__ A, int n, int herm, uint32_t seed)
+{
+    const int64_t N = (int64_t)1 << n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N * N; e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = e >> n, c = e & (N - 1);
+        bool conj = false;
+        if (herm && r > c) {
+            const int64_t t = r;
+            r = c;
+            c = t;
+            conj = true;
+        }
+        const uint32_t h = mix((uint32_t)(r * N + c) ^ mix(seed));
+        V re = (V)((int)(h % 17u) - 8);
+        V im = (V)((int)((h >> 8) % 17u) - 8);
+        if (herm && r == c) im = (V)0;
+        cplx<V> v;
+        v.re = re;
+        v.im = conj ? -im : im;
+        A[e] = v;
+    }
+}
+
+__global__ void k_count_diff(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b, int64_t words,
+                             uint32_t* __restrict__ diff)
+{
+    uint32_t local = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+        local += a[i] != b[i] ? 1u : 0u;
+    if (local) atomicAdd(diff, local);
+}
+
+struct Buffers {
+    void* A = nullptr;
+    void* ref = nullptr;
+    void* out = nullptr;
+    void* ws = nullptr;
+    uint32_t* diff = nullptr;
+    ~Buffers()
+    {
+        if (A) (void)hipFree(A);
+        if (ref) (void)hipFree(ref);
+        if (out) (void)hipFree(out);
+        if (ws) (void)hipFree(ws);
+        if (diff) (void)hipFree(diff);
+    }
+};
+
+}  // namespace
+
+bool get_fused_tuning(int n, ptd_dtype dt, bool herm, FusedTuning* t)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_table.find(key_of(n, dt, herm));
+    if (it == g_table.end()) return false;
+    *t = it->second;
+    return true;
+}
+
+void set_fused_tuning(int n, ptd_dtype dt, bool herm, const FusedTuning& t)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table[key_of(n, dt, herm)] = t;
+}
+
+void clear_fused_tuning()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table.clear();
+}
+
+hipError_t autotune_fused(int n, ptd_dtype dt, bool herm, int reps, hipStream_t st, FusedTuning* best, float* best_ms,
+                          int* tried, int* admitted)
+{
+    const int64_t N = (int64_t)1 << n;
+    const size_t esz = dt == PTD_C128 ? 16 : 8;
+    const size_t in_bytes = (size_t)(N * N) * esz;
+    const size_t out_bytes = herm ? in_bytes / 2 : in_bytes;
+    const size_t wsb = fused_workspace_bytes(n, dt);
+    Buffers b;
+    hipError_t e = hipMalloc(&b.A, in_bytes);
+    if (e == hipSuccess) e = hipMalloc(&b.ref, out_bytes);
+    if (e == hipSuccess) e = hipMalloc(&b.out, out_bytes);
+    if (e == hipSuccess) e = hipMalloc(&b.ws, wsb);
+    if (e == hipSuccess) e = hipMalloc(&b.diff, sizeof(uint32_t));
+    if (e != hipSuccess) return e;
+    if (dt == PTD_C128)
+        hipLaunchKernelGGL(k_fill_int<double>, dim3(4096), dim3(256), 0, st, (cplx<double>*)b.A, n, herm ? 1 : 0, 12345u);
+    else
+        hipLaunchKernelGGL(k_fill_int<float>, dim3(4096), dim3(256), 0, st, (cplx<float>*)b.A, n, herm ? 1 : 0, 12345u);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // reference: the default setting
+    e = launch_fused_fwd(n, dt, herm, b.A, N, b.ref, b.ws, 3, 0, st);
+    if (e != hipSuccess) return e;
+
+    std::vector<FusedTuning> cands;
+    const int shapes[] = {2, 1, 3};
+    for (int sh : shapes) {
+        if (n == 15 && sh != 1) continue;
+        for (int opt : {4 | 16, 16, 4, 4 | 8 | 16})
+            for (int la : {1, 2, 3, 4, 6}) cands.push_back(FusedTuning{sh | opt, la});
+    }
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return e;
+    }
+    float bestt = 1e30f;
+    FusedTuning bt{0, 3};
+    int ntried = 0, nadmit = 0;
+    for (const FusedTuning& c : cands) {
+        // correctness first: bit-identical to the default on the integer matrix
+        if ((e = hipMemsetAsync(b.diff, 0, sizeof(uint32_t), st)) != hipSuccess) break;
+        e = launch_fused_fwd(n, dt, herm, b.A, N, b.out, b.ws, c.la, c.cfg, st);
+        if (e == hipErrorInvalidValue) {
+            e = hipSuccess;  // shape not built for this n
+            continue;
+        }
+        if (e != hipSuccess) break;
+        ++ntried;
+        hipLaunchKernelGGL(k_count_diff, dim3(2048), dim3(256), 0, st, (const uint32_t*)b.out, (const uint32_t*)b.ref,
+                           (int64_t)(out_bytes / 4), b.diff);
+        uint32_t diff = 1;
+        if ((e = hipMemcpyAsync(&diff, b.diff, sizeof diff, hipMemcpyDeviceToHost, st)) != hipSuccess) break;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) break;
+        if (diff != 0) continue;
+        ++nadmit;
+        (void)launch_fused_fwd(n, dt, herm, b.A, N, b.out, b.ws, c.la, c.cfg, st);  // warm-up
+        if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
+        for (int r = 0; r < reps; ++r) (void)launch_fused_fwd(n, dt, herm, b.A, N, b.out, b.ws, c.la, c.cfg, st);
+        if ((e = hipEventRecord(e1, st)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        ms /= (float)reps;
+        if (ms < bestt) {
+            bestt = ms;
+            bt = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return e;
+    if (nadmit == 0) return hipErrorUnknown;
+    *best = bt;
+    *best_ms = bestt;
+    *tried = ntried;
+    *admitted = nadmit;
+    set_fused_tuning(n, dt, herm, bt);
+    return hipSuccess;
+}
+
+}  // namespace ptd

@@ -41,6 +41,17 @@ hipError_t launch_fused_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64
 // Plain 16-byte-per-lane device copy (bandwidth reference).
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 
+// Tuned settings of the single-launch schedule (autotune.hip).
+struct FusedTuning {
+    int cfg;  // shape and options, see fused.hip (0 = default)
+    int la;   // queue lookahead in groups
+};
+bool get_fused_tuning(int n, ptd_dtype dt, bool herm, FusedTuning* t);
+void set_fused_tuning(int n, ptd_dtype dt, bool herm, const FusedTuning& t);
+void clear_fused_tuning();
+hipError_t autotune_fused(int n, ptd_dtype dt, bool herm, int reps, hipStream_t st, FusedTuning* best, float* best_ms,
+                          int* tried, int* admitted);
+
 // Compute units of the current device (256 on MI355X).
 int device_cu_count();
 

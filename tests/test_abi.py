@@ -124,3 +124,36 @@ def test_labels():
                 assert labels.index(labels.label(x, z, n)) == (x, z)
     with pytest.raises(ValueError):
         labels.index("XQ")
+
+
+def test_tuning_registry(lib):
+    cfg, la = ctypes.c_int(), ctypes.c_int()
+    lib.ptd_clear_tuning()
+    assert lib.ptd_get_tuning(14, 0, 0, ctypes.byref(cfg), ctypes.byref(la)) == 0
+    assert lib.ptd_set_tuning(14, 0, 0, 22, 4) == 0
+    assert lib.ptd_get_tuning(14, 0, 0, ctypes.byref(cfg), ctypes.byref(la)) == 1
+    assert (cfg.value, la.value) == (22, 4)
+    assert lib.ptd_get_tuning(14, 0, 1, ctypes.byref(cfg), ctypes.byref(la)) == 0  # Hermitian is separate
+    assert lib.ptd_set_tuning(10, 0, 0, 22, 4) == -1  # single-pass sizes have nothing to tune
+    assert lib.ptd_set_tuning(14, 0, 0, 99, 4) == -1
+    assert lib.ptd_set_tuning(14, 0, 0, 22, 0) == -1
+    assert lib.ptd_set_tuning(15, 0, 0, 1, 2) == -1  # complex128 n=15 runs the two-pass schedule
+    lib.ptd_clear_tuning()
+    assert lib.ptd_get_tuning(14, 0, 0, ctypes.byref(cfg), ctypes.byref(la)) == 0
+
+
+def test_batched_argument_errors(lib):
+    ns = np.array([3, 11], dtype=np.int32)
+    offs = np.zeros(2, dtype=np.int64)
+    P = ctypes.c_void_p
+    assert lib.ptd_batched_workspace_bytes(2, 0, P(ns.ctypes.data)) == 0  # n = 11 is too large
+    ns[1] = 4
+    assert lib.ptd_batched_workspace_bytes(2, 0, P(ns.ctypes.data)) > 0
+    args = (P(ns.ctypes.data), P(offs.ctypes.data), P(offs.ctypes.data), P(1), P(2))
+    assert lib.pauli_decompose_batched(0, 0, 0, *args, None, 0, None) == -1
+    assert lib.pauli_decompose_batched(2, 0, 0, *args, None, 0, None) == -2  # no workspace
+    assert lib.pauli_decompose_batched(2, 0, 1 << 6, *args, P(3), 1 << 20, None) == -1  # adjoint: reconstruct only
+    plan = ctypes.c_void_p()
+    assert lib.ptd_batch_plan_create(2, 0, 1 << 6, *args, ctypes.byref(plan)) == -1
+    assert lib.ptd_batch_plan_launch(None, None) == -1
+    lib.ptd_batch_plan_destroy(None)

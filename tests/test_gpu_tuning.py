@@ -1,0 +1,55 @@
+"""Autotuner: candidates admitted only when bit-identical on integer input;
+the chosen setting is used by pauli_decompose afterwards."""
+import numpy as np
+import pytest
+
+import synth
+from tests.helpers import rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ptd():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_11644_amd as p
+
+    return p
+
+
+@pytest.mark.parametrize("code,hermitian", [(0, False), (1, False), (1, True)])
+def test_autotune_n11(ptd, oracle_mod, tmp_path, monkeypatch, code, hermitian):
+    import ctypes
+
+    from paper_2403_11644_amd import _native, tuning
+
+    monkeypatch.setenv("PTD_AUTOTUNE_CACHE", str(tmp_path / "t.json"))
+    L = _native.lib()
+    L.ptd_clear_tuning()
+    n = 11
+    re, im = synth.gaussian_int(n, seed=1) if not hermitian else synth.gaussian_int_hermitian(n, seed=1)
+    dt = np.complex128 if code == 0 else np.complex64
+    A = to_dev(synth.int_to_complex(re, im, dt))
+    before = to_host(ptd.decompose(A, hermitian=hermitian))
+    rec = tuning.autotune(n, code, hermitian=hermitian, reps=2)
+    assert rec["admitted"] >= 1 and rec["candidates"] >= rec["admitted"]
+    cfg, la = ctypes.c_int(), ctypes.c_int()
+    assert L.ptd_get_tuning(n, code, 1 if hermitian else 0, ctypes.byref(cfg), ctypes.byref(la)) == 1
+    assert (cfg.value, la.value) == (rec["cfg"], rec["lookahead"])
+    after = to_host(ptd.decompose(A, hermitian=hermitian))
+    np.testing.assert_array_equal(after, before)
+    # cache round trip
+    L.ptd_clear_tuning()
+    assert tuning.load() == 1
+    assert L.ptd_get_tuning(n, code, 1 if hermitian else 0, ctypes.byref(cfg), ctypes.byref(la)) == 1
+    L.ptd_clear_tuning()
+    # float input through the tuned setting stays within the bar
+    L.ptd_set_tuning(n, code, 1 if hermitian else 0, rec["cfg"], rec["lookahead"])
+    Af = synth.dense(n, seed=2, dtype=dt)
+    got = to_host(ptd.decompose(to_dev(Af)))
+    xs, zs = synth.sample_strings(n, 2000, seed=4)
+    assert rel_err(got[xs, zs], oracle_mod.coeffs(Af, xs, zs)) <= (1e-12 if code == 0 else 1e-5)
+    L.ptd_clear_tuning()
