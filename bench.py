@@ -13,7 +13,8 @@ Prints ONE JSON line.  Besides the contract fields it carries:
                 c once (32 B per coefficient for complex128)
   cpu_baseline  the oracle on this host's cores, on a bounded sample
   legs          complex64 (with its error against the float64 oracle), the
-                two-pass schedule, n = 13 Hermitian, n = 14 banded skip vs
+                two-pass schedule, n = 13 Hermitian (float64 and float32
+                output), n = 14 banded skip vs
                 dense, n = 15 compensated complex64, and the 4096-matrix
                 batched plan against per-matrix calls
 """
@@ -54,6 +55,57 @@ def _traffic(kernel: str, key: str):
     return rec.get("bytes_per_launch")
 
 
+def _herm_bytes(n: int, elem: int) -> float:
+    """Bytes a Hermitian decomposition must move: for n >= 5 one element of
+    each mirrored pair (r, c), (c, r) of A (half the matrix; the kernels read
+    the diagonal blocks whole) and the real output; for n <= 4 all of A."""
+    coef = 4.0 ** n
+    return coef * (elem / 2 if n >= 5 else elem) + coef * elem / 2
+
+
+def _counter_means(folder: str, counter: str) -> dict:
+    """Mean value per kernel of one counter in a rocprofv3 --pmc CSV folder."""
+    import csv
+    import glob
+
+    vals: dict = {}
+    for f in glob.glob(os.path.join(folder, "*counter_collection.csv")):
+        for r in csv.DictReader(open(f)):
+            if r.get("Counter_Name") != counter:
+                continue
+            nm = r["Kernel_Name"]
+            key = "k_fused_fwd" if "k_fused_fwd" in nm else ("k_copy16" if "k_copy16" in nm else None)
+            if key:
+                vals.setdefault(key, []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in vals.items()}
+
+
+def write_traffic(fetch_dir: str, write_dir: str, n: int) -> dict:
+    """profiles/traffic.json from two rocprofv3 counter runs of
+    `bench.py --legs copy` (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).
+    Each counter is scaled by what it reads for the reference copy, which
+    reads and writes the 2^n x 2^n complex128 matrix once each."""
+    fetch = _counter_means(fetch_dir, "FETCH_SIZE")
+    write = _counter_means(write_dir, "WRITE_SIZE")
+    mat_bytes = 16.0 * 4.0 ** n
+    fs = mat_bytes / (fetch["k_copy16"] * 1024.0)
+    ws = mat_bytes / (write["k_copy16"] * 1024.0)
+    fb = fetch["k_fused_fwd"] * 1024.0 * fs
+    wb = write["k_fused_fwd"] * 1024.0 * ws
+    rec = {"kernel_hash": _kernel_hash(), "bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
+           "fetch_scale": round(fs, 4), "write_scale": round(ws, 4), "algorithmic_bytes": 2 * mat_bytes,
+           "ratio_to_algorithmic": round((fb + wb) / (2 * mat_bytes), 3)}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        data = json.load(open(path))
+    except (OSError, ValueError):
+        data = {}
+    data["k_fused_fwd/n%d/c128" % n] = rec
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1)
+    return rec
+
+
 def _time(fn, steps: int, warmup: int, stream) -> float:
     import torch
 
@@ -85,7 +137,13 @@ def main() -> int:
                     help="comma list of reported legs to run: complex64, two_pass, copy, hermitian, band, n15, "
                          "batched; 'all' or 'none'")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc folders (FETCH_SIZE, WRITE_SIZE) "
+                         "of a '--legs copy' run, then exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        print(json.dumps(write_traffic(args.traffic_from[0], args.traffic_from[1], args.n)))
+        return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build measures one GPU only. The decomposition shards by X-pattern group "
@@ -185,9 +243,20 @@ def main() -> int:
         del B
         hout = torch.empty((1 << 13, 1 << 13), dtype=torch.float64, device=dev)
         msh = _time(lambda: ptd.decompose(H, hermitian=True, out=hout), 10, 3, stream)
+        # bytes the method needs: one element of each mirrored pair of A (half
+        # of it) plus the real output
         legs["hermitian_n13_f64"] = {"ms": round(msh, 4), "GCoeff_s": round(4.0 ** 13 / msh / 1e6, 2),
-                                     "path_hbm_frac": round(24 * 4.0 ** 13 / (msh * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+                                     "path_hbm_frac": round(_herm_bytes(13, 16) / (msh * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                                                            4)}
+        H32 = H.to(torch.complex64)
         del H, hout
+        hout32 = torch.empty((1 << 13, 1 << 13), dtype=torch.float32, device=dev)
+        msh32 = _time(lambda: ptd.decompose(H32, hermitian=True, out=hout32), 10, 3, stream)
+        legs["hermitian_n13_f32"] = {"ms": round(msh32, 4), "GCoeff_s": round(4.0 ** 13 / msh32 / 1e6, 2),
+                                     "path_hbm_frac": round(_herm_bytes(13, 8) / (msh32 * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                                                            4),
+                                     "speedup_vs_f64": round(msh / msh32, 2)}
+        del H32, hout32
     if "band" in want_legs:
         # n = 14 complex band, half-bandwidth 8: skip path from bands vs dense
         band = synth.banded_complex(n, 8, seed=2)
@@ -235,9 +304,10 @@ def main() -> int:
         msm = _time(per_matrix, 2, 1, stream)
         plan.close()
         tot = float(sizes.sum())
+        hb = sum(_herm_bytes(int(k), 8) for k in ns)
         legs["batched_4096_herm_c64"] = {"plan_ms": round(msp, 4), "per_matrix_ms": round(msm, 4),
                                          "speedup": round(msm / msp, 2), "GCoeff_s": round(tot / msp / 1e6, 2),
-                                         "path_hbm_frac": round(12 * tot / (msp * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                                         "path_hbm_frac": round(hb / (msp * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
                                          "coefficients": int(tot)}
         del bbuf, bout2, mats, outs
         torch.cuda.empty_cache()

@@ -54,8 +54,11 @@ typedef void *ptd_stream;
 /* Flags (bitwise OR). */
 /* A is Hermitian (Theorem 2: real coefficients).  The output is REAL: doubles
  * for PTD_C128, floats for PTD_C64, one per string.  The caller guarantees
- * A == A^*; the kernels read the whole matrix and drop the imaginary part,
- * which is exactly zero in their butterfly network. */
+ * A == A^* exactly: the dense kernels may read only one element of a
+ * mirrored pair (r, c), (c, r) and take the other as its conjugate (for
+ * n = 5..14 about half the matrix is read), so for a non-Hermitian A the
+ * result is unspecified.  The imaginary part dropped is exactly zero in the
+ * butterfly network. */
 #define PTD_HERMITIAN (1u << 0)
 /* A is diagonal (Sec. IV-A, diagonal matrices): only x = 0 can be nonzero. */
 #define PTD_DIAGONAL (1u << 1)
@@ -188,8 +191,9 @@ ptd_status ptd_parseval_residual(int n, ptd_dtype dtype, unsigned flags, const v
 /*
  * Autotuning of the dense single-launch schedule (n = 11..15, complex64 and
  * complex128 for n <= 14, flags 0 or PTD_HERMITIAN).  ptd_autotune times the
- * candidate settings (workgroup shape, gather cache policy, item prefetch,
- * completion signalling, queue lookahead) at this (n, dtype, Hermitian)
+ * candidate settings (workgroup shape, cache policies of the gathers, the
+ * final stores and the re-read partial results, queue lookahead) at this
+ * (n, dtype, Hermitian)
  * point on device buffers it allocates itself, admits a candidate only if
  * its output on a Gaussian-integer matrix equals the default setting's bit
  * for bit, records the fastest in a process-wide registry that

@@ -48,7 +48,6 @@ bool use_fused(int n, ptd_dtype dt, unsigned flags)
     return true;
 }
 
-constexpr int kFusedLookahead = 3;
 
 }  // namespace
 
@@ -140,7 +139,7 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
     if (flags & PTD_COMPENSATED) return hip_status(ptd::launch_dense_fwd_comp(n, herm, A, lda, coeff, st));
     if (use_fused(n, dtype, flags)) {
         if (!ws) return PTD_ENOSPC;
-        ptd::FusedTuning t{0, kFusedLookahead};
+        ptd::FusedTuning t = ptd::fused_default(n, dtype, herm);
         (void)ptd::get_fused_tuning(n, dtype, herm, &t);
         return hip_status(ptd::launch_fused_fwd(n, dtype, herm, A, lda, coeff, ws, t.la, t.cfg, st));
     }
@@ -337,7 +336,8 @@ ptd_status ptd_set_tuning(int n, ptd_dtype dtype, unsigned flags, int cfg, int l
 int ptd_get_tuning(int n, ptd_dtype dtype, unsigned flags, int* cfg, int* lookahead)
 {
     if (!valid_dtype(dtype) || (flags & ~PTD_HERMITIAN) || !cfg || !lookahead) return PTD_EINVAL;
-    ptd::FusedTuning t{0, kFusedLookahead};
+    ptd::FusedTuning t = use_fused(n, dtype, flags) ? ptd::fused_default(n, dtype, flags & PTD_HERMITIAN)
+                                                    : ptd::FusedTuning{0, 0};
     const bool tuned = ptd::get_fused_tuning(n, dtype, flags & PTD_HERMITIAN, &t);
     *cfg = t.cfg;
     *lookahead = t.la;
@@ -354,7 +354,7 @@ ptd_status ptd_autotune(int n, ptd_dtype dtype, unsigned flags, int reps, ptd_st
         return PTD_EINVAL;
     if (n < 1 || n > 16) return PTD_EINVAL;
     if (!use_fused(n, dtype, flags)) return PTD_EUNSUP;
-    ptd::FusedTuning best{0, kFusedLookahead};
+    ptd::FusedTuning best = ptd::fused_default(n, dtype, flags & PTD_HERMITIAN);
     hipError_t e = ptd::autotune_fused(n, dtype, flags & PTD_HERMITIAN, reps, (hipStream_t)stream, &best, ms, tried,
                                        admitted);
     if (e != hipSuccess) return hip_status(e);

@@ -1,8 +1,8 @@
 // autotune.hip -- measured choice of the single-launch schedule's parameters.
 //
-// The persistent dense kernel (fused.hip) has a shape (threads per
-// workgroup, rows per phase-1 item, X-patterns per group), an option for
-// non-temporal gathers, item prefetch, deferred completion signals, and the
+// The persistent dense kernel (fused.hpp) has a shape (threads per
+// workgroup, rows per phase-1 item, X-patterns per group), cache-policy
+// options (non-temporal gathers, final stores, phase-2 loads) and the
 // lookahead of its queues.  ptd_autotune times candidate settings at one
 // (n, dtype, Hermitian) point and records the fastest in a registry that
 // pauli_decompose reads.  A candidate is admitted only if its output on a
@@ -137,7 +137,7 @@ hipError_t autotune_fused(int n, ptd_dtype dt, bool herm, int reps, hipStream_t 
     const int shapes[] = {2, 1, 3};
     for (int sh : shapes) {
         if (n == 15 && sh != 1) continue;
-        for (int opt : {4 | 16, 16, 4, 4 | 8 | 16})
+        for (int opt : {4, 0, 4 | 8, 4 | 16, 4 | 8 | 16})
             for (int la : {1, 2, 3, 4, 6}) cands.push_back(FusedTuning{sh | opt, la});
     }
     hipEvent_t e0, e1;

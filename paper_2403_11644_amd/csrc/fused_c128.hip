@@ -1,0 +1,13 @@
+// fused_c128.hip -- complex128 instantiations of the single-launch
+// schedule (fused.hpp), in a translation unit of their own so they compile
+// in parallel with the others.
+#include "fused.hpp"
+
+namespace ptd {
+
+hipError_t fused_launch_c128(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg, hipStream_t st)
+{
+    return fused::fused_dispatch<double, false>(n, A, lda, out, ws, la, cfg, st);
+}
+
+}  // namespace ptd

@@ -1,0 +1,13 @@
+// fused_c64h.hip -- Hermitian complex64 instantiations of the single-launch
+// schedule (fused.hpp), in a translation unit of their own so they compile
+// in parallel with the others.
+#include "fused.hpp"
+
+namespace ptd {
+
+hipError_t fused_launch_c64_herm(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg, hipStream_t st)
+{
+    return fused::fused_dispatch<float, true>(n, A, lda, out, ws, la, cfg, st);
+}
+
+}  // namespace ptd

@@ -32,6 +32,38 @@ constexpr int group_lds_elems(int logn)
     return (1 << group_logt<V>(logn)) * ((1 << logn) + 1);
 }
 
+// First radix-16 round (index bits 0..3) for Hermitian input, group base
+// xg with xh = xg >> 4 != 0.  Position blocks B and B ^ xh of 16 rows hold
+// mirror entries, d_x[k ^ x] = conj(d_x[k]), so for c = x & 15 the round
+// outputs obey W0[B ^ xh][u] = (-1)^popcount(u & c) conj(W0[B][u]) exactly
+// (each radix-2 stage only swaps and negates under an XOR-permuted input).
+// Only the blocks whose bit hb (the top bit of xh) is clear are gathered;
+// each writes its own outputs and its mirror block's.
+template <class V, int LOGN, int LOGT, class G, class W>
+__device__ __forceinline__ void first_round_hermitian(const G& gather, const W& lw, uint32_t xg)
+{
+    constexpr int NT = GROUP_THREADS;
+    constexpr int NITEMS = (1 << LOGT) << (LOGN - 5);  // half of the (vector, block) pairs
+    const int xh = (int)(xg >> 4);
+    const int hb = 31 - __clz(xh);
+    for (int it = threadIdx.x; it < NITEMS; it += NT) {
+        const int vec = it & ((1 << LOGT) - 1);
+        const int base = insert_zero_bits(it >> LOGT, hb, 1) << 4;
+        const int c = (int)((xg | (uint32_t)vec) & 15u);
+        const int basep = base ^ (xh << 4);
+        V re[16], im[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) gather(vec, base + m, re[m], im[m]);
+        wht_reg<V, 4>(re, im);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            lw(vec, base + u, re[u], im[u]);
+            const bool s = __popc(u & c) & 1;
+            lw(vec, basep + u, s ? -re[u] : re[u], s ? im[u] : -im[u]);
+        }
+    }
+}
+
 template <class V, int LOGN, int LOGT, bool REAL_OUT>
 __device__ __forceinline__ void group_fwd(const cplx<V>* __restrict__ A, int64_t lda, void* __restrict__ out,
                                           int64_t ldo, int g, cplx<V>* lds)
@@ -62,16 +94,23 @@ __device__ __forceinline__ void group_fwd(const cplx<V>* __restrict__ A, int64_t
     LdsVecsW<V, LOGN> lw{lds};
     if constexpr (LOGN <= 4) {
         wht_round<V, LOGT, LOGN, 0, LOGN, NT, true>(gather, store);
-    } else if constexpr (LOGN <= 8) {
-        wht_round<V, LOGT, LOGN, 0, 4, NT, true>(gather, lw);
-        __syncthreads();
-        wht_round<V, LOGT, LOGN, 4, LOGN - 4, NT, false>(lr, store);
     } else {
-        wht_round<V, LOGT, LOGN, 0, 4, NT, true>(gather, lw);
+        if constexpr (REAL_OUT) {
+            if ((xg >> 4) != 0)
+                first_round_hermitian<V, LOGN, LOGT>(gather, lw, xg);
+            else
+                wht_round<V, LOGT, LOGN, 0, 4, NT, true>(gather, lw);
+        } else {
+            wht_round<V, LOGT, LOGN, 0, 4, NT, true>(gather, lw);
+        }
         __syncthreads();
-        wht_round<V, LOGT, LOGN, 4, 4, NT, false>(lr, lw);
-        __syncthreads();
-        wht_round<V, LOGT, LOGN, 8, LOGN - 8, NT, false>(lr, store);
+        if constexpr (LOGN <= 8) {
+            wht_round<V, LOGT, LOGN, 4, LOGN - 4, NT, false>(lr, store);
+        } else {
+            wht_round<V, LOGT, LOGN, 4, 4, NT, false>(lr, lw);
+            __syncthreads();
+            wht_round<V, LOGT, LOGN, 8, LOGN - 8, NT, false>(lr, store);
+        }
     }
 }
 

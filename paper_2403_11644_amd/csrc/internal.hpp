@@ -32,28 +32,44 @@ hipError_t launch_dense_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const 
 hipError_t launch_structured(int n, ptd_dtype dt, bool herm, bool bands, bool compact, int s, int count,
                              const void* A, int64_t lda, void* out, hipStream_t st);
 
-// Single-launch dense decompose for n = 11..15 (fused.hip); ws holds
+// Single-launch dense decompose for n = 11..15 (fused.hpp); ws holds
 // fused_workspace_bytes() bytes of queue and group counters; la = lookahead.
 size_t fused_workspace_bytes(int n, ptd_dtype dt);
-// cfg 0 = default shape; see fused.hip for the others.
+// cfg 0 = default shape; see fused.hpp for the others.
 hipError_t launch_fused_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out, void* ws, int la,
                             int cfg, hipStream_t st);
+// Per-dtype instantiations of the single-launch schedule (fused_*.hip).
+hipError_t fused_launch_c64(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg,
+                            hipStream_t st);
+hipError_t fused_launch_c128(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg,
+                             hipStream_t st);
+hipError_t fused_launch_c64_herm(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg,
+                                 hipStream_t st);
+hipError_t fused_launch_c128_herm(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg,
+                                  hipStream_t st);
+// Zero `count` uint32 words with a small kernel (capturable, unlike a memset node).
+hipError_t launch_zero_words(uint32_t* p, int count, hipStream_t st);
 // Plain 16-byte-per-lane device copy (bandwidth reference).
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 
 // Tuned settings of the single-launch schedule (autotune.hip).
 struct FusedTuning {
-    int cfg;  // shape and options, see fused.hip (0 = default)
+    int cfg;  // shape and options, see fused.hpp (0 = default)
     int la;   // queue lookahead in groups
 };
+// Default setting at (n, dtype, Hermitian) (fused.hip); cfg = 0 in a call
+// stands for its cfg.
+FusedTuning fused_default(int n, ptd_dtype dt, bool herm);
 bool get_fused_tuning(int n, ptd_dtype dt, bool herm, FusedTuning* t);
 void set_fused_tuning(int n, ptd_dtype dt, bool herm, const FusedTuning& t);
 void clear_fused_tuning();
 hipError_t autotune_fused(int n, ptd_dtype dt, bool herm, int reps, hipStream_t st, FusedTuning* best, float* best_ms,
                           int* tried, int* admitted);
 
-// Compute units of the current device (256 on MI355X).
+// Compute units of the current device (256 on MI355X) and its XCD count
+// (32 compute units per XCD; partitioned modes expose fewer).
 int device_cu_count();
+int device_xcd_count();
 
 // Batched single-pass launches over (matrix, group) items, n <= 10 each.
 int64_t batched_item_count(int count, ptd_dtype dt, const int32_t* n_host);

@@ -96,7 +96,7 @@ def test_dense_integer_exact(ptd, oracle_mod, dt, n, path):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("n,path", [(5, 1), (10, 1), (8, 2), (11, 2)])
+@pytest.mark.parametrize("n,path", [(4, 1), (5, 1), (7, 1), (8, 1), (10, 1), (8, 2), (11, 2)])
 def test_hermitian_integer_exact(ptd, oracle_mod, dt, n, path):
     from paper_2403_11644_amd import api
 
@@ -233,8 +233,10 @@ def _fused(A, hermitian=False, lookahead=1, cfg=0):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("n,la,cfg", [(11, 1, 0), (11, 3, 1), (11, 2, 3), (12, 2, 7), (12, 4, 14), (13, 1, 1),
-                                      (13, 4, 0), (13, 2, 3)])
+# cfg: shape in bits 0-1, then non-temporal gathers (4), final stores (8),
+# phase-2 loads (16)
+@pytest.mark.parametrize("n,la,cfg", [(11, 1, 0), (11, 3, 1), (11, 2, 3), (12, 2, 7), (12, 4, 14), (12, 3, 17),
+                                      (13, 1, 1), (13, 4, 0), (13, 2, 3), (13, 2, 30), (13, 3, 25)])
 def test_fused_vs_oracle(ptd, oracle_mod, dt, n, la, cfg):
     A = synth.dense(n, seed=500 + n, dtype=_np_dtype(dt))
     got = to_host(_fused(to_dev(A), lookahead=la, cfg=cfg))
@@ -267,7 +269,8 @@ def test_fused_integer_exact(ptd, oracle_mod, dt, n):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("n,cfg", [(11, 0), (11, 3), (13, 0), (13, 1), (14, 0), (14, 7)])
+@pytest.mark.parametrize("n,cfg", [(11, 0), (11, 3), (12, 26), (13, 0), (13, 1), (13, 31), (14, 0), (14, 7),
+                                   (14, 22)])
 def test_fused_hermitian(ptd, oracle_mod, dt, n, cfg):
     re, im = synth.gaussian_int_hermitian(n, seed=1)
     A = to_dev(synth.int_to_complex(re, im, _np_dtype(dt)))
