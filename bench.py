@@ -13,7 +13,8 @@ Prints ONE JSON line.  Besides the contract fields it carries:
                 c once (32 B per coefficient for complex128)
   cpu_baseline  the oracle on this host's cores, on a bounded sample
   legs          complex64 (with its error against the float64 oracle), the
-                two-pass schedule, n = 13 Hermitian (float64 and float32
+                two-pass schedule, the reconstruction A = sum_P c_P P and
+                the float64 Parseval reductions, n = 13 Hermitian (float64 and float32
                 output), n = 14 banded skip vs
                 dense, n = 15 compensated complex64, and the 4096-matrix
                 batched plan against per-matrix calls
@@ -134,8 +135,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=14)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="all",
-                    help="comma list of reported legs to run: complex64, two_pass, copy, hermitian, band, n15, "
-                         "batched; 'all' or 'none'")
+                    help="comma list of reported legs to run: complex64, two_pass, copy, reconstruct, parseval, "
+                         "hermitian, band, n15, batched; 'all' or 'none'")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc folders (FETCH_SIZE, WRITE_SIZE) "
@@ -194,9 +195,28 @@ def main() -> int:
     legs = {}
     want_legs = set()
     if args.legs == "all":
-        want_legs = {"complex64", "two_pass", "copy", "hermitian", "band", "n15", "batched"}
+        want_legs = {"complex64", "two_pass", "copy", "reconstruct", "parseval", "hermitian", "band", "n15",
+                     "batched"}
     elif args.legs != "none":
         want_legs = set(args.legs.split(","))
+    if "reconstruct" in want_legs:
+        # A = sum_P c_P P from the coefficients just computed (the adjoint
+        # path of autograd); checked against the input on sampled entries
+        rec = torch.empty_like(A)
+        msr = _time(lambda: ptd.reconstruct(out128, out=rec), 10, 3, stream)
+        ptd.reconstruct(out128, out=rec)
+        torch.cuda.synchronize()
+        rerr = _rel(rec[ix, iz].cpu().numpy(), A_host[xs, zs])
+        legs["reconstruct_f64"] = {"ms": round(msr, 4), "GCoeff_s": round(ncoef / msr / 1e6, 2),
+                                   "path_hbm_frac": round(32 * ncoef / (msr * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                                   "err_rel_sampled_entries": rerr}
+        del rec
+    if "parseval" in want_legs:
+        # float64 residual reductions: ||A||_F^2 and 2^n sum |c|^2 (reads A
+        # and c once each, then one 48-byte copy to the host)
+        msp_ = _time(lambda: ptd.parseval(A, out128), 10, 3, stream)
+        legs["parseval_f64"] = {"ms": round(msp_, 4),
+                                "path_hbm_frac": round(32 * ncoef / (msp_ * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
     if "complex64" in want_legs:
         # complex64 cast of the same matrix (cast excluded from the time)
         A64 = A.to(torch.complex64)

@@ -88,10 +88,15 @@ typedef void *ptd_stream;
 /* ptd_batch_plan_create only: the plan reconstructs (coefficients -> matrices). */
 #define PTD_PLAN_RECONSTRUCT (1u << 7)
 
-/* Workspace (device bytes) a pauli_decompose / pauli_reconstruct call with
- * these arguments needs: a few KiB of queue counters for dense decompositions
- * with n = 11..15 (one persistent launch), 0 otherwise.  Host-only, pure. */
+/* Workspace (device bytes) a pauli_decompose call with these arguments
+ * needs: a few KiB of queue counters for dense decompositions with
+ * n = 11..15 (one persistent launch), 0 otherwise.  Host-only, pure. */
 size_t ptd_workspace_bytes(int n, ptd_dtype dtype, unsigned flags, int s);
+
+/* Workspace (device bytes) a pauli_reconstruct call with these arguments
+ * needs: a few KiB of queue counters for n = 11..14 (one persistent launch),
+ * 0 otherwise; 0 for bad arguments.  Host-only, pure. */
+size_t ptd_reconstruct_workspace_bytes(int n, ptd_dtype dtype, unsigned flags);
 
 /* Number of X-patterns x that can carry a nonzero coefficient: 2^n for a
  * dense matrix, 1 for PTD_DIAGONAL, and for PTD_BANDED
@@ -131,8 +136,12 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
  *
  *   coeff    dense [x][z] coefficients (complex of dtype; real with
  *            PTD_HERMITIAN, giving a Hermitian A)
- *   A, lda   output matrix, lda >= 2^n; all 4^n entries are written
+ *   A, lda   output matrix, lda >= 2^n; all 4^n entries are written (for
+ *            n = 11..14 A also holds the intermediate transform, so coeff
+ *            must not overlap it)
  *   flags    PTD_HERMITIAN | PTD_ADJOINT
+ *   ws       ptd_reconstruct_workspace_bytes() device bytes (NULL when 0);
+ *            PTD_ENOSPC if smaller
  */
 ptd_status pauli_reconstruct(int n, ptd_dtype dtype, unsigned flags, const void *coeff, void *A,
                              int64_t lda, void *ws, size_t ws_bytes, ptd_stream stream);

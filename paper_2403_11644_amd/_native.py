@@ -25,6 +25,7 @@ SZ = ctypes.c_size_t
 # name -> (restype, argtypes); mirrors include/ptd.h
 SIGNATURES = {
     "ptd_workspace_bytes": (SZ, [I, I, U, I]),
+    "ptd_reconstruct_workspace_bytes": (SZ, [I, I, U]),
     "ptd_num_nonempty_x": (I, [I, U, I]),
     "ptd_nonempty_x": (I, [I, U, I, P]),
     "pauli_decompose": (I, [I, I, U, I, P, I64, P, P, SZ, P]),

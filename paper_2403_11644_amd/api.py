@@ -194,8 +194,10 @@ def reconstruct(c: torch.Tensor, *, hermitian: bool = False, adjoint: bool = Fal
     elif out.dim() != 2 or out.shape != (N, N) or out.dtype != adt or out.stride(1) != 1:
         raise ValueError("out must be a (2^n, 2^n) %s tensor with contiguous rows" % adt)
     L = _native.lib()
-    st = L.pauli_reconstruct(n, code, flags, _ptr(c), _ptr(out), out.stride(0), None, 0,
-                             _stream_handle(c.device, stream))
+    wsb = L.ptd_reconstruct_workspace_bytes(n, code, flags)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=c.device) if wsb else None
+    st = L.pauli_reconstruct(n, code, flags, _ptr(c), _ptr(out), out.stride(0),
+                             _ptr(ws) if ws is not None else None, wsb, _stream_handle(c.device, stream))
     _native.check(st, "pauli_reconstruct")
     return out
 

@@ -40,6 +40,9 @@ ptd_status check_structure(int n, unsigned flags, int s)
 // except at n = 15 for complex128 or Hermitian input (the 32-point row
 // transform is built for complex64 values only); those and n = 16 use the
 // two-pass schedule.
+// Dense reconstruction for n = 11..14 runs in one launch (fused.hpp).
+bool use_fused_rec(int n) { return n >= 11 && n <= 14; }
+
 bool use_fused(int n, ptd_dtype dt, unsigned flags)
 {
     if (flags & (PTD_DIAGONAL | PTD_BANDED | PTD_COMPENSATED)) return false;
@@ -146,17 +149,27 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
     return hip_status(ptd::launch_dense_fwd(n, dtype, herm, A, lda, coeff, 0, st));
 }
 
+size_t ptd_reconstruct_workspace_bytes(int n, ptd_dtype dtype, unsigned flags)
+{
+    if (n < 1 || n > 16 || !valid_dtype(dtype) || (flags & ~(PTD_HERMITIAN | PTD_ADJOINT))) return 0;
+    return use_fused_rec(n) ? ptd::fused_workspace_bytes(n, dtype) : 0;
+}
+
 ptd_status pauli_reconstruct(int n, ptd_dtype dtype, unsigned flags, const void* coeff, void* A, int64_t lda,
                              void* ws, size_t ws_bytes, ptd_stream stream)
 {
     if (n < 1 || n > 16 || !valid_dtype(dtype) || !A || !coeff) return PTD_EINVAL;
     if (flags & ~(PTD_HERMITIAN | PTD_ADJOINT)) return PTD_EINVAL;
     if (lda < ((int64_t)1 << n)) return PTD_EINVAL;
-    if (ws_bytes < ptd_workspace_bytes(n, dtype, flags, 0)) return PTD_ENOSPC;
-    (void)ws;
     if (A == coeff) return PTD_EINVAL;
-    return hip_status(ptd::launch_dense_rec(n, dtype, flags & PTD_HERMITIAN, flags & PTD_ADJOINT, coeff, A, lda, 0,
-                                            (hipStream_t)stream));
+    const bool herm = flags & PTD_HERMITIAN, adj = flags & PTD_ADJOINT;
+    if (use_fused_rec(n)) {
+        if (!ws || ws_bytes < ptd_reconstruct_workspace_bytes(n, dtype, flags)) return PTD_ENOSPC;
+        // lookahead as measured on MI355X: the forward's at n <= 13, 4 at 14
+        const int la = n == 14 ? 4 : ptd::fused_default(n, dtype, herm).la;
+        return hip_status(ptd::launch_fused_rec(n, dtype, herm, adj, coeff, A, lda, ws, la, (hipStream_t)stream));
+    }
+    return hip_status(ptd::launch_dense_rec(n, dtype, herm, adj, coeff, A, lda, 0, (hipStream_t)stream));
 }
 
 size_t ptd_reduce_workspace_bytes(void) { return ptd::reduce_workspace_bytes(); }

@@ -92,6 +92,17 @@ hipError_t launch_fused_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64
                 : fused_launch_c64(n, A, lda, out, ws, la, cfg, st);
 }
 
+hipError_t launch_fused_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const void* coeff, void* A, int64_t lda,
+                            void* ws, int la, hipStream_t st)
+{
+    if (n < 11 || n > 14 || la < 1) return hipErrorInvalidValue;
+    if (dt == PTD_C128)
+        return herm ? fused_rec_c128_herm(n, coeff, A, lda, ws, la, adjoint, st)
+                    : fused_rec_c128(n, coeff, A, lda, ws, la, adjoint, st);
+    return herm ? fused_rec_c64_herm(n, coeff, A, lda, ws, la, adjoint, st)
+                : fused_rec_c64(n, coeff, A, lda, ws, la, adjoint, st);
+}
+
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st)
 {
     const int64_t count = (int64_t)(bytes / 16);

@@ -217,8 +217,10 @@ struct Shape {
 };
 
 // Phase-1 rounds over bits [B0, KAP): radix-16 steps, the first gathering
-// from A (vector index fastest across lanes), the last storing.
-template <class V, class S, int B0, class G, class St>
+// from A (vector index fastest across lanes), the last storing (positions
+// fastest across lanes for contiguous output rows, or with VEC_LAST the
+// vector index fastest, for stores into the band's row segments).
+template <class V, class S, int B0, bool VEC_LAST = false, class G, class St>
 __device__ __forceinline__ void p1_rounds(const G& gather, const St& store, cplx<V>* lds)
 {
     constexpr int KAP = S::KAP, LOGT = S::LOGT, NT = S::NT;
@@ -231,13 +233,13 @@ __device__ __forceinline__ void p1_rounds(const G& gather, const St& store, cplx
     } else if constexpr (FIRST) {
         wht_round<V, LOGT, KAP, B0, NB, NT, true>(gather, lw);
         __syncthreads();
-        p1_rounds<V, S, B0 + NB>(gather, store, lds);
+        p1_rounds<V, S, B0 + NB, VEC_LAST>(gather, store, lds);
     } else if constexpr (LAST) {
-        wht_round<V, LOGT, KAP, B0, NB, NT, false>(lr, store);
+        wht_round<V, LOGT, KAP, B0, NB, NT, VEC_LAST>(lr, store);
     } else {
         wht_round<V, LOGT, KAP, B0, NB, NT, false>(lr, lw);
         __syncthreads();
-        p1_rounds<V, S, B0 + NB>(gather, store, lds);
+        p1_rounds<V, S, B0 + NB, VEC_LAST>(gather, store, lds);
     }
 }
 
@@ -493,6 +495,221 @@ __global__ __launch_bounds__(S::NT, 4) void k_fused_fwd(const cplx<V>* __restric
     __syncthreads();
     if (!s_last) return;
     for (int qq = 0; qq < Q; ++qq) drain(qq);
+}
+
+// ------------------------------------------------------------------------
+// Reconstruction, the same schedule run backwards.  For X-pattern x,
+// d_x = WHT( (-i)^popcount(x&z) c[x][z] ) over z, and A[k][k ^ x] = d_x[k]
+// (times 2^-n for the adjoint).  The group's band of A (one 128-byte
+// segment per row) holds the intermediate: slot x_lo of row k's segment.
+//
+//   phase R1, item (g, s):  coefficient columns z_lo in [s Z, (s+1) Z) of
+//       the group's T rows: inverse phase, the WHT over the high bits (the
+//       row-block index j of k = j K + z_lo) in registers, then a transpose
+//       through LDS so that lanes over x_lo store whole segments
+//       A[j K + z_lo][seg + x_lo];
+//   phase R2, item (g, b):  rows k in [b K, (b+1) K) of the band: the low
+//       KAP WHT bits in registers and LDS, and d_x[k] stored to A[k][k ^ x]
+//       (the same segment, slots permuted), in place.
+//
+// R2 items of a group wait for all its R1 items (counter per group), as in
+// the forward launch.
+
+template <class V, class S>
+struct RecShape {
+    static constexpr bool SW = S::SWAP;
+    static constexpr int NBL = SW ? S::NB2 - 1 : S::NB2;
+    static constexpr int NL = 1 << NBL;                     // values per thread
+    static constexpr int PAIRS = SW ? S::NT / 2 : S::NT;  // (x_lo, z_lo) pairs per item
+    static constexpr int T = 1 << S::LOGT;
+    static constexpr int ZR = PAIRS / T;                  // z_lo columns per R1 item
+    static constexpr int NR1 = (1 << S::KAP) / ZR;        // R1 items per group
+    static constexpr int NR2 = 1 << (S::LOGN - S::KAP);   // R2 items per group
+    static constexpr int H = SW ? 2 : 1;
+    // values per thread moved through LDS per transpose round
+    static constexpr int RB_FIT = ((1 << S::KAP) + 1) / (H * (ZR + 1));
+    static constexpr int RB = RB_FIT >= 16 ? 16 : RB_FIT >= 8 ? 8 : RB_FIT >= 4 ? 4 : RB_FIT >= 2 ? 2 : 1;
+    static constexpr int RBU = RB < NL ? RB : NL;
+    static_assert(ZR >= 1 && (1 << S::KAP) % ZR == 0, "R1 items tile the row block");
+    static_assert(H * RBU * T * (ZR + 1) <= T * ((1 << S::KAP) + 1), "transpose fits the LDS of phase 1");
+};
+
+template <class V, class S, bool REAL_IN>
+__device__ __forceinline__ void rec_phase1(const void* __restrict__ coeff, cplx<V>* __restrict__ A, int64_t lda,
+                                           int g, int sub, cplx<V>* lds)
+{
+    typedef RecShape<V, S> R;
+    constexpr int KAP = S::KAP, LOGT = S::LOGT, T = R::T, ZR = R::ZR, NBL = R::NBL, NL = R::NL;
+    constexpr int N = 1 << S::LOGN;
+    const int lane = (int)(threadIdx.x & 63);
+    const int jh = R::SW ? (lane >> 5) : 0;
+    const int p = R::SW ? (((int)threadIdx.x >> 6) << 5) | (lane & 31) : (int)threadIdx.x;
+    const uint32_t xg = (uint32_t)g << LOGT;
+    const int z0 = sub * ZR;
+    // load side: z_lo fastest across lanes (contiguous coefficient runs)
+    const int xl = p / ZR, zl = p % ZR;
+    const uint32_t x = xg | (uint32_t)xl;
+    V re[NL], im[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+        const uint32_t z = (uint32_t)(z0 + zl) | ((uint32_t)((jh << NBL) | j) << KAP);
+        const int64_t o = (int64_t)x * N + z;
+        if constexpr (REAL_IN) {
+            re[j] = __builtin_nontemporal_load((const V*)coeff + o);
+            im[j] = (V)0;
+        } else {
+            load_c<V, true>((const cplx<V>*)coeff + o, re[j], im[j]);
+        }
+        mul_ipow((4 - (__popc(x & z) & 3)) & 3, re[j], im[j]);
+    }
+    wht_reg<V, NBL>(re, im);
+    if constexpr (R::SW) {
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+            const V pr = swap_halves(re[j]), pi = swap_halves(im[j]);
+            re[j] = jh ? pr - re[j] : re[j] + pr;
+            im[j] = jh ? pi - im[j] : im[j] + pi;
+        }
+    }
+    // store side: x_lo fastest across lanes (whole 128-byte segments)
+    const int xs = p % T, zs = p / T;
+    constexpr int PITCH = ZR + 1;
+#pragma unroll
+    for (int r0 = 0; r0 < NL; r0 += R::RBU) {
+        __syncthreads();  // previous round's reads are done
+#pragma unroll
+        for (int jr = 0; jr < R::RBU; ++jr) {
+            cplx<V> c;
+            c.re = re[r0 + jr];
+            c.im = im[r0 + jr];
+            lds[((jh * R::RBU + jr) * T + xl) * PITCH + zl] = c;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int jr = 0; jr < R::RBU; ++jr) {
+            const cplx<V> c = lds[((jh * R::RBU + jr) * T + xs) * PITCH + zs];
+            const int k = (((jh << NBL) | (r0 + jr)) << KAP) | (z0 + zs);
+            const int64_t col = (int64_t)(((uint32_t)k ^ xg) & ~(uint32_t)(T - 1)) + xs;
+            A[(int64_t)k * lda + col] = c;
+        }
+    }
+}
+
+template <class V, class S>
+__device__ __forceinline__ void rec_phase2(cplx<V>* __restrict__ A, int64_t lda, int g, int b, cplx<V>* lds,
+                                           V scale)
+{
+    constexpr int KAP = S::KAP, LOGT = S::LOGT, T = 1 << LOGT;
+    const uint32_t xg = (uint32_t)g << LOGT;
+    const int k0 = b << KAP;
+    auto gather = [&](int vec, int pos, V& re, V& im) {
+        const int k = k0 + pos;
+        const int64_t col = (int64_t)(((uint32_t)k ^ xg) & ~(uint32_t)(T - 1)) + vec;
+        load_c<V, false>(A + (int64_t)k * lda + col, re, im);
+    };
+    auto store = [&](int vec, int pos, V re, V im) {
+        const int k = k0 + pos;
+        store_c<V, true>(A + (int64_t)k * lda + ((uint32_t)k ^ (xg | (uint32_t)vec)), re * scale, im * scale);
+    };
+    // lanes over the vector index in the last round: whole segments per store
+    p1_rounds<V, S, 0, true>(gather, store, lds);
+}
+
+template <class V, class S, bool REAL_IN>
+__global__ __launch_bounds__(S::NT, 4) void k_fused_rec(const void* __restrict__ coeff, cplx<V>* __restrict__ A,
+                                                     int64_t lda, uint32_t* __restrict__ ws, int Q, int LA,
+                                                     uint32_t spin_limit, V scale)
+{
+    typedef RecShape<V, S> R;
+    constexpr int NP1 = R::NR1, NP2 = R::NR2, NG = S::NG;
+    __shared__ cplx<V> lds[(1 << S::LOGT) * ((1 << S::KAP) + 1)];
+    __shared__ int s_next;
+    __shared__ int s_last;
+
+    auto publish = [&](int grp) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(ws + WS_GROUP + grp, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    auto wait_group = [&](int grp) {
+        if (threadIdx.x == 0) {
+            uint32_t spins = 0;
+            while (__hip_atomic_fetch_add(ws + WS_GROUP + grp, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                   (uint32_t)NP1) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > spin_limit ||
+                    ((spins & 255) == 0 &&
+                     __hip_atomic_load(ws + WS_ERR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
+                    __hip_atomic_store(ws + WS_ERR, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+    };
+    auto groups_of = [&](int q) { return (NG - q + Q - 1) / Q; };
+    auto drain = [&](int q) {
+        const int gq = groups_of(q);
+        const int total = gq * (NP1 + NP2);
+        if (threadIdx.x == 0)
+            s_next = (int)__hip_atomic_fetch_add(ws + WS_HEAD + q, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        int cur = __builtin_amdgcn_readfirstlane(s_next);
+        while (cur < total) {
+            const Item it = decode_item(cur, q, Q, gq, NP1, NP2, LA);
+            if (it.phase == 1) {
+                rec_phase1<V, S, REAL_IN>(coeff, A, lda, it.group, it.sub, lds);
+                publish(it.group);
+            } else {
+                wait_group(it.group);
+                rec_phase2<V, S>(A, lda, it.group, it.sub, lds, scale);
+            }
+            __syncthreads();  // LDS reuse, s_next reuse
+            if (threadIdx.x == 0)
+                s_next = (int)__hip_atomic_fetch_add(ws + WS_HEAD + q, 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            cur = __builtin_amdgcn_readfirstlane(s_next);
+        }
+    };
+
+    drain(xcc_id() % Q);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        s_last = __hip_atomic_fetch_add(ws + WS_DONE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                 gridDim.x - 1;
+    __syncthreads();
+    if (!s_last) return;
+    for (int qq = 0; qq < Q; ++qq) drain(qq);
+}
+
+template <class V, int LOGN, bool REAL_IN>
+hipError_t launch_rec_n(const void* coeff, void* A, int64_t lda, void* ws, int la, bool adjoint, hipStream_t st)
+{
+    // 512-thread workgroups, 512-row R2 items, 128-byte segments
+    typedef Shape<V, LOGN, 9, 512, fused_logt<V>()> S;
+    const int words = WS_GROUP + S::NG;
+    hipError_t e = launch_zero_words((uint32_t*)ws, words, st);
+    if (e != hipSuccess) return e;
+    const V scale = adjoint ? (V)1 / (V)(1u << LOGN) : (V)1;  // exact power of two
+    hipLaunchKernelGGL((k_fused_rec<V, S, REAL_IN>), dim3(device_cu_count() * 2), dim3(512), 0, st, coeff,
+                       (cplx<V>*)A, lda, (uint32_t*)ws, device_xcd_count(), la, 1u << 22, scale);
+    return hipGetLastError();
+}
+
+template <class V, bool REAL_IN>
+hipError_t fused_rec_dispatch(int n, const void* coeff, void* A, int64_t lda, void* ws, int la, bool adjoint,
+                              hipStream_t st)
+{
+    switch (n) {
+        case 11: return launch_rec_n<V, 11, REAL_IN>(coeff, A, lda, ws, la, adjoint, st);
+        case 12: return launch_rec_n<V, 12, REAL_IN>(coeff, A, lda, ws, la, adjoint, st);
+        case 13: return launch_rec_n<V, 13, REAL_IN>(coeff, A, lda, ws, la, adjoint, st);
+        case 14: return launch_rec_n<V, 14, REAL_IN>(coeff, A, lda, ws, la, adjoint, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <class V, int LOGN, int KAP, int NT, int LOGT, bool HERM, int POL>

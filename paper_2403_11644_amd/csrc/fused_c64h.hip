@@ -1,5 +1,5 @@
 // fused_c64h.hip -- Hermitian complex64 instantiations of the single-launch
-// schedule (fused.hpp), in a translation unit of their own so they compile
+// schedules (fused.hpp: decomposition and reconstruction), in a translation unit of their own so they compile
 // in parallel with the others.
 #include "fused.hpp"
 
@@ -8,6 +8,11 @@ namespace ptd {
 hipError_t fused_launch_c64_herm(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg, hipStream_t st)
 {
     return fused::fused_dispatch<float, true>(n, A, lda, out, ws, la, cfg, st);
+}
+
+hipError_t fused_rec_c64_herm(int n, const void* coeff, void* A, int64_t lda, void* ws, int la, bool adjoint, hipStream_t st)
+{
+    return fused::fused_rec_dispatch<float, true>(n, coeff, A, lda, ws, la, adjoint, st);
 }
 
 }  // namespace ptd

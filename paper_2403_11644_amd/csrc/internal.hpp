@@ -47,6 +47,18 @@ hipError_t fused_launch_c64_herm(int n, const void* A, int64_t lda, void* out, v
                                  hipStream_t st);
 hipError_t fused_launch_c128_herm(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg,
                                   hipStream_t st);
+// Single-launch dense reconstruction for n = 11..14 (fused.hpp); ws holds
+// fused_workspace_bytes() bytes; real coefficients for the Hermitian forms.
+hipError_t fused_rec_c64(int n, const void* coeff, void* A, int64_t lda, void* ws, int la, bool adjoint,
+                         hipStream_t st);
+hipError_t fused_rec_c128(int n, const void* coeff, void* A, int64_t lda, void* ws, int la, bool adjoint,
+                          hipStream_t st);
+hipError_t fused_rec_c64_herm(int n, const void* coeff, void* A, int64_t lda, void* ws, int la, bool adjoint,
+                              hipStream_t st);
+hipError_t fused_rec_c128_herm(int n, const void* coeff, void* A, int64_t lda, void* ws, int la, bool adjoint,
+                               hipStream_t st);
+hipError_t launch_fused_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const void* coeff, void* A, int64_t lda,
+                            void* ws, int la, hipStream_t st);
 // Zero `count` uint32 words with a small kernel (capturable, unlike a memset node).
 hipError_t launch_zero_words(uint32_t* p, int count, hipStream_t st);
 // Plain 16-byte-per-lane device copy (bandwidth reference).

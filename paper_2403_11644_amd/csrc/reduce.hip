@@ -11,8 +11,9 @@ namespace ptd {
 
 namespace {
 
-constexpr int RED_BLOCKS = 1024;
+constexpr int RED_BLOCKS = 2048;
 constexpr int RED_THREADS = 256;
+constexpr int RED_UNROLL = 4;  // independent loads in flight per thread
 
 __device__ __forceinline__ double block_sum(double v, double* sh)
 {
@@ -25,7 +26,8 @@ __device__ __forceinline__ double block_sum(double v, double* sh)
     return sh[0];
 }
 
-// sum of |A[r][c]|^2 over the 2^n x 2^n matrix with row pitch lda
+// sum of |A[r][c]|^2 over the 2^n x 2^n matrix with row pitch lda; every
+// thread walks a fixed index sequence, RED_UNROLL loads at a time
 template <class V>
 __global__ __launch_bounds__(RED_THREADS) void k_sumsq_matrix(const cplx<V>* __restrict__ A, int64_t lda, int n,
                                                                double* __restrict__ partial)
@@ -33,28 +35,71 @@ __global__ __launch_bounds__(RED_THREADS) void k_sumsq_matrix(const cplx<V>* __r
     __shared__ double sh[RED_THREADS];
     const int64_t N = (int64_t)1 << n;
     const int64_t total = N * N;
+    const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
     double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * RED_THREADS) {
-        const int64_t r = i >> n, c = i & (N - 1);
-        const cplx<V> v = A[r * lda + c];
-        const double a = (double)v.re, b = (double)v.im;
-        acc += a * a;
-        acc += b * b;
+    for (int64_t i0 = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i0 < total; i0 += stride * RED_UNROLL) {
+        cplx<V> v[RED_UNROLL];
+#pragma unroll
+        for (int u = 0; u < RED_UNROLL; ++u) {
+            const int64_t i = i0 + u * stride;
+            if (i < total) {
+                v[u] = A[(i >> n) * lda + (i & (N - 1))];
+            } else {
+                v[u].re = (V)0;
+                v[u].im = (V)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RED_UNROLL; ++u) {
+            const double a = (double)v[u].re, b = (double)v[u].im;
+            acc += a * a;
+            acc += b * b;
+        }
     }
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// sum of squares of `count` real values
+// sum of squares of `count` real values: 16-byte loads over the body when
+// the pointer is 16-byte aligned, scalar loads otherwise
 template <class V>
 __global__ __launch_bounds__(RED_THREADS) void k_sumsq_vec(const V* __restrict__ v, int64_t count,
                                                             double* __restrict__ partial)
 {
     __shared__ double sh[RED_THREADS];
+    constexpr int PER = 16 / sizeof(V);
+    typedef V vec_t __attribute__((ext_vector_type(PER)));
+    const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
+    const int64_t tid = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x;
     double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < count;
-         i += (int64_t)gridDim.x * RED_THREADS) {
+    int64_t body = 0;
+    if (((uintptr_t)v & 15) == 0) {
+        const vec_t* w = (const vec_t*)v;
+        const int64_t nw = count / PER;
+        body = nw * PER;
+        for (int64_t i0 = tid; i0 < nw; i0 += stride * RED_UNROLL) {
+            vec_t x[RED_UNROLL];
+#pragma unroll
+            for (int u = 0; u < RED_UNROLL; ++u) {
+                const int64_t i = i0 + u * stride;
+                if (i < nw) {
+                    x[u] = w[i];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < PER; ++e) x[u][e] = (V)0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < RED_UNROLL; ++u) {
+#pragma unroll
+                for (int e = 0; e < PER; ++e) {
+                    const double a = (double)x[u][e];
+                    acc += a * a;
+                }
+            }
+        }
+    }
+    for (int64_t i = body + tid; i < count; i += stride) {
         const double a = (double)v[i];
         acc += a * a;
     }

@@ -51,6 +51,15 @@ def test_workspace_sizes(lib):
     assert lib.ptd_workspace_bytes(15, 0, 0, 0) == 0
     assert lib.ptd_workspace_bytes(14, 0, 1 << 1, 0) == 0  # structured
     assert lib.ptd_workspace_bytes(13, 0, 1, 0) > 0  # Hermitian
+    # reconstruction: one launch with counters for n = 11..14, none otherwise
+    for n in (1, 10, 15, 16):
+        assert lib.ptd_reconstruct_workspace_bytes(n, 0, 0) == 0
+    for n in (11, 14):
+        for dt in (0, 1):
+            assert lib.ptd_reconstruct_workspace_bytes(n, dt, 0) == lib.ptd_workspace_bytes(n, dt, 0, 0)
+    assert lib.ptd_reconstruct_workspace_bytes(12, 0, 1 | (1 << 6)) > 0  # Hermitian adjoint
+    assert lib.ptd_reconstruct_workspace_bytes(12, 0, 1 << 1) == 0  # not a reconstruct flag
+    assert lib.ptd_reconstruct_workspace_bytes(0, 0, 0) == 0
 
 
 def test_nonempty_counts_match_bruteforce(lib, oracle_mod):
@@ -105,6 +114,9 @@ def test_reconstruct_argument_errors(lib):
     assert rec(lda=8) == EINVAL
     assert rec(flags=1 << 1) == EINVAL
     assert rec(dt=3) == EINVAL
+    assert rec(C=5, A=5) == EINVAL  # coefficients and matrix must differ
+    ENOSPC = -2
+    assert rec(n=12, lda=4096) == ENOSPC  # the single-launch schedule needs its counters
 
 
 def test_nonempty_x_errors(lib):

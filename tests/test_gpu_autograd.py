@@ -37,7 +37,7 @@ def test_gradcheck_small_full(ptd):
     assert torch.autograd.gradcheck(ptd.PauliReconstruct.apply, (c,), eps=1e-6, atol=1e-8, rtol=1e-6)
 
 
-@pytest.mark.parametrize("n", [6, 12])
+@pytest.mark.parametrize("n", [6, 12, 14])
 def test_oracle_gradient(ptd, oracle_mod, n):
     A = to_dev(synth.dense(n, seed=3)).requires_grad_(True)
     w = synth.dense(n, seed=9)

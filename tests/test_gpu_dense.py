@@ -173,6 +173,62 @@ def test_reconstruct_integer_exact(ptd, oracle_mod):
 # --------------------------------------------------------------------------
 # Parseval residual in float64 (Theorem 1)
 
+# the single-launch reconstruction (n = 11..14) behind the public call
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n", [11, 12, 13, 14])
+def test_reconstruct_single_launch_integer(ptd, dt, n):
+    """Gaussian-integer A: c = decompose(A) holds exact multiples of 2^-n, so
+    the reconstruction must give A back bit for bit, and it must equal the
+    two-pass schedule (checked against the oracle at n <= 11) exactly."""
+    from paper_2403_11644_amd import api
+
+    re, im = synth.gaussian_int(n, seed=700 + n)
+    A = to_dev(synth.int_to_complex(re, im, _np_dtype(dt)))
+    c = ptd.decompose(A)
+    back = ptd.reconstruct(c)
+    assert torch_equal(back, A)
+    two = api._debug_reconstruct_path(c, 2)
+    assert torch_equal(back, two)
+    adj = ptd.reconstruct(c, adjoint=True)
+    assert torch_equal(adj * (1 << n), back)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n", [11, 13])
+def test_reconstruct_single_launch_float(ptd, dt, n):
+    from paper_2403_11644_amd import api
+
+    c = synth.dense(n, seed=800 + n, dtype=_np_dtype(dt))
+    cd = to_dev(c)
+    got = to_host(ptd.reconstruct(cd))
+    two = to_host(api._debug_reconstruct_path(cd, 2))
+    assert rel_err(got, two) <= TOL[dt]
+    # A = sum_P c_P P  <=>  decompose(A) = c
+    back = to_host(ptd.decompose(to_dev(got)))
+    assert rel_err(back, c) <= (1e-12 if dt == "c128" else 2e-5)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n", [11, 12, 14])
+def test_reconstruct_single_launch_hermitian(ptd, dt, n):
+    from paper_2403_11644_amd import api
+
+    re, im = synth.gaussian_int_hermitian(n, seed=900 + n)
+    A = to_dev(synth.int_to_complex(re, im, _np_dtype(dt)))
+    ch = ptd.decompose(A, hermitian=True)
+    back = ptd.reconstruct(ch, hermitian=True)
+    assert torch_equal(back, A)
+    two = api._debug_reconstruct_path(ch, 2, hermitian=True)
+    assert torch_equal(back, two)
+
+
+def torch_equal(a, b):
+    import torch
+
+    return bool(torch.equal(a, b))
+
+
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 def test_parseval(ptd, oracle_mod, dt):
     n = 9
