@@ -198,11 +198,19 @@ ptd_status ptd_parseval_residual(int n, ptd_dtype dtype, unsigned flags, const v
                                  ptd_stream stream);
 
 /*
- * Autotuning of the dense single-launch schedule (n = 11..15, complex64 and
- * complex128 for n <= 14, flags 0 or PTD_HERMITIAN).  ptd_autotune times the
- * candidate settings (workgroup shape, cache policies of the gathers, the
- * final stores and the re-read partial results, queue lookahead) at this
- * (n, dtype, Hermitian)
+ * Autotuning of the dense schedules (flags 0 or PTD_HERMITIAN).
+ *
+ * n = 1..10, the single-pass group kernel (single calls and batched
+ * launches): cfg is the plan, bit 0 = 1024 threads per workgroup (else 512),
+ * bit 1 = radix-32 WHT rounds (complex64 only; else radix 16); lookahead is
+ * unused (0).  ptd_autotune times the plans on a batch of equal-size
+ * matrices through the batched kernel.
+ *
+ * n = 11..15, the single-launch schedule (complex128 for n <= 14): cfg holds
+ * the workgroup shape and the cache policies of the gathers, the final
+ * stores and the re-read partial results; lookahead is the queue lookahead.
+ *
+ * ptd_autotune times the candidate settings at this (n, dtype, Hermitian)
  * point on device buffers it allocates itself, admits a candidate only if
  * its output on a Gaussian-integer matrix equals the default setting's bit
  * for bit, records the fastest in a process-wide registry that

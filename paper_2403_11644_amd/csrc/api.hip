@@ -237,14 +237,15 @@ ptd_status batched_common(bool rec, int count, ptd_dtype dtype, unsigned flags, 
     if (flags & ~allowed) return PTD_EINVAL;
     if (!ws || ws_bytes < ptd::batched_buffer_bytes(count, dtype, n_host)) return PTD_ENOSPC;
     std::vector<unsigned char> img;
-    int nitems = 0;
-    ptd::batched_fill(count, dtype, n_host, in_off, out_off, img, &nitems);
+    ptd::BatchLaunch bl;
+    ptd::batched_fill(count, dtype, flags & PTD_HERMITIAN, rec, n_host, in_off, out_off, img, &bl);
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = hipMemcpyAsync((unsigned char*)ws + 256, img.data(), img.size(), hipMemcpyHostToDevice, st);
+    hipError_t e = hipMemcpyAsync((unsigned char*)ws + ptd::BATCH_HEAD_BYTES, img.data(), img.size(),
+                                  hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // img is released on return
     if (e != hipSuccess) return hip_status(e);
     return hip_status(ptd::batched_launch(dtype, flags & PTD_HERMITIAN, rec, flags & PTD_ADJOINT, in_base, out_base,
-                                          ws, count, nitems, ptd::device_cu_count(), st));
+                                          ws, count, bl, ptd::device_cu_count(), st));
 }
 
 }  // namespace
@@ -291,23 +292,23 @@ ptd_status ptd_batch_plan_create(int count, ptd_dtype dtype, unsigned flags, con
     const bool rec = flags & PTD_PLAN_RECONSTRUCT;
     if ((flags & PTD_ADJOINT) && !rec) return PTD_EINVAL;
     std::vector<unsigned char> img;
-    int nitems = 0;
-    ptd::batched_fill(count, dtype, n_host, in_off_host, out_off_host, img, &nitems);
+    ptd::BatchLaunch bl;
+    ptd::batched_fill(count, dtype, flags & PTD_HERMITIAN, rec, n_host, in_off_host, out_off_host, img, &bl);
     ptd_plan* p = new (std::nothrow) ptd_plan;
     if (!p) return PTD_ENOMEM;
-    const size_t bytes = 256 + img.size();
+    const size_t bytes = ptd::BATCH_HEAD_BYTES + img.size();
     if (hipMalloc(&p->buf, bytes) != hipSuccess) {
         delete p;
         return PTD_ENOMEM;
     }
-    hipError_t e = hipMemcpy((unsigned char*)p->buf + 256, img.data(), img.size(), hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpy((unsigned char*)p->buf + ptd::BATCH_HEAD_BYTES, img.data(), img.size(), hipMemcpyHostToDevice);
     hipStream_t cs = nullptr;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         // the queue counter is reset by a kernel node (no memset node in the graph)
         hipError_t le = ptd::batched_launch(dtype, flags & PTD_HERMITIAN, rec, flags & PTD_ADJOINT, in_base, out_base,
-                                            p->buf, count, nitems, ptd::device_cu_count(), cs);
+                                            p->buf, count, bl, ptd::device_cu_count(), cs);
         e = hipStreamEndCapture(cs, &p->graph);
         if (le != hipSuccess) e = le;
     }
@@ -338,9 +339,19 @@ void ptd_batch_plan_destroy(ptd_plan* plan)
 
 // ------------------------------------------------------------------ tuning
 
+// Sizes n <= 10 tune the single-pass group plan: cfg = plan (bit 0: 1024
+// threads, bit 1: radix-32 rounds, complex64 only), lookahead unused.
+static bool group_tunable(int n) { return n >= 1 && n <= 10; }
+
 ptd_status ptd_set_tuning(int n, ptd_dtype dtype, unsigned flags, int cfg, int lookahead)
 {
-    if (!valid_dtype(dtype) || (flags & ~PTD_HERMITIAN) || !use_fused(n, dtype, flags)) return PTD_EINVAL;
+    if (!valid_dtype(dtype) || (flags & ~PTD_HERMITIAN)) return PTD_EINVAL;
+    if (group_tunable(n)) {
+        if (cfg < 0 || cfg > (dtype == PTD_C64 ? 3 : 1) || lookahead < 0) return PTD_EINVAL;
+        ptd::set_group_tuning(n, dtype, flags & PTD_HERMITIAN, cfg);
+        return PTD_OK;
+    }
+    if (!use_fused(n, dtype, flags)) return PTD_EINVAL;
     if (cfg < 0 || cfg > 31 || lookahead < 1 || lookahead > 64) return PTD_EINVAL;
     ptd::set_fused_tuning(n, dtype, flags & PTD_HERMITIAN, ptd::FusedTuning{cfg, lookahead});
     return PTD_OK;
@@ -349,6 +360,13 @@ ptd_status ptd_set_tuning(int n, ptd_dtype dtype, unsigned flags, int cfg, int l
 int ptd_get_tuning(int n, ptd_dtype dtype, unsigned flags, int* cfg, int* lookahead)
 {
     if (!valid_dtype(dtype) || (flags & ~PTD_HERMITIAN) || !cfg || !lookahead) return PTD_EINVAL;
+    if (group_tunable(n)) {
+        int plan = ptd::group_default_plan(n, dtype, flags & PTD_HERMITIAN);
+        const bool tuned = ptd::get_group_tuning(n, dtype, flags & PTD_HERMITIAN, &plan);
+        *cfg = plan;
+        *lookahead = 0;
+        return tuned ? 1 : 0;
+    }
     ptd::FusedTuning t = use_fused(n, dtype, flags) ? ptd::fused_default(n, dtype, flags & PTD_HERMITIAN)
                                                     : ptd::FusedTuning{0, 0};
     const bool tuned = ptd::get_fused_tuning(n, dtype, flags & PTD_HERMITIAN, &t);
@@ -366,6 +384,15 @@ ptd_status ptd_autotune(int n, ptd_dtype dtype, unsigned flags, int reps, ptd_st
         !admitted)
         return PTD_EINVAL;
     if (n < 1 || n > 16) return PTD_EINVAL;
+    if (group_tunable(n)) {
+        int plan = 0;
+        hipError_t e = ptd::autotune_group(n, dtype, flags & PTD_HERMITIAN, reps, (hipStream_t)stream, &plan, ms, tried,
+                                           admitted);
+        if (e != hipSuccess) return hip_status(e);
+        *cfg = plan;
+        *lookahead = 0;
+        return PTD_OK;
+    }
     if (!use_fused(n, dtype, flags)) return PTD_EUNSUP;
     ptd::FusedTuning best = ptd::fused_default(n, dtype, flags & PTD_HERMITIAN);
     hipError_t e = ptd::autotune_fused(n, dtype, flags & PTD_HERMITIAN, reps, (hipStream_t)stream, &best, ms, tried,

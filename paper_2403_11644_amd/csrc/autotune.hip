@@ -1,5 +1,11 @@
-// autotune.hip -- measured choice of the single-launch schedule's parameters.
+// autotune.hip -- measured choice of the dense schedules' parameters.
 //
+// Sizes n <= 10 (single-pass group kernel, also inside batched launches):
+// the plan, i.e. the workgroup size (512 or 1024 threads) and the widest
+// WHT round (radix 16 or, for complex64, radix 32), timed on a batch of
+// equal-size matrices through the batched persistent kernel.
+//
+// Sizes n = 11..15:
 // The persistent dense kernel (fused.hpp) has a shape (threads per
 // workgroup, rows per phase-1 item, X-patterns per group), cache-policy
 // options (non-temporal gathers, final stores, phase-2 loads) and the
@@ -21,6 +27,7 @@ namespace {
 
 std::mutex g_mu;
 std::map<int, FusedTuning> g_table;
+std::map<int, int> g_group;  // single-pass group plans, n <= 10
 
 int key_of(int n, ptd_dtype dt, bool herm) { return (n << 2) | ((int)dt << 1) | (herm ? 1 : 0); }
 
@@ -35,13 +42,16 @@ __device__ __forceinline__ uint32_t mix(uint32_t x)
     return x;
 }
 
-// Gaussian integers in [-8, 8]; Hermitian: the upper triangle decides.
+// `count` consecutive 2^n x 2^n matrices of Gaussian integers in [-8, 8];
+// Hermitian: the upper triangle of each matrix decides.
 template <class V>
-__global__ void k_fill_int(cplx<V>* __restrict__ A, int n, int herm, uint32_t seed)
+__global__ void k_fill_int(cplx<V>* __restrict__ A, int n, int herm, uint32_t seed, int count = 1)
 {
     const int64_t N = (int64_t)1 << n;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N * N; e += (int64_t)gridDim.x * blockDim.x) {
-        int64_t r = e >> n, c = e & (N - 1);
+    const int64_t total = N * N * count;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t mi = e >> (2 * n);
+        int64_t r = (e >> n) & (N - 1), c = e & (N - 1);
         bool conj = false;
         if (herm && r > c) {
             const int64_t t = r;
@@ -49,7 +59,7 @@ __global__ void k_fill_int(cplx<V>* __restrict__ A, int n, int herm, uint32_t se
             c = t;
             conj = true;
         }
-        const uint32_t h = mix((uint32_t)(r * N + c) ^ mix(seed));
+        const uint32_t h = mix((uint32_t)(((mi << (2 * n)) + r * N + c) & 0xffffffff) ^ mix(seed));
         V re = (V)((int)(h % 17u) - 8);
         V im = (V)((int)((h >> 8) % 17u) - 8);
         if (herm && r == c) im = (V)0;
@@ -106,6 +116,37 @@ void clear_fused_tuning()
 {
     std::lock_guard<std::mutex> lk(g_mu);
     g_table.clear();
+    g_group.clear();
+}
+
+int group_default_plan(int n, ptd_dtype dt, bool herm)
+{
+    // measured on MI355X (batches of equal-size matrices): radix-32 rounds
+    // win for complex64 at n = 10, Hermitian or not; elsewhere the radix-16
+    // 512-thread plan
+    (void)herm;
+    return (dt == PTD_C64 && n == 10) ? 2 : 0;
+}
+
+bool get_group_tuning(int n, ptd_dtype dt, bool herm, int* plan)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_group.find(key_of(n, dt, herm));
+    if (it == g_group.end()) return false;
+    *plan = it->second;
+    return true;
+}
+
+void set_group_tuning(int n, ptd_dtype dt, bool herm, int plan)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_group[key_of(n, dt, herm)] = plan;
+}
+
+int group_plan(int n, ptd_dtype dt, bool herm)
+{
+    int p = 0;
+    return get_group_tuning(n, dt, herm, &p) ? p : group_default_plan(n, dt, herm);
 }
 
 hipError_t autotune_fused(int n, ptd_dtype dt, bool herm, int reps, hipStream_t st, FusedTuning* best, float* best_ms,
@@ -188,6 +229,104 @@ hipError_t autotune_fused(int n, ptd_dtype dt, bool herm, int reps, hipStream_t 
     *tried = ntried;
     *admitted = nadmit;
     set_fused_tuning(n, dt, herm, bt);
+    return hipSuccess;
+}
+
+// Plans of the single-pass group kernel at size n, timed on a batch of
+// equal-size matrices (about 256 MiB of input, the shape of a batched launch)
+// through the batched persistent kernel; admitted only if bit-identical to
+// plan 0 on Gaussian integers.
+hipError_t autotune_group(int n, ptd_dtype dt, bool herm, int reps, hipStream_t st, int* best, float* best_ms,
+                          int* tried, int* admitted)
+{
+    const int64_t N = (int64_t)1 << n;
+    const size_t esz = dt == PTD_C128 ? 16 : 8;
+    const int64_t mat = N * N;
+    int64_t M = ((int64_t)256 << 20) / (mat * (int64_t)esz);
+    M = M < 1 ? 1 : (M > 4096 ? 4096 : M);
+    const int count = (int)M;
+    std::vector<int32_t> ns(count, n);
+    std::vector<int64_t> off(count);
+    for (int i = 0; i < count; ++i) off[i] = (int64_t)i * mat;
+    const size_t in_bytes = (size_t)(M * mat) * esz;
+    const size_t out_bytes = herm ? in_bytes / 2 : in_bytes;
+    const size_t desc_bytes = batched_buffer_bytes(count, dt, ns.data());
+    Buffers b;
+    hipError_t e = hipMalloc(&b.A, in_bytes);
+    if (e == hipSuccess) e = hipMalloc(&b.ref, out_bytes);
+    if (e == hipSuccess) e = hipMalloc(&b.out, out_bytes);
+    if (e == hipSuccess) e = hipMalloc(&b.ws, desc_bytes);
+    if (e == hipSuccess) e = hipMalloc(&b.diff, sizeof(uint32_t));
+    if (e != hipSuccess) return e;
+    if (dt == PTD_C128)
+        hipLaunchKernelGGL(k_fill_int<double>, dim3(4096), dim3(256), 0, st, (cplx<double>*)b.A, n, herm ? 1 : 0,
+                           777u, count);
+    else
+        hipLaunchKernelGGL(k_fill_int<float>, dim3(4096), dim3(256), 0, st, (cplx<float>*)b.A, n, herm ? 1 : 0, 777u,
+                           count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    std::vector<unsigned char> img;
+    BatchLaunch bl;
+    batched_fill(count, dt, herm, false, ns.data(), off.data(), off.data(), img, &bl, 0);
+    if ((e = hipMemcpyAsync((unsigned char*)b.ws + BATCH_HEAD_BYTES, img.data(), img.size(), hipMemcpyHostToDevice, st)) !=
+        hipSuccess)
+        return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    const int cus = device_cu_count();
+    // reference: plan 0
+    if ((e = batched_launch(dt, herm, false, false, b.A, b.ref, b.ws, count, bl, cus, st)) != hipSuccess) return e;
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return e;
+    }
+    // plans that differ at this size: 1024-thread workgroups at n = 10 only,
+    // radix-32 rounds for complex64 at n >= 6 only
+    std::vector<int> cands{0};
+    if (n == 10) cands.push_back(1);
+    if (dt == PTD_C64 && n >= 6) {
+        cands.push_back(2);
+        if (n == 10) cands.push_back(3);
+    }
+    float bestt = 1e30f;
+    int bp = 0, ntried = 0, nadmit = 0;
+    for (int plan : cands) {
+        if (e != hipSuccess) break;
+        BatchLaunch cl;
+        std::vector<unsigned char> unused;
+        batched_fill(count, dt, herm, false, ns.data(), off.data(), off.data(), unused, &cl, plan);
+        ++ntried;
+        if ((e = hipMemsetAsync(b.diff, 0, sizeof(uint32_t), st)) != hipSuccess) break;
+        if ((e = batched_launch(dt, herm, false, false, b.A, b.out, b.ws, count, cl, cus, st)) != hipSuccess) break;
+        hipLaunchKernelGGL(k_count_diff, dim3(2048), dim3(256), 0, st, (const uint32_t*)b.out, (const uint32_t*)b.ref,
+                           (int64_t)(out_bytes / 4), b.diff);
+        uint32_t diff = 1;
+        if ((e = hipMemcpyAsync(&diff, b.diff, sizeof diff, hipMemcpyDeviceToHost, st)) != hipSuccess) break;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) break;
+        if (diff != 0) continue;
+        ++nadmit;
+        if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
+        for (int r = 0; r < reps; ++r) (void)batched_launch(dt, herm, false, false, b.A, b.out, b.ws, count, cl, cus, st);
+        if ((e = hipEventRecord(e1, st)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        ms /= (float)reps;
+        if (ms < bestt) {
+            bestt = ms;
+            bp = plan;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return e;
+    if (nadmit == 0) return hipErrorUnknown;
+    *best = bp;
+    *best_ms = bestt;
+    *tried = ntried;
+    *admitted = nadmit;
+    set_group_tuning(n, dt, herm, bp);
     return hipSuccess;
 }
 

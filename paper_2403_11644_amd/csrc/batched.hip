@@ -1,16 +1,21 @@
-// batched.hip -- many matrices of uneven size (n <= 10) in one persistent launch.
+// batched.hip -- many matrices of uneven size (n <= 10) in persistent launches.
 //
 // Work items are (matrix, X-pattern group) pairs; each is the single-pass
-// group routine of group.hpp for that matrix's n, chosen by a switch inside
-// the kernel.  Items are listed largest matrices first (longest-processing-
-// time order) and taken from one atomic counter, so workgroups that finish
-// small items early keep pulling work and the tail is short.  The forward
-// map and the reconstruction (with optional 2^-n adjoint scale) share the
-// kernel.
+// group routine of group.hpp.  Items are listed largest matrices first
+// (longest-processing-time order).  Every size present gets one persistent
+// launch over its own contiguous range of items, taken from its own atomic
+// counter, so workgroups that finish items early keep pulling work and the
+// tail is short.  One launch per size gives each kernel the register budget
+// and LDS of its own size, hence its own occupancy (one 131 KiB workgroup per
+// CU at n = 10, two below), and lets the tuned plan of each size (workgroup
+// size, radix) apply.  The forward map and the reconstruction (with optional
+// 2^-n adjoint scale) share the kernel.  A batch plan captures all launches
+// in one graph.
 //
 // Workspace / plan buffer layout (bytes):
-//   [0, 256)          queue counter (zeroed by a kernel before each launch)
-//   [256, ...)        BatchMat[count] then BatchItem[items]
+//   [0, BATCH_HEAD_BYTES)   queue counters, one per size, 64 bytes apart
+//                           (zeroed by a kernel before each launch)
+//   [BATCH_HEAD_BYTES, ...) BatchMat[count] then BatchItem[items]
 #include <vector>
 
 #include "engine.hpp"
@@ -33,7 +38,8 @@ struct BatchItem {
     uint32_t group;
 };
 
-constexpr size_t HEAD_BYTES = 256;
+constexpr int COUNTER_STRIDE = 16;  // uint32 words: one 64-byte line per counter
+static_assert(11 * COUNTER_STRIDE * 4 <= (int)BATCH_HEAD_BYTES, "counters fit the head");
 
 template <class V>
 __host__ __device__ constexpr int batch_logt(int n)
@@ -41,62 +47,119 @@ __host__ __device__ constexpr int batch_logt(int n)
     return group_logt<V>(n);
 }
 
-template <class V, bool HERM, bool REC>
-__global__ __launch_bounds__(GROUP_THREADS) void k_batched(const void* __restrict__ in_base, void* __restrict__ out_base,
-                                                          const BatchMat* __restrict__ mats,
-                                                          const BatchItem* __restrict__ items, int nitems,
-                                                          uint32_t* __restrict__ counter, int adjoint)
+// 512-thread workgroups per CU that the LDS of size NN allows, at most 2
+template <class V, int NN>
+constexpr int wgs_per_cu()
 {
-    __shared__ cplx<V> lds[group_lds_elems<V>(10)];
+    return (160 * 1024) / (group_lds_elems<V>(NN) * (int)sizeof(cplx<V>)) >= 2 ? 2 : 1;
+}
+
+// Items [begin, end) of size-NN matrices.
+template <class V, int NN, bool HERM, bool REC, int NT, int RMAX>
+__global__ __launch_bounds__(NT, (NT / 256) * (NT == 512 ? wgs_per_cu<V, NN>() : 1)) void k_batched(
+    const void* __restrict__ in_base, void* __restrict__ out_base, const BatchMat* __restrict__ mats,
+    const BatchItem* __restrict__ items, int begin, int end, uint32_t* __restrict__ counter, int adjoint)
+{
+    constexpr int LOGT = group_logt<V>(NN);
+    constexpr int64_t N = (int64_t)1 << NN;
+    __shared__ cplx<V> lds[group_lds_elems<V>(NN)];
     __shared__ int s_item;
     for (;;) {
         if (threadIdx.x == 0)
-            s_item = (int)__hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_item = begin + (int)__hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
         const int i = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
-        if (i >= nitems) break;
+        if (i >= end) break;
         const BatchItem it = items[i];
         const BatchMat m = mats[it.mat];
         const int g = (int)it.group;
-        const int64_t N = (int64_t)1 << m.n;
         if constexpr (!REC) {
             const cplx<V>* A = (const cplx<V>*)in_base + m.in_off;
             void* out = HERM ? (void*)((V*)out_base + m.out_off) : (void*)((cplx<V>*)out_base + m.out_off);
-            switch (m.n) {
-#define PTD_CASE(NN)                                                                   \
-    case NN: group_fwd<V, NN, group_logt<V>(NN), HERM>(A, N, out, N, g, lds); break;
-                PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5)
-                PTD_CASE(6) PTD_CASE(7) PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
-#undef PTD_CASE
-                default: break;
-            }
+            group_fwd<V, NN, LOGT, HERM, NT, RMAX>(A, N, out, N, g, lds);
         } else {
             const void* C = HERM ? (const void*)((const V*)in_base + m.in_off)
                                  : (const void*)((const cplx<V>*)in_base + m.in_off);
             cplx<V>* A = (cplx<V>*)out_base + m.out_off;
-            const V scale = adjoint ? exp2_neg<V>(m.n) : (V)1;
-            switch (m.n) {
-#define PTD_CASE(NN)                                                                      \
-    case NN: group_rec<V, NN, group_logt<V>(NN), HERM>(C, A, N, scale, g, lds); break;
-                PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5)
-                PTD_CASE(6) PTD_CASE(7) PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
-#undef PTD_CASE
-                default: break;
-            }
+            const V scale = adjoint ? exp2_neg<V>(NN) : (V)1;
+            group_rec<V, NN, LOGT, HERM, NT>(C, A, N, scale, g, lds);
         }
         __syncthreads();  // LDS and s_item reuse
     }
 }
 
-__global__ void k_zero_counter(uint32_t* __restrict__ p)
+__global__ void k_zero_counters(uint32_t* __restrict__ p)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
+    if (blockIdx.x == 0 && threadIdx.x <= 10) p[threadIdx.x * COUNTER_STRIDE] = 0u;
 }
 
 int logt_of(ptd_dtype dt, int n)
 {
     return dt == PTD_C64 ? batch_logt<float>(n) : batch_logt<double>(n);
+}
+
+template <class V, int NN, bool HERM, bool REC, int NT, int RMAX>
+void launch_size(const void* in_base, void* out_base, const BatchMat* mats, const BatchItem* its, int begin, int end,
+                 uint32_t* counter, int adj, int cus, hipStream_t st)
+{
+    const int per_cu = NT == 512 ? wgs_per_cu<V, NN>() : 1;
+    hipLaunchKernelGGL((k_batched<V, NN, HERM, REC, NT, RMAX>), dim3(cus * per_cu), dim3(NT), 0, st, in_base,
+                       out_base, mats, its, begin, end, counter, adj);
+}
+
+// The plan of size NN: 1024-thread workgroups only at n = 10 (where one
+// workgroup fills a CU), radix-32 rounds only for complex64 and n >= 6.
+template <class V, int NN, bool HERM, bool REC>
+void launch_size_plan(int plan, const void* in_base, void* out_base, const BatchMat* mats, const BatchItem* its,
+                      int begin, int end, uint32_t* counter, int adj, int cus, hipStream_t st)
+{
+    constexpr bool CAN_BIG = NN == 10 && !REC;
+    constexpr bool CAN_R5 = !REC && sizeof(V) == 4 && NN >= 6;
+    const bool big = CAN_BIG && group_plan_nt(plan) == 1024;
+    const bool r5 = CAN_R5 && group_effective_rmax(NN, PTD_C64, plan) == 5;
+    if constexpr (CAN_BIG) {
+        if (big) {
+            if constexpr (CAN_R5) {
+                if (r5) {
+                    launch_size<V, NN, HERM, REC, 1024, 5>(in_base, out_base, mats, its, begin, end, counter, adj, cus,
+                                                          st);
+                    return;
+                }
+            }
+            launch_size<V, NN, HERM, REC, 1024, 4>(in_base, out_base, mats, its, begin, end, counter, adj, cus, st);
+            return;
+        }
+    }
+    if constexpr (CAN_R5) {
+        if (r5) {
+            launch_size<V, NN, HERM, REC, 512, 5>(in_base, out_base, mats, its, begin, end, counter, adj, cus, st);
+            return;
+        }
+    }
+    launch_size<V, NN, HERM, REC, 512, 4>(in_base, out_base, mats, its, begin, end, counter, adj, cus, st);
+}
+
+template <class V, bool HERM, bool REC>
+void launch_all(const BatchLaunch& bl, const void* in_base, void* out_base, const BatchMat* mats,
+                const BatchItem* its, uint32_t* counters, int adj, int cus, hipStream_t st)
+{
+    for (int n = 10; n >= 1; --n) {
+        const int b = bl.begin[n], e = bl.begin[n - 1];
+        if (e <= b) continue;
+        uint32_t* c = counters + n * COUNTER_STRIDE;
+        const int plan = bl.plan[n];
+        switch (n) {
+#define PTD_CASE(NN)                                                                                    \
+    case NN:                                                                                            \
+        launch_size_plan<V, NN, HERM, REC>(plan, in_base, out_base, mats, its, b, e, c, adj, cus, st); \
+        break;
+            PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5)
+            PTD_CASE(6) PTD_CASE(7) PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
+#undef PTD_CASE
+            default: break;
+        }
+    }
 }
 
 }  // namespace
@@ -110,13 +173,14 @@ int64_t batched_item_count(int count, ptd_dtype dt, const int32_t* n_host)
 
 size_t batched_buffer_bytes(int count, ptd_dtype dt, const int32_t* n_host)
 {
-    return HEAD_BYTES + (size_t)count * sizeof(BatchMat) +
+    return BATCH_HEAD_BYTES + (size_t)count * sizeof(BatchMat) +
            (size_t)batched_item_count(count, dt, n_host) * sizeof(BatchItem);
 }
 
-// Fill the host image of the descriptor buffer (after the head).
-void batched_fill(int count, ptd_dtype dt, const int32_t* n_host, const int64_t* in_off, const int64_t* out_off,
-                  std::vector<unsigned char>& img, int* nitems_out)
+// Fill the host image of the descriptor buffer (after the head), the item
+// range of every size and the plan of every size.
+void batched_fill(int count, ptd_dtype dt, bool herm, bool rec, const int32_t* n_host, const int64_t* in_off,
+                  const int64_t* out_off, std::vector<unsigned char>& img, BatchLaunch* bl, int force_plan)
 {
     const int64_t items = batched_item_count(count, dt, n_host);
     img.assign((size_t)count * sizeof(BatchMat) + (size_t)items * sizeof(BatchItem), 0);
@@ -128,11 +192,13 @@ void batched_fill(int count, ptd_dtype dt, const int32_t* n_host, const int64_t*
         mats[i].n = n_host[i];
         mats[i].pad = 0;
     }
-    // largest matrices first; ties keep the caller's order
-    std::vector<int> byn[17];
+    // largest matrices first; ties keep the caller's order.  Items of size n
+    // occupy [begin[n], begin[n - 1]).
+    std::vector<int> byn[11];
     for (int i = 0; i < count; ++i) byn[n_host[i]].push_back(i);
     int64_t k = 0;
-    for (int n = 16; n >= 1; --n)
+    for (int n = 10; n >= 1; --n) {
+        bl->begin[n] = (int)k;
         for (int mi : byn[n]) {
             const int groups = 1 << (n - logt_of(dt, n));
             for (int g = 0; g < groups; ++g) {
@@ -141,36 +207,39 @@ void batched_fill(int count, ptd_dtype dt, const int32_t* n_host, const int64_t*
                 ++k;
             }
         }
-    *nitems_out = (int)items;
+    }
+    bl->begin[0] = (int)k;
+    bl->nitems = (int)items;
+    for (int n = 1; n <= 10; ++n)
+        bl->plan[n] = rec ? 0 : (force_plan >= 0 ? force_plan : group_plan(n, dt, herm));
 }
 
 hipError_t batched_launch(ptd_dtype dt, bool herm, bool rec, bool adjoint, const void* in_base, void* out_base,
-                          void* buf, int count, int nitems, int cus, hipStream_t st)
+                          void* buf, int count, const BatchLaunch& bl, int cus, hipStream_t st)
 {
-    uint32_t* counter = (uint32_t*)buf;
-    const BatchMat* mats = (const BatchMat*)((unsigned char*)buf + HEAD_BYTES);
-    const BatchItem* its = (const BatchItem*)((unsigned char*)buf + HEAD_BYTES + (size_t)count * sizeof(BatchMat));
-    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, st, counter);
+    uint32_t* counters = (uint32_t*)buf;
+    const BatchMat* mats = (const BatchMat*)((unsigned char*)buf + BATCH_HEAD_BYTES);
+    const BatchItem* its =
+        (const BatchItem*)((unsigned char*)buf + BATCH_HEAD_BYTES + (size_t)count * sizeof(BatchMat));
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(256), 0, st, counters);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 grid(cus), block(GROUP_THREADS);
     const int adj = adjoint ? 1 : 0;
-#define PTD_LAUNCH(VV, HH, RR) \
-    hipLaunchKernelGGL((k_batched<VV, HH, RR>), grid, block, 0, st, in_base, out_base, mats, its, nitems, counter, adj)
+#define PTD_ALL(VV, HH, RR) launch_all<VV, HH, RR>(bl, in_base, out_base, mats, its, counters, adj, cus, st)
     if (dt == PTD_C128) {
         if (rec) {
-            if (herm) PTD_LAUNCH(double, true, true); else PTD_LAUNCH(double, false, true);
+            if (herm) PTD_ALL(double, true, true); else PTD_ALL(double, false, true);
         } else {
-            if (herm) PTD_LAUNCH(double, true, false); else PTD_LAUNCH(double, false, false);
+            if (herm) PTD_ALL(double, true, false); else PTD_ALL(double, false, false);
         }
     } else {
         if (rec) {
-            if (herm) PTD_LAUNCH(float, true, true); else PTD_LAUNCH(float, false, true);
+            if (herm) PTD_ALL(float, true, true); else PTD_ALL(float, false, true);
         } else {
-            if (herm) PTD_LAUNCH(float, true, false); else PTD_LAUNCH(float, false, false);
+            if (herm) PTD_ALL(float, true, false); else PTD_ALL(float, false, false);
         }
     }
-#undef PTD_LAUNCH
+#undef PTD_ALL
     return hipGetLastError();
 }
 

@@ -52,13 +52,13 @@ constexpr int high_logw()
 // ------------------------------------------------------------------------
 // single pass, n <= 10
 
-template <class V, int LOGN, bool REAL_OUT>
-__global__ __launch_bounds__(GROUP_THREADS) void k_group_fwd(const cplx<V>* __restrict__ A, int64_t lda,
-                                                             void* __restrict__ out, int64_t ldo)
+template <class V, int LOGN, bool REAL_OUT, int NT, int RMAX>
+__global__ __launch_bounds__(NT) void k_group_fwd(const cplx<V>* __restrict__ A, int64_t lda,
+                                                  void* __restrict__ out, int64_t ldo)
 {
     constexpr int LOGT = group_logt<V>(LOGN);
     __shared__ cplx<V> lds[(1 << LOGT) * ((1 << LOGN) + 1)];
-    group_fwd<V, LOGN, LOGT, REAL_OUT>(A, lda, out, ldo, blockIdx.x, lds);
+    group_fwd<V, LOGN, LOGT, REAL_OUT, NT, RMAX>(A, lda, out, ldo, blockIdx.x, lds);
 }
 
 template <class V, int LOGN, bool REAL_IN>
@@ -350,22 +350,36 @@ __global__ __launch_bounds__(TILE_THREADS) void k_small_comp(const cplx<V>* __re
 // ------------------------------------------------------------------------
 // dispatch over n (compile-time sizes)
 
-template <class V, bool HERM>
-hipError_t fwd_group(int n, const void* A, int64_t lda, void* out, hipStream_t st)
+template <class V, bool HERM, int NT, int RMAX>
+hipError_t fwd_group_plan(int n, const cplx<V>* a, int64_t lda, void* out, int64_t ldo, hipStream_t st)
 {
-    const cplx<V>* a = (const cplx<V>*)A;
-    const int64_t ldo = (int64_t)1 << n;
     const int logt = group_logt<V>(n);
-    const dim3 grid(1u << (n - logt)), block(GROUP_THREADS);
+    const dim3 grid(1u << (n - logt)), block(NT);
     switch (n) {
 #define PTD_CASE(NN) \
-    case NN: hipLaunchKernelGGL((k_group_fwd<V, NN, HERM>), grid, block, 0, st, a, lda, out, ldo); break;
+    case NN: hipLaunchKernelGGL((k_group_fwd<V, NN, HERM, NT, RMAX>), grid, block, 0, st, a, lda, out, ldo); break;
         PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5)
         PTD_CASE(6) PTD_CASE(7) PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
 #undef PTD_CASE
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// plan: see group.hpp (workgroup size, widest round); radix 32 is complex64 only
+template <class V, bool HERM>
+hipError_t fwd_group(int n, const void* A, int64_t lda, void* out, int plan, hipStream_t st)
+{
+    const cplx<V>* a = (const cplx<V>*)A;
+    const int64_t ldo = (int64_t)1 << n;
+    const bool big = group_plan_nt(plan) == 1024;
+    if constexpr (sizeof(V) == 4) {
+        if (group_effective_rmax(n, PTD_C64, plan) == 5)
+            return big ? fwd_group_plan<V, HERM, 1024, 5>(n, a, lda, out, ldo, st)
+                       : fwd_group_plan<V, HERM, 512, 5>(n, a, lda, out, ldo, st);
+    }
+    return big ? fwd_group_plan<V, HERM, 1024, 4>(n, a, lda, out, ldo, st)
+               : fwd_group_plan<V, HERM, 512, 4>(n, a, lda, out, ldo, st);
 }
 
 // stage: 3 = both passes, 1 = tile pass only, 2 = row pass only (timing)
@@ -454,12 +468,13 @@ hipError_t launch_dense_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64
     const bool two = path == 2 ? true : path == 1 ? false : n > 10;
     if (two && n < 7) return hipErrorInvalidValue;
     if (!two && n > 10) return hipErrorInvalidValue;
+    const int plan = two ? 0 : group_plan(n, dt, herm);
     if (dt == PTD_C128) {
         if (two) return herm ? fwd_two_pass<double, true>(n, A, lda, out, st) : fwd_two_pass<double, false>(n, A, lda, out, st);
-        return herm ? fwd_group<double, true>(n, A, lda, out, st) : fwd_group<double, false>(n, A, lda, out, st);
+        return herm ? fwd_group<double, true>(n, A, lda, out, plan, st) : fwd_group<double, false>(n, A, lda, out, plan, st);
     }
     if (two) return herm ? fwd_two_pass<float, true>(n, A, lda, out, st) : fwd_two_pass<float, false>(n, A, lda, out, st);
-    return herm ? fwd_group<float, true>(n, A, lda, out, st) : fwd_group<float, false>(n, A, lda, out, st);
+    return herm ? fwd_group<float, true>(n, A, lda, out, plan, st) : fwd_group<float, false>(n, A, lda, out, plan, st);
 }
 
 hipError_t launch_dense_fwd_stage(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out, int stage,

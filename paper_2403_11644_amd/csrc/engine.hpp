@@ -14,8 +14,8 @@
 // of the generalised diagonal d_x[k] = A[k][k ^ x].
 //
 // Kernels here hold a small set of vectors in LDS and run the WHT as rounds:
-// each round applies the radix-2 butterflies of up to 4 consecutive index
-// bits in registers (a radix-16 step per work item), reading its operands
+// each round applies the radix-2 butterflies of up to 5 consecutive index
+// bits in registers (a radix-16 or radix-32 step per work item), reading its operands
 // from a source functor and writing results to a destination functor (global
 // gather, LDS, or global store with the fused phase and scale).
 //
@@ -82,7 +82,7 @@ __device__ __forceinline__ void mul_ipow(int p, V& re, V& im)
 template <class V, int LOG_NV, int LOG_L, int B0, int NB, int NTHR, bool VEC_FAST, class Src, class Dst>
 __device__ __forceinline__ void wht_round(const Src& src, const Dst& dst)
 {
-    static_assert(NB >= 1 && NB <= 4, "radix 2..16 per round");
+    static_assert(NB >= 1 && NB <= 5, "radix 2..32 per round");
     static_assert(B0 + NB <= LOG_L, "round bits inside the vector");
     constexpr int R = 1 << NB;
     constexpr int NITEMS = 1 << (LOG_NV + LOG_L - NB);

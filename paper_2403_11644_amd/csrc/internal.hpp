@@ -78,18 +78,42 @@ void clear_fused_tuning();
 hipError_t autotune_fused(int n, ptd_dtype dt, bool herm, int reps, hipStream_t st, FusedTuning* best, float* best_ms,
                           int* tried, int* admitted);
 
+// Plan of the single-pass group kernel at (n, dtype, Hermitian), n <= 10
+// (group.hpp plan bits; tuned value if one was set, else the default).
+int group_plan(int n, ptd_dtype dt, bool herm);
+// Widest WHT round a plan gives size n: radix 32 only for complex64 and
+// n >= 6 (single calls and batched launches must agree, since the round
+// structure decides the rounding order).
+inline int group_effective_rmax(int n, ptd_dtype dt, int plan)
+{
+    return (dt == PTD_C64 && n >= 6 && (plan & 2)) ? 5 : 4;
+}
+int group_default_plan(int n, ptd_dtype dt, bool herm);
+bool get_group_tuning(int n, ptd_dtype dt, bool herm, int* plan);
+void set_group_tuning(int n, ptd_dtype dt, bool herm, int plan);
+hipError_t autotune_group(int n, ptd_dtype dt, bool herm, int reps, hipStream_t st, int* best, float* best_ms,
+                          int* tried, int* admitted);
+
 // Compute units of the current device (256 on MI355X) and its XCD count
 // (32 compute units per XCD; partitioned modes expose fewer).
 int device_cu_count();
 int device_xcd_count();
 
 // Batched single-pass launches over (matrix, group) items, n <= 10 each.
+constexpr size_t BATCH_HEAD_BYTES = 1024;  // queue counters, one 64-byte line per size
+struct BatchLaunch {
+    int nitems = 0;      // all items, largest sizes first
+    int begin[11] = {};  // items of size n: [begin[n], begin[n - 1]); begin[0] = nitems
+    int plan[11] = {};   // group plan per size (group.hpp)
+};
 int64_t batched_item_count(int count, ptd_dtype dt, const int32_t* n_host);
 size_t batched_buffer_bytes(int count, ptd_dtype dt, const int32_t* n_host);
-void batched_fill(int count, ptd_dtype dt, const int32_t* n_host, const int64_t* in_off, const int64_t* out_off,
-                  std::vector<unsigned char>& img, int* nitems_out);
+// force_plan >= 0 applies that group plan to every size (autotuning); -1
+// takes each size's tuned or default plan (forward only).
+void batched_fill(int count, ptd_dtype dt, bool herm, bool rec, const int32_t* n_host, const int64_t* in_off,
+                  const int64_t* out_off, std::vector<unsigned char>& img, BatchLaunch* bl, int force_plan = -1);
 hipError_t batched_launch(ptd_dtype dt, bool herm, bool rec, bool adjoint, const void* in_base, void* out_base,
-                          void* buf, int count, int nitems, int cus, hipStream_t st);
+                          void* buf, int count, const BatchLaunch& bl, int cus, hipStream_t st);
 
 // Parseval residual: out_host[0] = ||A||_F^2, [1] = 2^n sum|c|^2, [2] = relative gap.
 size_t reduce_workspace_bytes();

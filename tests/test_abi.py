@@ -146,7 +146,16 @@ def test_tuning_registry(lib):
     assert lib.ptd_get_tuning(14, 0, 0, ctypes.byref(cfg), ctypes.byref(la)) == 1
     assert (cfg.value, la.value) == (22, 4)
     assert lib.ptd_get_tuning(14, 0, 1, ctypes.byref(cfg), ctypes.byref(la)) == 0  # Hermitian is separate
-    assert lib.ptd_set_tuning(10, 0, 0, 22, 4) == -1  # single-pass sizes have nothing to tune
+    # single-pass sizes tune the group plan: 0..3 for complex64, 0..1 for complex128
+    assert lib.ptd_set_tuning(10, 0, 0, 22, 4) == -1
+    assert lib.ptd_set_tuning(10, 0, 0, 2, 0) == -1  # radix 32 is complex64 only
+    assert lib.ptd_set_tuning(10, 1, 1, 3, 0) == 0
+    assert lib.ptd_get_tuning(10, 1, 1, ctypes.byref(cfg), ctypes.byref(la)) == 1
+    assert (cfg.value, la.value) == (3, 0)
+    assert lib.ptd_get_tuning(10, 1, 0, ctypes.byref(cfg), ctypes.byref(la)) == 0  # default plan
+    assert cfg.value == 2  # radix-32 rounds at complex64 n = 10
+    assert lib.ptd_get_tuning(9, 0, 0, ctypes.byref(cfg), ctypes.byref(la)) == 0
+    assert cfg.value == 0
     assert lib.ptd_set_tuning(14, 0, 0, 99, 4) == -1
     assert lib.ptd_set_tuning(14, 0, 0, 22, 0) == -1
     assert lib.ptd_set_tuning(15, 0, 0, 1, 2) == -1  # complex128 n=15 runs the two-pass schedule

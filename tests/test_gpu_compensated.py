@@ -57,12 +57,12 @@ def test_compensated_hermitian(ptd, n):
 
 def test_compensated_n15_sampled(ptd, oracle_mod):
     """n = 15 complex64 (the largest measured size): compensated vs plain on
-    sampled coefficients against the float64 oracle, plus the float64
+    10^6 sampled coefficients against the float64 oracle, plus the float64
     Parseval residual of both."""
     n = 15
     A = synth.dense(n, seed=0, dtype=np.complex64)
     Ad = to_dev(A)
-    xs, zs = synth.sample_strings(n, 100000, seed=2)
+    xs, zs = synth.sample_strings(n, 1000000, seed=2)
     want = oracle_mod.coeffs(A, xs, zs)
     import torch
 

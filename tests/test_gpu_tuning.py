@@ -53,3 +53,37 @@ def test_autotune_n11(ptd, oracle_mod, tmp_path, monkeypatch, code, hermitian):
     xs, zs = synth.sample_strings(n, 2000, seed=4)
     assert rel_err(got[xs, zs], oracle_mod.coeffs(Af, xs, zs)) <= (1e-12 if code == 0 else 1e-5)
     L.ptd_clear_tuning()
+
+
+@pytest.mark.parametrize("code,hermitian,n", [(1, True, 10), (1, False, 9), (0, False, 10)])
+def test_autotune_group_plan(ptd, oracle_mod, code, hermitian, n):
+    """Sizes n <= 10 tune the group plan (workgroup size, radix) on a batch;
+    every plan is admitted only if bit-identical on integer input, and single
+    calls and batched launches keep agreeing bit for bit under the tuned plan
+    and under every other plan."""
+    import ctypes
+
+    from paper_2403_11644_amd import _native, tuning
+
+    L = _native.lib()
+    L.ptd_clear_tuning()
+    rec = tuning.autotune(n, code, hermitian=hermitian, reps=2, save=False)
+    assert rec["admitted"] == rec["candidates"] >= 1
+    assert rec["lookahead"] == 0
+    dt = np.complex128 if code == 0 else np.complex64
+    plans = [0, 1] + ([2, 3] if code == 1 else [])
+    mats = [synth.hermitian(n, seed=s, dtype=dt) if hermitian else synth.dense(n, seed=s, dtype=dt)
+            for s in range(3)]
+    dev = [to_dev(m) for m in mats]
+    for plan in plans:
+        assert L.ptd_set_tuning(n, code, 1 if hermitian else 0, plan, 0) == 0
+        batched = [to_host(c) for c in ptd.decompose_batched(dev, hermitian=hermitian)]
+        for m, d, b in zip(mats, dev, batched):
+            np.testing.assert_array_equal(to_host(ptd.decompose(d, hermitian=hermitian)), b)
+        want = oracle_mod.decompose(mats[0].astype(np.complex128))
+        if hermitian:
+            want = want.real
+        assert rel_err(batched[0], want) <= (1e-12 if code == 0 else 1e-5)
+    cfg, la = ctypes.c_int(), ctypes.c_int()
+    L.ptd_clear_tuning()
+    assert L.ptd_get_tuning(n, code, 1 if hermitian else 0, ctypes.byref(cfg), ctypes.byref(la)) == 0
