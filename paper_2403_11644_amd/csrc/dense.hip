@@ -49,6 +49,22 @@ constexpr int high_logw()
     return sizeof(V) == 4 ? 4 : 3;
 }
 
+// Row pass shape: 2^LOGW columns (128 bytes) per block.  Compensated mode
+// keeps hi and lo in LDS; it keeps whole 128-byte columns while both planes
+// fit (512 threads and one block per CU at LOGM = 9) and halves the columns
+// beyond that.
+template <class V, int LOGM, bool COMP>
+constexpr int row_logw()
+{
+    return (COMP && LOGM > 9) ? high_logw<V>() - 1 : high_logw<V>();
+}
+
+template <int LOGM, bool COMP>
+constexpr int row_threads()
+{
+    return (COMP && LOGM == 9) ? 512 : HIGH_THREADS;
+}
+
 // ------------------------------------------------------------------------
 // single pass, n <= 10
 
@@ -135,12 +151,11 @@ __global__ __launch_bounds__(TILE_THREADS) void k_tile_fwd(const cplx<V>* __rest
 // pass 2: WHT over the block index (stride 64) of each output row chunk,
 // then the phase and the scale.
 template <class V, int LOGM, bool HERM, bool COMP>
-__global__ __launch_bounds__(HIGH_THREADS) void k_high_fwd(void* __restrict__ out, int64_t ldo, int x0)
+__global__ __launch_bounds__((row_threads<LOGM, COMP>())) void k_high_fwd(void* __restrict__ out, int64_t ldo, int x0)
 {
-    // compensated mode keeps hi and lo in LDS: half as many columns per block
-    constexpr int LOGW = COMP ? high_logw<V>() - 1 : high_logw<V>();
+    constexpr int LOGW = row_logw<V, LOGM, COMP>();
     constexpr int CH = 6 - LOGW;
-    constexpr int NT = HIGH_THREADS;
+    constexpr int NT = row_threads<LOGM, COMP>();
     constexpr int PLANE = (1 << LOGW) * ((1 << LOGM) + 1);
     __shared__ cplx<V> lds[(COMP ? 2 : 1) * PLANE];
     const int x = x0 + (int)(blockIdx.x >> CH);
@@ -406,11 +421,14 @@ hipError_t fwd_two_pass(int n, const void* A, int64_t lda, void* out, hipStream_
             if (e != hipSuccess) return e;
         }
         if (!(stage & 2)) continue;
-        const dim3 g2((unsigned)(((int64_t)cnt * 64) << (6 - (COMP ? high_logw<V>() - 1 : high_logw<V>()))));
         const int x0 = xh0 * 64;
         switch (n - 6) {
-#define PTD_CASE(MM) \
-    case MM: hipLaunchKernelGGL((k_high_fwd<V, MM, HERM, COMP>), g2, dim3(HIGH_THREADS), 0, st, out, ldo, x0); break;
+#define PTD_CASE(MM)                                                                                              \
+    case MM:                                                                                                      \
+        hipLaunchKernelGGL((k_high_fwd<V, MM, HERM, COMP>),                                                       \
+                           dim3((unsigned)(((int64_t)cnt * 64) << (6 - row_logw<V, MM, COMP>()))),                \
+                           dim3(row_threads<MM, COMP>()), 0, st, out, ldo, x0);                                   \
+        break;
             PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5)
             PTD_CASE(6) PTD_CASE(7) PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
 #undef PTD_CASE
