@@ -171,7 +171,8 @@ hipError_t autotune_fused(int n, ptd_dtype dt, bool herm, int reps, hipStream_t 
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     // reference: the default setting
-    e = launch_fused_fwd(n, dt, herm, b.A, N, b.ref, b.ws, 3, 0, st);
+    const FusedTuning def = fused_default(n, dt, herm);
+    e = launch_fused_fwd(n, dt, herm, b.A, N, b.ref, b.ws, def.la, 0, st);
     if (e != hipSuccess) return e;
 
     std::vector<FusedTuning> cands;
@@ -179,7 +180,7 @@ hipError_t autotune_fused(int n, ptd_dtype dt, bool herm, int reps, hipStream_t 
     for (int sh : shapes) {
         if (n == 15 && sh != 1) continue;
         for (int opt : {4, 0, 4 | 8, 4 | 16, 4 | 8 | 16})
-            for (int la : {1, 2, 3, 4, 6}) cands.push_back(FusedTuning{sh | opt, la});
+            for (int la : {2, 3, 4, 6, 8, 12, 16}) cands.push_back(FusedTuning{sh | opt, la});
     }
     hipEvent_t e0, e1;
     if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
@@ -188,7 +189,7 @@ hipError_t autotune_fused(int n, ptd_dtype dt, bool herm, int reps, hipStream_t 
         return e;
     }
     float bestt = 1e30f;
-    FusedTuning bt{0, 3};
+    FusedTuning bt = def;
     int ntried = 0, nadmit = 0;
     for (const FusedTuning& c : cands) {
         // correctness first: bit-identical to the default on the integer matrix
