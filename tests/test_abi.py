@@ -178,3 +178,18 @@ def test_batched_argument_errors(lib):
     assert lib.ptd_batch_plan_create(2, 0, 1 << 6, *args, ctypes.byref(plan)) == -1
     assert lib.ptd_batch_plan_launch(None, None) == -1
     lib.ptd_batch_plan_destroy(None)
+
+
+def test_pad_to_power_of_two():
+    """Zero padding (Sec. II-A) embeds A top-left in the next 2^n square; the
+    host logic runs on CPU tensors too."""
+    import torch
+
+    from paper_2403_11644_amd import api
+
+    for shape, N in (((1, 1), 2), ((3, 3), 4), ((5, 7), 8), ((8, 8), 8), ((100, 64), 128)):
+        A = torch.arange(shape[0] * shape[1], dtype=torch.float64).reshape(shape).to(torch.complex128) + 1
+        P = api.pad_to_power_of_two(A)
+        assert P.shape == (N, N)
+        assert torch.equal(P[: shape[0], : shape[1]], A)
+        assert float(P.abs().sum()) == float(A.abs().sum())

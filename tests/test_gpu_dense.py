@@ -344,6 +344,25 @@ def test_fused_hermitian(ptd, oracle_mod, dt, n, cfg):
         np.testing.assert_array_equal(real[xs, zs], want.real)
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_hermitian_n13_float(ptd, oracle_mod, dt):
+    """The n = 13 Hermitian workload, (B + B^H)/2 with complex N(0, 1) B from
+    seed 0, through the public call: sampled strings against the oracle and
+    bit-identical to the real part of the general path."""
+    n = 13
+    A = synth.hermitian(n, seed=0, dtype=_np_dtype(dt))
+    Ad = to_dev(A)
+    real = ptd.decompose(Ad, hermitian=True)
+    full = ptd.decompose(Ad)
+    assert float(full.imag.abs().max()) == 0.0
+    assert bool((full.real == real).all())
+    del full
+    xs, zs = synth.sample_strings(n, 3000, seed=13)
+    want = oracle_mod.coeffs(A, xs, zs)
+    assert np.max(np.abs(want.imag)) <= 1e-12 * np.max(np.abs(want.real))
+    assert rel_err(to_host(real)[xs, zs], want.real) <= TOL[dt]
+
+
 def test_fused_n15_c64(ptd, oracle_mod):
     n = 15
     A = synth.dense(n, seed=0, dtype=np.complex64)
@@ -353,3 +372,22 @@ def test_fused_n15_c64(ptd, oracle_mod):
     want = oracle_mod.coeffs(A, xs, zs)
     g = to_host(got[to_dev(xs.astype(np.int64)), to_dev(zs.astype(np.int64))])
     assert rel_err(g, want) <= 1e-5
+
+
+@pytest.mark.parametrize("size", [3, 100, 1500])
+def test_pad_non_power_of_two(ptd, oracle_mod, size):
+    """pad=True: the coefficients are those of A embedded top-left in the
+    next 2^n zero matrix."""
+    rng = np.random.default_rng(size)
+    A = (rng.standard_normal((size, size)) + 1j * rng.standard_normal((size, size)))
+    got = to_host(ptd.decompose(to_dev(A), pad=True))
+    N = 1 << (size - 1).bit_length()
+    P = np.zeros((N, N), dtype=np.complex128)
+    P[:size, :size] = A
+    n = N.bit_length() - 1
+    if n <= 8:
+        want = oracle_mod.decompose(P)
+        assert rel_err(got, want) <= 1e-12
+    else:
+        xs, zs = synth.sample_strings(n, 3000, seed=1)
+        assert rel_err(got[xs, zs], oracle_mod.coeffs(P, xs, zs)) <= 1e-12

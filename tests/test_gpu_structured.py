@@ -66,11 +66,17 @@ def test_structured_vs_oracle(ptd, oracle_mod, dt, kind, n):
     mask = np.ones(1 << n, dtype=bool)
     mask[xs] = False
     assert np.all(full[mask] == 0)
-    if n <= 12:
-        # the general dense path agrees on the listed rows
-        dense = to_host(ptd.decompose(Ad))
-        assert rel_err(dense[xs], comp_dense_in) <= TOL[dt]
-        assert np.max(np.abs(dense[mask])) == 0.0
+    # the general dense path agrees on the listed rows and gives exact zeros
+    # elsewhere (compared on the device: the dense output is 4 GiB at n = 14)
+    import torch
+
+    dense = ptd.decompose(Ad)
+    ix = torch.tensor(xs, dtype=torch.int64, device=dense.device)
+    assert rel_err(to_host(dense.index_select(0, ix)), comp_dense_in) <= TOL[dt]
+    keep = torch.ones(1 << n, dtype=torch.bool, device=dense.device)
+    keep[ix] = False
+    assert float(dense[keep].abs().max()) == 0.0
+    del dense
 
 
 @pytest.mark.parametrize("n,s", [(6, 1), (8, 3), (11, 5), (12, 8)])
