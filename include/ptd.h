@@ -204,7 +204,10 @@ ptd_status ptd_parseval_residual(int n, ptd_dtype dtype, unsigned flags, const v
  * launches): cfg is the plan, bit 0 = 1024 threads per workgroup (else 512),
  * bit 1 = radix-32 WHT rounds (complex64 only; else radix 16); lookahead is
  * unused (0).  ptd_autotune times the plans on a batch of equal-size
- * matrices through the batched kernel.
+ * matrices through the batched kernel.  In a batch, matrices of n <= 7
+ * share one launch that runs a fixed plan, so for those sizes the plan
+ * reaches single calls only (and the tuner times plan 0 alone).  Every plan
+ * gives the same bits.
  *
  * n = 11..15, the single-launch schedule (complex128 for n <= 14): cfg holds
  * the workgroup shape and the cache policies of the gathers, the final

@@ -283,10 +283,11 @@ hipError_t autotune_group(int n, ptd_dtype dt, bool herm, int reps, hipStream_t 
         return e;
     }
     // plans that differ at this size: 1024-thread workgroups at n = 10 only,
-    // radix-32 rounds for complex64 at n >= 6 only
+    // radix-32 rounds for complex64 at n >= 6 only; the shared launch of the
+    // small sizes in a batch runs one fixed plan, so only plan 0 is timed there
     std::vector<int> cands{0};
     if (n == 10) cands.push_back(1);
-    if (dt == PTD_C64 && n >= 6) {
+    if (dt == PTD_C64 && n > BATCH_SMALL_MAX) {
         cands.push_back(2);
         if (n == 10) cands.push_back(3);
     }

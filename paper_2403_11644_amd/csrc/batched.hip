@@ -2,18 +2,20 @@
 //
 // Work items are (matrix, X-pattern group) pairs; each is the single-pass
 // group routine of group.hpp.  Items are listed largest matrices first
-// (longest-processing-time order).  Every size present gets one persistent
-// launch over its own contiguous range of items, taken from its own atomic
-// counter, so workgroups that finish items early keep pulling work and the
-// tail is short.  One launch per size gives each kernel the register budget
-// and LDS of its own size, hence its own occupancy (one 131 KiB workgroup per
-// CU at n = 10, two below), and lets the tuned plan of each size (workgroup
-// size, radix) apply.  The forward map and the reconstruction (with optional
+// (longest-processing-time order).  Every size from 8 to 10 present gets one
+// persistent launch over its own contiguous range of items, taken from its
+// own atomic counter, so workgroups that finish items early keep pulling work
+// and the tail is short.  One launch per size gives each kernel the register
+// budget and LDS of its own size, hence its own occupancy (one 131 KiB
+// workgroup per CU at n = 10, two below), and lets the tuned plan of each
+// size (workgroup size, radix) apply.  Sizes 1..7 share one launch of small
+// workgroups that stride over their items (k_batched_small).  The forward map and the reconstruction (with optional
 // 2^-n adjoint scale) share the kernel.  A batch plan captures all launches
 // in one graph.
 //
 // Workspace / plan buffer layout (bytes):
-//   [0, BATCH_HEAD_BYTES)   queue counters, one per size, 64 bytes apart
+//   [0, BATCH_HEAD_BYTES)   queue counters, index n for size n, 64 bytes
+//                           apart (only sizes 8..10 take them)
 //                           (zeroed by a kernel before each launch)
 //   [BATCH_HEAD_BYTES, ...) BatchMat[count] then BatchItem[items]
 #include <vector>
@@ -52,6 +54,63 @@ template <class V, int NN>
 constexpr int wgs_per_cu()
 {
     return (160 * 1024) / (group_lds_elems<V>(NN) * (int)sizeof(cplx<V>)) >= 2 ? 2 : 1;
+}
+
+// Sizes 1..SMALL_MAX share one launch (a switch per item) of one-wave
+// workgroups, SMALL_WGS of them per CU, each striding over the items.  An
+// item of these sizes moves at most 16 KiB: a launch per size would cost more
+// than its work, and a shared queue counter, one atomic round trip to the
+// memory side per item, more than the item itself (measured: 4096 Hermitian
+// complex64 matrices, the sizes <= 7 took 137 us through per-size queues and
+// 30 us this way).  Larger items keep the queues, whose balance pays there.
+constexpr int SMALL_MAX = BATCH_SMALL_MAX;
+constexpr int SMALL_NT = 64;
+constexpr int SMALL_WGS = 8;
+
+template <class V, int NN, bool HERM, bool REC>
+__device__ __forceinline__ void batched_item(const void* __restrict__ in_base, void* __restrict__ out_base,
+                                             const BatchMat& m, int g, int adjoint, cplx<V>* lds)
+{
+    constexpr int LOGT = group_logt<V>(NN);
+    constexpr int64_t N = (int64_t)1 << NN;
+    (void)adjoint;
+    if constexpr (!REC) {
+        const cplx<V>* A = (const cplx<V>*)in_base + m.in_off;
+        void* out = HERM ? (void*)((V*)out_base + m.out_off) : (void*)((cplx<V>*)out_base + m.out_off);
+        group_fwd<V, NN, LOGT, HERM, SMALL_NT, 4>(A, N, out, N, g, lds);
+    } else {
+        const void* C = HERM ? (const void*)((const V*)in_base + m.in_off)
+                             : (const void*)((const cplx<V>*)in_base + m.in_off);
+        cplx<V>* A = (cplx<V>*)out_base + m.out_off;
+        const V scale = adjoint ? exp2_neg<V>(NN) : (V)1;
+        group_rec<V, NN, LOGT, HERM, SMALL_NT>(C, A, N, scale, g, lds);
+    }
+}
+
+template <class V, bool HERM, bool REC>
+__global__ __launch_bounds__(SMALL_NT) void k_batched_small(const void* __restrict__ in_base, void* __restrict__ out_base,
+                                                       const BatchMat* __restrict__ mats,
+                                                       const BatchItem* __restrict__ items, int begin, int end,
+                                                       int adjoint)
+{
+    // static round-robin; the list is sorted by size, so striding hands every
+    // workgroup a like mix
+    __shared__ cplx<V> lds[group_lds_elems<V>(SMALL_MAX)];
+    for (int i = begin + (int)blockIdx.x; i < end; i += (int)gridDim.x) {
+        const BatchItem it = items[i];
+        const BatchMat m = mats[it.mat];
+        switch (m.n) {
+            case 1: batched_item<V, 1, HERM, REC>(in_base, out_base, m, (int)it.group, adjoint, lds); break;
+            case 2: batched_item<V, 2, HERM, REC>(in_base, out_base, m, (int)it.group, adjoint, lds); break;
+            case 3: batched_item<V, 3, HERM, REC>(in_base, out_base, m, (int)it.group, adjoint, lds); break;
+            case 4: batched_item<V, 4, HERM, REC>(in_base, out_base, m, (int)it.group, adjoint, lds); break;
+            case 5: batched_item<V, 5, HERM, REC>(in_base, out_base, m, (int)it.group, adjoint, lds); break;
+            case 6: batched_item<V, 6, HERM, REC>(in_base, out_base, m, (int)it.group, adjoint, lds); break;
+            case 7: batched_item<V, 7, HERM, REC>(in_base, out_base, m, (int)it.group, adjoint, lds); break;
+            default: break;
+        }
+        __syncthreads();  // LDS reuse
+    }
 }
 
 // Items [begin, end) of size-NN matrices.
@@ -104,8 +163,10 @@ void launch_size(const void* in_base, void* out_base, const BatchMat* mats, cons
                  uint32_t* counter, int adj, int cus, hipStream_t st)
 {
     const int per_cu = NT == 512 ? wgs_per_cu<V, NN>() : 1;
-    hipLaunchKernelGGL((k_batched<V, NN, HERM, REC, NT, RMAX>), dim3(cus * per_cu), dim3(NT), 0, st, in_base,
-                       out_base, mats, its, begin, end, counter, adj);
+    // persistent: every resident workgroup slot, but no more than there are items
+    const int grid = cus * per_cu < end - begin ? cus * per_cu : end - begin;
+    hipLaunchKernelGGL((k_batched<V, NN, HERM, REC, NT, RMAX>), dim3(grid), dim3(NT), 0, st, in_base, out_base,
+                       mats, its, begin, end, counter, adj);
 }
 
 // The plan of size NN: 1024-thread workgroups only at n = 10 (where one
@@ -144,7 +205,16 @@ template <class V, bool HERM, bool REC>
 void launch_all(const BatchLaunch& bl, const void* in_base, void* out_base, const BatchMat* mats,
                 const BatchItem* its, uint32_t* counters, int adj, int cus, hipStream_t st)
 {
-    for (int n = 10; n >= 1; --n) {
+    {
+        // sizes 1..SMALL_MAX are contiguous at the end of the list
+        const int b = bl.begin[SMALL_MAX], e = bl.begin[0];
+        if (e > b) {
+            const int cap = SMALL_WGS * cus;
+            hipLaunchKernelGGL((k_batched_small<V, HERM, REC>), dim3(e - b < cap ? e - b : cap), dim3(SMALL_NT), 0, st,
+                               in_base, out_base, mats, its, b, e, adj);
+        }
+    }
+    for (int n = 10; n > SMALL_MAX; --n) {
         const int b = bl.begin[n], e = bl.begin[n - 1];
         if (e <= b) continue;
         uint32_t* c = counters + n * COUNTER_STRIDE;
@@ -154,8 +224,7 @@ void launch_all(const BatchLaunch& bl, const void* in_base, void* out_base, cons
     case NN:                                                                                            \
         launch_size_plan<V, NN, HERM, REC>(plan, in_base, out_base, mats, its, b, e, c, adj, cus, st); \
         break;
-            PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5)
-            PTD_CASE(6) PTD_CASE(7) PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
+            PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
 #undef PTD_CASE
             default: break;
         }

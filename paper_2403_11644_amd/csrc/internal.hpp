@@ -101,6 +101,7 @@ int device_xcd_count();
 
 // Batched single-pass launches over (matrix, group) items, n <= 10 each.
 constexpr size_t BATCH_HEAD_BYTES = 1024;  // queue counters, one 64-byte line per size
+constexpr int BATCH_SMALL_MAX = 7;  // sizes 1..7 share one batched launch that ignores the group plan
 struct BatchLaunch {
     int nitems = 0;      // all items, largest sizes first
     int begin[11] = {};  // items of size n: [begin[n], begin[n - 1]); begin[0] = nitems
