@@ -54,23 +54,29 @@ hipError_t launch_zero_words(uint32_t* p, int count, hipStream_t st)
 
 FusedTuning fused_default(int n, ptd_dtype dt, bool herm)
 {
-    // The fastest settings measured on MI355X.  Shape: 512-thread workgroups
-    // with 512-row phase-1 items up to n = 14, 1024-thread ones at n = 15.
-    // Cache policy: non-temporal gathers, final stores and phase-2 loads,
-    // except complex128 at n = 14, where phase-2 loads stay cached.
-    // Lookahead: deep enough that phase-2 items rarely wait for their group
-    // (the 64 workgroups of an XCD hold more groups' items at small n).
-    FusedTuning t{0, 4};
-    const int shape = n <= 14 ? 2 : 1;
-    t.cfg = (dt == PTD_C128 && n == 14) ? (shape | 4 | 8) : (shape | 4 | 8 | 16);
+    // The fastest settings the autotuner found on MI355X (cfg: shape | POL
+    // bits, see fused_dispatch; la: queue lookahead in groups).  1024-thread
+    // workgroups with 1024-row phase-1 items (shape 1) win at n <= 12 and for
+    // Hermitian input, 512-thread ones (shape 2) for dense n = 13, 14;
+    // non-temporal gathers and final stores almost everywhere.  The
+    // lookahead is deep enough that phase-2 items rarely wait for their
+    // group (an XCD's workgroups hold more groups' items at small n).
+    const bool c128 = dt == PTD_C128;
     switch (n) {
-        case 11: t.la = 16; break;
-        case 12: t.la = 12; break;
-        case 13: t.la = 8; break;
-        case 14: t.la = (dt == PTD_C128 && !herm) ? 4 : 6; break;
-        default: t.la = 4; break;
+        case 11:
+            return c128 && !herm ? FusedTuning{29, 16} : FusedTuning{1, 16};
+        case 12:
+            if (c128) return herm ? FusedTuning{29, 12} : FusedTuning{29, 16};
+            return FusedTuning{1, 8};
+        case 13:
+            if (herm) return c128 ? FusedTuning{13, 8} : FusedTuning{29, 6};
+            return FusedTuning{30, 8};
+        case 14:
+            if (herm) return c128 ? FusedTuning{30, 6} : FusedTuning{29, 12};
+            return c128 ? FusedTuning{14, 4} : FusedTuning{30, 6};
+        default:
+            return FusedTuning{29, 4};
     }
-    return t;
 }
 
 size_t fused_workspace_bytes(int n, ptd_dtype dt)

@@ -325,8 +325,8 @@ def test_fused_integer_exact(ptd, oracle_mod, dt, n):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("n,cfg", [(11, 0), (11, 3), (12, 26), (13, 0), (13, 1), (13, 31), (14, 0), (14, 7),
-                                   (14, 22)])
+@pytest.mark.parametrize("n,cfg", [(11, 0), (11, 3), (12, 26), (12, 29), (13, 0), (13, 1), (13, 13), (13, 31),
+                                   (14, 0), (14, 7), (14, 22)])
 def test_fused_hermitian(ptd, oracle_mod, dt, n, cfg):
     re, im = synth.gaussian_int_hermitian(n, seed=1)
     A = to_dev(synth.int_to_complex(re, im, _np_dtype(dt)))
