@@ -124,6 +124,29 @@ def _time(fn, steps: int, warmup: int, stream) -> float:
     return t0.elapsed_time(t1) / steps  # ms
 
 
+def _call_us(fn, reps: int, warmup: int, stream, before=None) -> float:
+    """Median over `reps` single calls of the device time from an event before
+    the call to one after it, in microseconds; `before` runs ahead of each
+    call (outside the two events), on the same stream."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    out = []
+    for _ in range(reps):
+        if before is not None:
+            before()
+        t0.record(stream)
+        fn()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        out.append(t0.elapsed_time(t1) * 1e3)
+    return float(np.median(out))
+
+
 def _rel(g, w) -> float:
     return float(np.linalg.norm(g - w) / np.linalg.norm(w))
 
@@ -137,7 +160,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="all",
                     help="comma list of reported legs to run: complex64, two_pass, copy, reconstruct, parseval, "
-                         "hermitian, band, n15, batched; 'all' or 'none'")
+                         "small, hermitian, band, n15, batched; 'all' or 'none'")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc folders (FETCH_SIZE, WRITE_SIZE) "
@@ -196,8 +219,8 @@ def main() -> int:
     legs = {}
     want_legs = set()
     if args.legs == "all":
-        want_legs = {"complex64", "two_pass", "copy", "reconstruct", "parseval", "hermitian", "band", "n15",
-                     "batched"}
+        want_legs = {"complex64", "two_pass", "copy", "reconstruct", "parseval", "small", "hermitian", "band",
+                     "n15", "batched"}
     elif args.legs != "none":
         want_legs = set(args.legs.split(","))
     if "reconstruct" in want_legs:
@@ -256,39 +279,100 @@ def main() -> int:
         del cpy
         torch.cuda.empty_cache()
     g = torch.Generator(device=dev)
+    if "small" in want_legs:
+        # n = 8 dense complex128 (65,536 coefficients): latency of one call,
+        # warm and after a 1 GiB write that evicts A from the L2 and the
+        # memory-side cache; every coefficient against the oracle
+        n8 = 8
+        N8 = 1 << n8
+        A8_host = synth.dense(n8, seed=0)
+        A8 = torch.from_numpy(A8_host).to(dev)
+        o8 = torch.empty_like(A8)
+        flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+
+        def run8():
+            _native.check(L.pauli_decompose(n8, api.C128, 0, 0, api._ptr(A8), N8, api._ptr(o8), None, 0, sh),
+                          "pauli_decompose")
+
+        warm8 = _call_us(run8, 20, 5, stream)
+        cold8 = _call_us(run8, 10, 2, stream, before=lambda: flush.fill_(1))
+        run8()
+        torch.cuda.synchronize()
+        legs["n8_c128"] = {"warm_us": round(warm8, 2), "cold_us": round(cold8, 2),
+                           "err_rel_all_vs_oracle": _rel(o8.cpu().numpy(), O.decompose(A8_host))}
+        del A8, o8, flush
     if "hermitian" in want_legs:
-        # n = 13 Hermitian complex128 -> real float64 (device-generated input)
+        # n = 13 Hermitian A = (B + B^H)/2 (device-generated B): the Hermitian
+        # path (real output, reads one element of each mirrored pair) and the
+        # dense path on the same matrix, in complex128 and in a complex64 cast
         g.manual_seed(13)
         B = torch.randn((1 << 13, 1 << 13), dtype=torch.complex128, device=dev, generator=g)
         H = (B + B.conj().T) / 2
         del B
+        xs13, zs13 = synth.sample_strings(13, 2000, seed=7)
+        want13 = O.coeffs(H.cpu().numpy(), xs13, zs13)
+        ix13 = torch.from_numpy(xs13.astype(np.int64)).to(dev)
+        iz13 = torch.from_numpy(zs13.astype(np.int64)).to(dev)
         hout = torch.empty((1 << 13, 1 << 13), dtype=torch.float64, device=dev)
         msh = _time(lambda: ptd.decompose(H, hermitian=True, out=hout), 10, 3, stream)
+        errh = _rel(hout[ix13, iz13].cpu().numpy(), want13.real)
+        dout = torch.empty_like(H)
+        msd = _time(lambda: ptd.decompose(H, out=dout), 10, 3, stream)
+        im_max = float(dout.imag.abs().max())
+        del dout, hout
         # bytes the method needs: one element of each mirrored pair of A (half
         # of it) plus the real output
         legs["hermitian_n13_f64"] = {"ms": round(msh, 4), "GCoeff_s": round(4.0 ** 13 / msh / 1e6, 2),
                                      "path_hbm_frac": round(_herm_bytes(13, 16) / (msh * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-                                                            4)}
+                                                            4),
+                                     "err_rel_sampled": errh, "dense_path_ms": round(msd, 4),
+                                     "dense_path_max_abs_im": im_max}
         H32 = H.to(torch.complex64)
-        del H, hout
+        del H
         hout32 = torch.empty((1 << 13, 1 << 13), dtype=torch.float32, device=dev)
         msh32 = _time(lambda: ptd.decompose(H32, hermitian=True, out=hout32), 10, 3, stream)
+        errh32 = _rel(hout32[ix13, iz13].cpu().numpy().astype(np.float64), want13.real)
+        dout32 = torch.empty_like(H32)
+        msd32 = _time(lambda: ptd.decompose(H32, out=dout32), 10, 3, stream)
         legs["hermitian_n13_f32"] = {"ms": round(msh32, 4), "GCoeff_s": round(4.0 ** 13 / msh32 / 1e6, 2),
                                      "path_hbm_frac": round(_herm_bytes(13, 8) / (msh32 * 1e-3) / 1e9 / HBM_PEAK_GBPS,
                                                             4),
-                                     "speedup_vs_f64": round(msh / msh32, 2)}
-        del H32, hout32
+                                     "speedup_vs_f64": round(msh / msh32, 2),
+                                     "err_rel_sampled_vs_f64_oracle": errh32, "dense_path_ms": round(msd32, 4)}
+        del H32, hout32, dout32
+        torch.cuda.empty_cache()
     if "band" in want_legs:
-        # n = 14 complex band, half-bandwidth 8: skip path from bands vs dense
-        band = synth.banded_complex(n, 8, seed=2)
-        bd = torch.from_numpy(band).to(dev)
-        cnt = ptd.num_nonempty_x(n, "banded", 8)
-        bout = torch.empty((cnt, N), dtype=torch.complex128, device=dev)
-        msb = _time(lambda: ptd.decompose(bd, structure="banded", s=8, bands=True, compact=True, out=bout), 10, 3,
-                    stream)
-        legs["band8_n14_skip"] = {"ms": round(msb, 4), "nonempty_x": cnt,
-                                  "speedup_vs_dense_f64": round(ms128 / msb, 1)}
-        del bd, bout
+        # n = 14 structured inputs: the skip path over the nonempty X-patterns
+        # only (1 / 15 / 96 of 16384), from compressed bands with compact
+        # output, and for s = 8 also from the dense matrix (reading only the
+        # band) with compact and with zero-filled dense output
+        wsd = torch.empty(16, dtype=torch.uint8, device=dev)
+
+        def skip_call(src, flags, s_, out, lda):
+            wsb_ = L.ptd_workspace_bytes(n, api.C128, flags, s_)
+            assert wsb_ <= wsd.numel()
+            return lambda: _native.check(L.pauli_decompose(n, api.C128, flags, s_, api._ptr(src), lda, api._ptr(out),
+                                                           api._ptr(wsd), wsb_, sh), "pauli_decompose")
+
+        band_legs = {}
+        for name, s_, arr in (("diag", 0, synth.bands_from_diag(synth.diagonal_real(n, seed=0))),
+                              ("tridiag", 1, synth.bands_from_tridiag(*synth.tridiag_real_sym(n, seed=1))),
+                              ("band8", 8, synth.banded_complex(n, 8, seed=2))):
+            flags = (api.DIAGONAL if s_ == 0 else api.BANDED) | api.BANDS_IN | api.COMPACT
+            cnt = ptd.num_nonempty_x(n, "diagonal" if s_ == 0 else "banded", s_)
+            bd = torch.from_numpy(arr).to(dev)
+            bout = torch.empty((cnt, N), dtype=torch.complex128, device=dev)
+            us = _call_us(skip_call(bd, flags, s_, bout, N), 20, 5, stream)
+            band_legs[name] = {"s": s_, "nonempty_x": cnt, "from_bands_compact_us": round(us, 2)}
+            if s_ == 8:
+                fl = api.BANDED | api.COMPACT
+                us_dc = _call_us(skip_call(A, fl, 8, bout, N), 20, 5, stream)
+                us_dd = _call_us(skip_call(A, api.BANDED, 8, out128, N), 10, 3, stream)
+                band_legs[name].update({"from_dense_compact_us": round(us_dc, 2),
+                                        "from_dense_zero_filled_us": round(us_dd, 2),
+                                        "speedup_vs_dense_f64": round(ms128 * 1e3 / us, 1)})
+            del bd, bout
+        legs["structured_n14"] = band_legs
     if "n15" in want_legs:
         # n = 15 complex64, plain and compensated butterflies
         g.manual_seed(15)
