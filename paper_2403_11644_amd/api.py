@@ -285,9 +285,12 @@ def _out_layout(ns, odt, device):
 def decompose_batched(mats, *, hermitian: bool = False, stream=None):
     """Decompose a list of square GPU matrices (n <= 10 each) in one launch.
 
-    Returns a list of coefficient tensors (views of one packed buffer)."""
+    Returns a list of coefficient tensors (views of one packed buffer); an
+    empty list gives an empty list."""
     import numpy as np
 
+    if len(mats) == 0:
+        return []
     base, in_offs, ns = _batch_layout(mats)
     code = _dtype_code(mats[0].dtype)
     odt = _real_dtype(code) if hermitian else _complex_dtype(code)

@@ -193,3 +193,11 @@ def test_pad_to_power_of_two():
         assert P.shape == (N, N)
         assert torch.equal(P[: shape[0], : shape[1]], A)
         assert float(P.abs().sum()) == float(A.abs().sum())
+
+
+def test_empty_batch():
+    """An empty list of matrices decomposes to an empty list, before any
+    device call; the C entry points reject count < 1."""
+    from paper_2403_11644_amd import api
+
+    assert api.decompose_batched([]) == []

@@ -391,3 +391,44 @@ def test_pad_non_power_of_two(ptd, oracle_mod, size):
     else:
         xs, zs = synth.sample_strings(n, 3000, seed=1)
         assert rel_err(got[xs, zs], oracle_mod.coeffs(P, xs, zs)) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# the largest size the library takes: n = 16, 2^32 elements per matrix
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_max_size_n16_strings(ptd, oracle_mod, dt):
+    """A = 3 P1 - 5 P2 + 0.5 P3 at n = 16 (the sparse forms of the three
+    strings come from the oracle's PauliComposer and are scattered into a
+    zero matrix on the device).  Theorem 1: the coefficients are exactly
+    those three numbers at those three strings and zero elsewhere (every
+    partial sum is a small multiple of the scalar, exact in either
+    precision), and the reconstruction returns exactly the scattered
+    entries.  Offsets past 2^31 elements are exercised throughout."""
+    import torch
+
+    n, N = 16, 1 << 16
+    tdt = torch.complex128 if dt == "c128" else torch.complex64
+    strings = [(0xBEEF, 0x1234, 3.0), (0x8001, 0xFFFF, -5.0), (0x0000, 0x7A5C, 0.5)]
+    rows = torch.arange(N, device="cuda")
+    sparse = []
+    A = torch.zeros((N, N), dtype=tdt, device="cuda")
+    for x, z, alpha in strings:
+        k, m = oracle_mod.pauli_sparse(oracle_mod.label(x, z, n))
+        assert np.array_equal(k, np.arange(N) ^ x)
+        kd, md = to_dev(k), to_dev(alpha * m, tdt)
+        A[rows, kd] = md  # distinct X-patterns: no two strings share an entry
+        sparse.append((kd, md))
+    c = ptd.decompose(A)
+    del A
+    torch.cuda.synchronize()
+    for x, z, alpha in strings:
+        assert complex(c[x, z].item()) == alpha
+    assert int((c != 0).sum().item()) == len(strings)
+    R = ptd.reconstruct(c)
+    del c
+    for kd, md in sparse:
+        assert bool(torch.equal(R[rows, kd], md))
+    assert int((R != 0).sum().item()) == len(strings) * N
+    del R, rows
+    torch.cuda.empty_cache()
