@@ -164,6 +164,26 @@ def _call_us(fn, reps: int, warmup: int, stream, before=None) -> float:
     return float(np.median(out))
 
 
+# Vector FP32 adds per second without packed math or FMA: 256 CUs x 4 SIMDs
+# x 16 lanes x 2.4 GHz (the 157.3 TFLOP/s FP32 peak counts an FMA as two
+# flops and a packed instruction as two).
+FP32_ADD_PEAK = 256 * 4 * 16 * 2.4e9
+
+
+def _comp_roofline(n: int, ms: float) -> dict:
+    """Compensated (TwoSum) butterflies are bound by vector adds.  Per complex
+    element: 16 adds per radix-2 stage (per real part two TwoSums of 6 adds
+    for the sum and the difference, plus 2 adds on the low parts, over a
+    pair of outputs), and 12 per renormalisation (two TwoSums) after each
+    register round: the two-pass schedule runs rounds of 4 + 2 bits in the
+    tile pass and 4 + 4 + (n - 14) in the row pass at n = 15."""
+    rounds = 2 + 3
+    adds = (16 * n + 12 * rounds) * 4.0 ** n
+    achieved = adds / (ms * 1e-3)
+    return {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(FP32_ADD_PEAK / 1e12, 2),
+            "unit": "Tadd/s", "frac": round(achieved / FP32_ADD_PEAK, 4)}
+
+
 def _rel(g, w) -> float:
     return float(np.linalg.norm(g - w) / np.linalg.norm(w))
 
@@ -412,6 +432,7 @@ def main() -> int:
         legs["n15_c64"] = {"ms": round(ms15, 4), "GCoeff_s": round(4.0 ** 15 / ms15 / 1e6, 2),
                            "path_hbm_frac": round(16 * 4.0 ** 15 / (ms15 * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
                            "compensated_ms": round(ms15c, 4),
+                           "compensated_roofline": _comp_roofline(15, ms15c),
                            "err_rel_1e6_sampled_vs_f64_oracle": {"plain": _rel(got_plain, want15),
                                                                  "compensated": _rel(got_comp, want15)}}
         torch.cuda.empty_cache()
