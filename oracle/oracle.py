@@ -280,3 +280,61 @@ def band_term_bound(n: int, s: int) -> int:
     L = int(np.floor(np.log2(s)))
     c = s * (L + 1) - 2 ** (L + 1)
     return (s * n - c) * (1 << n)
+
+
+# --------------------------------------------------------------------------
+# combinations of decompositions (Sec. IV-B), from the coefficients alone
+
+def direct_sum(ca: np.ndarray, cb: np.ndarray) -> np.ndarray:
+    """Coefficients of A (+) B = [[A, 0], [0, B]] on n + 1 qubits (Sec. IV-B,
+    "Direct sum"): C = I (x) (A + B)/2 + Z (x) (A - B)/2, the new factor on the
+    left, i.e. the most significant qubit.  In the (x, z) layout its I is
+    (x_n, z_n) = (0, 0) and its Z is (0, 1); X and Y do not occur."""
+    ca = np.asarray(ca)
+    cb = np.asarray(cb)
+    N = ca.shape[0]
+    out = np.zeros((2 * N, 2 * N), dtype=np.result_type(ca, cb))
+    out[:N, :N] = (ca + cb) / 2
+    out[:N, N:] = (ca - cb) / 2
+    return out
+
+
+def block_diagonal(blocks) -> np.ndarray:
+    """Coefficients of diag(A_1, ..., A_N), N = 2^m blocks of one size, by the
+    recursion of Sec. IV-B ("Block-diagonal matrices"): neighbouring blocks are
+    joined two by two with direct_sum, then the results two by two again,
+    ((A_1 (+) A_2) (+) (A_3 (+) A_4)) (+) ..., until one matrix remains."""
+    level = [np.asarray(b) for b in blocks]
+    if len(level) < 2 or len(level) & (len(level) - 1):
+        raise ValueError("need a power-of-two number (>= 2) of blocks")
+    while len(level) > 1:
+        level = [direct_sum(level[i], level[i + 1]) for i in range(0, len(level), 2)]
+    return level[0]
+
+
+def hermitian_augment(c: np.ndarray) -> np.ndarray:
+    """Real coefficients of [[0, A^H], [A, 0]] on n + 1 qubits (Sec. IV-B,
+    "Hermitian matrix augmentation"): X (x) sum a_j P_j + Y (x) sum b_j P_j with
+    a_j, b_j the real and imaginary parts of A's coefficients.  The new factor
+    is the most significant qubit: X is (x_n, z_n) = (1, 0), Y is (1, 1)."""
+    c = np.asarray(c)
+    N = c.shape[0]
+    out = np.zeros((2 * N, 2 * N), dtype=c.real.dtype)
+    out[N:, :N] = c.real
+    out[N:, N:] = c.imag
+    return out
+
+
+def linear_combination(mu: complex, ca: np.ndarray, cb: np.ndarray) -> np.ndarray:
+    """Coefficients of mu A + B (Sec. IV-B, "Linear combination"): mu c_A + c_B,
+    elementwise, in the precision of the arrays (mu rounded to it), each part
+    rounded as re = (mu_re a_re - mu_im a_im) + b_re, im = (mu_re a_im +
+    mu_im a_re) + b_im."""
+    ca = np.asarray(ca)
+    cb = np.asarray(cb)
+    rt = ca.real.dtype
+    mr, mi = rt.type(complex(mu).real), rt.type(complex(mu).imag)
+    out = np.empty_like(ca)
+    out.real = (mr * ca.real - mi * ca.imag) + cb.real
+    out.imag = (mr * ca.imag + mi * ca.real) + cb.imag
+    return out

@@ -262,19 +262,62 @@ def test_kronecker_factorisation(oracle_mod):
     np.testing.assert_allclose(cAB, np.kron(cA, cB), rtol=0, atol=1e-14)
 
 
+def _embed(blocks):
+    """diag(blocks...) as a dense matrix."""
+    N = blocks[0].shape[0]
+    M = np.zeros((N * len(blocks), N * len(blocks)), dtype=np.complex128)
+    for i, b in enumerate(blocks):
+        M[i * N:(i + 1) * N, i * N:(i + 1) * N] = b
+    return M
+
+
 def test_direct_sum(oracle_mod):
+    # the identity of Sec. IV-B (oracle.direct_sum) against the definition on
+    # the assembled matrix
     n = 3
     A = synth.dense(n, seed=42)
     B = synth.dense(n, seed=43)
     N = 1 << n
-    C = np.zeros((2 * N, 2 * N), dtype=np.complex128)
-    C[:N, :N] = A
-    C[N:, N:] = B
-    cA, cB, cC = (oracle_mod.decompose(M) for M in (A, B, C))
+    cA, cB, cC = (oracle_mod.decompose(M) for M in (A, B, _embed([A, B])))
+    got = oracle_mod.direct_sum(cA, cB)
+    np.testing.assert_allclose(got, cC, rtol=0, atol=1e-15)
     # I (x) (a+b)/2 + Z (x) (a-b)/2; the new qubit is the most significant one
     np.testing.assert_allclose(cC[:N, :N], (cA + cB) / 2, atol=1e-15)
     np.testing.assert_allclose(cC[:N, N:], (cA - cB) / 2, atol=1e-15)
-    assert np.all(cC[N:, :] == 0)
+    assert np.all(cC[N:, :] == 0) and np.all(got[N:, :] == 0)
+
+
+@pytest.mark.parametrize("nblocks,k", [(2, 2), (4, 2), (8, 2), (8, 1), (32, 1)])
+def test_block_diagonal_exact(oracle_mod, nblocks, k):
+    # the paper's N = 8 example and others: pairwise direct sums of the
+    # blocks' coefficients equal the decomposition of the assembled matrix,
+    # exactly for Gaussian-integer blocks (2^(k+m) c is an integer)
+    blocks_int = [synth.gaussian_int(k, seed=60 + i) for i in range(nblocks)]
+    blocks = [synth.int_to_complex(re, im) for re, im in blocks_int]
+    cs = [oracle_mod.decompose(b) for b in blocks]
+    got = oracle_mod.block_diagonal(cs)
+    M = _embed(blocks)
+    re, im = oracle_mod.decompose_int(M.real.astype(np.int64), M.imag.astype(np.int64))
+    scale = float(M.shape[0])
+    np.testing.assert_array_equal(got.real * scale, re.astype(np.float64))
+    np.testing.assert_array_equal(got.imag * scale, im.astype(np.float64))
+
+
+def test_block_diagonal_is_a_transform_over_the_block_index(oracle_mod):
+    # unrolled, the recursion is c'[x][(t << k) | z] = 2^-m sum_i
+    # (-1)^popcount(t & i) c_i[x][z] (a Sylvester Hadamard transform over i,
+    # scipy.linalg.hadamard), rows x >= 2^k zero
+    from scipy.linalg import hadamard
+
+    k, m = 2, 3
+    K = 1 << k
+    cs = [synth.complex_normal((K, K), seed=70 + i) for i in range(1 << m)]
+    got = oracle_mod.block_diagonal(cs)
+    H = hadamard(1 << m)
+    stack = np.stack(cs)                          # [i][x][z]
+    want = np.einsum("ti,ixz->xtz", H, stack) / (1 << m)
+    np.testing.assert_allclose(got[:K].reshape(K, 1 << m, K), want, rtol=0, atol=1e-15)
+    assert np.all(got[K:] == 0)
 
 
 def test_hermitian_augmentation(oracle_mod):
@@ -287,6 +330,8 @@ def test_hermitian_augmentation(oracle_mod):
     cA = oracle_mod.decompose(A)
     cT = oracle_mod.decompose(At)
     # X (x) Re(alpha) + Y (x) Im(alpha)
+    np.testing.assert_allclose(oracle_mod.hermitian_augment(cA), cT.real, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(cT.imag, 0, atol=1e-15)
     np.testing.assert_allclose(cT[N:, :N], cA.real, atol=1e-15)
     np.testing.assert_allclose(cT[N:, N:], cA.imag, atol=1e-15)
     assert np.all(cT[:N, :] == 0)
@@ -297,6 +342,11 @@ def test_linearity(oracle_mod):
     A = synth.dense(n, seed=45)
     B = synth.dense(n, seed=46)
     mu = 0.3 - 1.7j
-    np.testing.assert_allclose(oracle_mod.decompose(mu * A + B),
-                               mu * oracle_mod.decompose(A) + oracle_mod.decompose(B),
+    cA, cB = oracle_mod.decompose(A), oracle_mod.decompose(B)
+    np.testing.assert_allclose(oracle_mod.decompose(mu * A + B), mu * cA + cB, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(oracle_mod.linear_combination(mu, cA, cB), oracle_mod.decompose(mu * A + B),
                                rtol=0, atol=1e-13)
+    # float32 arrays stay float32, with mu rounded to it
+    got32 = oracle_mod.linear_combination(mu, cA.astype(np.complex64), cB.astype(np.complex64))
+    assert got32.dtype == np.complex64
+    np.testing.assert_allclose(got32, mu * cA + cB, rtol=0, atol=1e-5)
