@@ -197,7 +197,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="all",
                     help="comma list of reported legs to run: complex64, two_pass, copy, reconstruct, parseval, "
-                         "small, hermitian, band, n15, batched; 'all' or 'none'")
+                         "small, hermitian, band, algebra, n15, batched; 'all' or 'none'")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc folders (FETCH_SIZE, WRITE_SIZE) "
@@ -258,7 +258,7 @@ def main() -> int:
     want_legs = set()
     if args.legs == "all":
         want_legs = {"complex64", "two_pass", "copy", "reconstruct", "parseval", "small", "hermitian", "band",
-                     "n15", "batched"}
+                     "algebra", "n15", "batched"}
     elif args.legs != "none":
         want_legs = set(args.legs.split(","))
     if "reconstruct" in want_legs:
@@ -411,6 +411,42 @@ def main() -> int:
                                         "speedup_vs_dense_f64": round(ms128 * 1e3 / us, 1)})
             del bd, bout
         legs["structured_n14"] = band_legs
+    if "algebra" in want_legs:
+        # Sec. IV-B combinations on coefficient arrays: one HBM pass each
+        # (bytes = inputs read once + output written once)
+        n13 = 13
+        N13 = 1 << n13
+        g.manual_seed(131)
+        ca = torch.randn((N13, N13), dtype=torch.complex128, device=dev, generator=g)
+        cb = torch.randn((N13, N13), dtype=torch.complex128, device=dev, generator=g)
+        alg = {}
+        ds = torch.empty((N13, 2 * N13), dtype=torch.complex128, device=dev)
+        ms_ds = _time(lambda: ptd.direct_sum(ca, cb, compact=True, out=ds), 10, 3, stream)
+        byt = 4.0 * 16 * 4 ** n13
+        alg["direct_sum_n13_compact"] = {"ms": round(ms_ds, 4), "GBps": round(byt / ms_ds / 1e6, 1),
+                                         "hbm_frac": round(byt / (ms_ds * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+        del ds
+        blocks = torch.randn((8, 1 << 11, 1 << 11), dtype=torch.complex128, device=dev, generator=g)
+        bdo = torch.empty((1 << 11, 1 << 14), dtype=torch.complex128, device=dev)
+        ms_bd = _time(lambda: ptd.block_diagonal(blocks, compact=True, out=bdo), 10, 3, stream)
+        byt = 2.0 * 16 * 8 * 4 ** 11
+        alg["block_diagonal_8x_n11_compact"] = {"ms": round(ms_bd, 4), "GBps": round(byt / ms_bd / 1e6, 1),
+                                                "hbm_frac": round(byt / (ms_bd * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+        del blocks, bdo
+        ha = torch.empty((2 * N13, 2 * N13), dtype=torch.float64, device=dev)
+        ms_ha = _time(lambda: ptd.hermitian_augment(ca, out=ha), 10, 3, stream)
+        byt = 16.0 * 4 ** n13 + 8.0 * 4 ** (n13 + 1)  # read c, write the dense real output (zeros included)
+        alg["hermitian_augment_n13_dense"] = {"ms": round(ms_ha, 4), "GBps": round(byt / ms_ha / 1e6, 1),
+                                              "hbm_frac": round(byt / (ms_ha * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+        del ha
+        lco = torch.empty_like(ca)
+        ms_lc = _time(lambda: ptd.linear_combination(0.5 - 1j, ca, cb, out=lco), 10, 3, stream)
+        byt = 3.0 * 16 * 4 ** n13
+        alg["linear_combination_n13"] = {"ms": round(ms_lc, 4), "GBps": round(byt / ms_lc / 1e6, 1),
+                                         "hbm_frac": round(byt / (ms_lc * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+        legs["algebra_c128"] = alg
+        del ca, cb, lco
+        torch.cuda.empty_cache()
     if "n15" in want_legs:
         # n = 15 complex64, plain and compensated butterflies
         g.manual_seed(15)

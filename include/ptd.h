@@ -185,6 +185,64 @@ ptd_status ptd_batch_plan_launch(ptd_plan *plan, ptd_stream stream);
 void ptd_batch_plan_destroy(ptd_plan *plan);
 
 /*
+ * Combinations of decompositions (Sec. IV-B, "Combinations of matrices"):
+ * the coefficients of a matrix assembled from matrices whose coefficients
+ * are known, computed from those coefficients alone, with no matrix formed
+ * and nothing decomposed again.  Coefficient arrays are dense, c[x * 2^n +
+ * z] as pauli_decompose writes them, in caller-owned device memory; each
+ * call is one pass over its inputs and outputs on `stream`.  Outputs must
+ * not overlap inputs (PTD_EINVAL), except as stated for the linear
+ * combination.  Arrays are aligned to their element size, and the outputs
+ * of the first three calls to 16 bytes (PTD_EINVAL otherwise: their zero
+ * rows are written 16 bytes per lane).  flags: 0, or PTD_COMPACT where
+ * stated.
+ *
+ * ptd_block_diagonal: diag(A_0, ..., A_{2^m - 1}) on k + m qubits from the
+ * coefficients of its 2^m diagonal blocks A_i on k qubits (Sec. IV-B
+ * "Block-diagonal matrices"; the direct sum is m = 1).  Block i's array is at
+ * blocks + i * 4^k elements of dtype.  The new top m qubits carry I or Z
+ * only:
+ *     c'[x][(t << k) | z] = 2^-m sum_i (-1)^popcount(t & i) c_i[x][z]
+ * for x, z < 2^k and t < 2^m (the paper's pairwise direct sums, unrolled; the
+ * pairs of the lowest block bit are combined first); rows x' >= 2^k are zero.
+ * The output is 2^(k+m) x 2^(k+m) complex of dtype with those rows written as
+ * zeros, or with PTD_COMPACT only its first 2^k rows (2^k x 2^(k+m)).
+ * k >= 1, 1 <= m <= 5, k + m <= 16.
+ */
+ptd_status ptd_block_diagonal(int k, int m, ptd_dtype dtype, unsigned flags, const void *blocks, void *coeff_out,
+                              ptd_stream stream);
+/*
+ * Direct sum A (+) B on n + 1 qubits (Sec. IV-B "Direct sum"): the m = 1 case
+ * of ptd_block_diagonal with the two arrays at separate addresses: the top
+ * qubit's I carries (c_A + c_B) / 2 and its Z carries (c_A - c_B) / 2.
+ * flags: PTD_COMPACT as above.  n >= 1, n + 1 <= 16.
+ */
+ptd_status ptd_direct_sum(int n, ptd_dtype dtype, unsigned flags, const void *ca, const void *cb, void *coeff_out,
+                          ptd_stream stream);
+/*
+ * Hermitian augmentation [[0, A^H], [A, 0]] on n + 1 qubits (Sec. IV-B
+ * "Hermitian matrix augmentation"): X on the new top qubit carries Re c and
+ * Y carries Im c, so the coefficients are real (float64 for PTD_C128, float32
+ * for PTD_C64):
+ *     c'[2^n + x][z] = Re c[x][z],   c'[2^n + x][2^n + z] = Im c[x][z];
+ * rows x' < 2^n are zero.  The output is 2^(n+1) x 2^(n+1) reals with those
+ * rows written as zeros, or with PTD_COMPACT the 2^n x 2^(n+1) rows x' >= 2^n
+ * only (output row x holds row 2^n + x).  n >= 1, n + 1 <= 16.
+ */
+ptd_status ptd_hermitian_augment(int n, ptd_dtype dtype, unsigned flags, const void *coeff, void *coeff_out,
+                                 ptd_stream stream);
+/*
+ * Linear combination mu A + B (Sec. IV-B "Linear combination"): c_out =
+ * mu c_A + c_B elementwise over the 4^n coefficients, mu = mu_re + i mu_im
+ * (rounded to float32 for PTD_C64).  Per element, without fused
+ * multiply-adds: re = (mu_re a_re - mu_im a_im) + b_re, im = (mu_re a_im +
+ * mu_im a_re) + b_im.  c_out may be c_a or c_b itself (not a shifted view).
+ * 1 <= n <= 16.
+ */
+ptd_status ptd_linear_combination(int n, ptd_dtype dtype, double mu_re, double mu_im, const void *ca, const void *cb,
+                                  void *c_out, ptd_stream stream);
+
+/*
  * Parseval check (Theorem 1: the strings are orthogonal with Tr(P^* P) = 2^n,
  * so ||A||_F^2 = 2^n sum_P |c_P|^2).  Reduces both sides in float64 on the
  * device (also for PTD_C64 data) and copies them to out_host[0] =

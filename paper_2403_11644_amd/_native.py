@@ -21,6 +21,7 @@ I = ctypes.c_int
 U = ctypes.c_uint
 I64 = ctypes.c_int64
 SZ = ctypes.c_size_t
+D = ctypes.c_double
 
 # name -> (restype, argtypes); mirrors include/ptd.h
 SIGNATURES = {
@@ -38,6 +39,10 @@ SIGNATURES = {
     "ptd_batch_plan_create": (I, [I, I, U, P, P, P, P, P, P]),
     "ptd_batch_plan_launch": (I, [P, P]),
     "ptd_batch_plan_destroy": (None, [P]),
+    "ptd_block_diagonal": (I, [I, I, I, U, P, P, P]),
+    "ptd_direct_sum": (I, [I, I, U, P, P, P, P]),
+    "ptd_hermitian_augment": (I, [I, I, U, P, P, P]),
+    "ptd_linear_combination": (I, [I, I, D, D, P, P, P, P]),
     "ptd_autotune": (I, [I, I, U, I, P, P, P, P, P, P]),
     "ptd_set_tuning": (I, [I, I, U, I, I]),
     "ptd_get_tuning": (I, [I, I, U, P, P]),

@@ -219,6 +219,92 @@ def parseval(A: torch.Tensor, c: torch.Tensor, *, hermitian: bool = False, strea
     return float(res[0]), float(res[1]), float(res[2])
 
 
+# --------------------------------------------------------------------------
+# combinations of decompositions (Sec. IV-B): new coefficients from known ones
+
+def _coeff_square(c: torch.Tensor, name: str) -> int:
+    _require_device(c, name)
+    if c.dim() != 2 or c.shape[0] != c.shape[1] or not c.is_contiguous():
+        raise ValueError("%s must be a contiguous square (2^n, 2^n) coefficient tensor" % name)
+    return _nqubits(c.shape[0])
+
+
+def _check_out(out, shape, dtype, device):
+    if out is None:
+        return torch.empty(shape, dtype=dtype, device=device)
+    if tuple(out.shape) != tuple(shape) or out.dtype != dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous %s tensor of shape %r" % (dtype, tuple(shape)))
+    return out
+
+
+def block_diagonal(blocks, *, compact: bool = False, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Coefficients of diag(A_0, ..., A_{2^m - 1}) from those of its blocks.
+
+    blocks: a (2^m, 2^k, 2^k) tensor (block i = blocks[i]) or a list of 2^m
+    (2^k, 2^k) tensors (stacked first), 1 <= m <= 5.  Returns
+    (2^(k+m), 2^(k+m)) coefficients, or with compact=True only the first 2^k
+    rows (the others are zero: those strings have X or Y on a new qubit)."""
+    if isinstance(blocks, (list, tuple)):
+        blocks = torch.stack(list(blocks))
+    _require_device(blocks, "blocks")
+    if blocks.dim() != 3 or blocks.shape[1] != blocks.shape[2] or not blocks.is_contiguous():
+        raise ValueError("blocks must be a contiguous (2^m, 2^k, 2^k) tensor")
+    k = _nqubits(blocks.shape[1])
+    m = _nqubits(blocks.shape[0]) if blocks.shape[0] > 1 else 0
+    code = _dtype_code(blocks.dtype)
+    W = 1 << (k + m)
+    out = _check_out(out, ((1 << k) if compact else W, W), blocks.dtype, blocks.device)
+    st = _native.lib().ptd_block_diagonal(k, m, code, COMPACT if compact else 0, _ptr(blocks), _ptr(out),
+                                          _stream_handle(blocks.device, stream))
+    _native.check(st, "ptd_block_diagonal")
+    return out
+
+
+def direct_sum(ca: torch.Tensor, cb: torch.Tensor, *, compact: bool = False, out: torch.Tensor | None = None,
+               stream=None) -> torch.Tensor:
+    """Coefficients of A (+) B = [[A, 0], [0, B]] from those of A and B."""
+    n = _coeff_square(ca, "ca")
+    if _coeff_square(cb, "cb") != n or cb.dtype != ca.dtype:
+        raise ValueError("ca and cb must have the same size and dtype")
+    code = _dtype_code(ca.dtype)
+    W = 2 << n
+    out = _check_out(out, ((1 << n) if compact else W, W), ca.dtype, ca.device)
+    st = _native.lib().ptd_direct_sum(n, code, COMPACT if compact else 0, _ptr(ca), _ptr(cb), _ptr(out),
+                                      _stream_handle(ca.device, stream))
+    _native.check(st, "ptd_direct_sum")
+    return out
+
+
+def hermitian_augment(c: torch.Tensor, *, compact: bool = False, out: torch.Tensor | None = None,
+                      stream=None) -> torch.Tensor:
+    """Real coefficients of [[0, A^H], [A, 0]] on n + 1 qubits from those of A:
+    X on the new qubit carries Re c, Y carries Im c.  compact=True returns
+    only the rows 2^n .. 2^(n+1) - 1 (the others are zero)."""
+    n = _coeff_square(c, "c")
+    code = _dtype_code(c.dtype)
+    W = 2 << n
+    out = _check_out(out, ((1 << n) if compact else W, W), _real_dtype(code), c.device)
+    st = _native.lib().ptd_hermitian_augment(n, code, COMPACT if compact else 0, _ptr(c), _ptr(out),
+                                             _stream_handle(c.device, stream))
+    _native.check(st, "ptd_hermitian_augment")
+    return out
+
+
+def linear_combination(mu, ca: torch.Tensor, cb: torch.Tensor, *, out: torch.Tensor | None = None,
+                       stream=None) -> torch.Tensor:
+    """Coefficients of mu A + B: mu * ca + cb elementwise (out may be ca or cb)."""
+    n = _coeff_square(ca, "ca")
+    if _coeff_square(cb, "cb") != n or cb.dtype != ca.dtype:
+        raise ValueError("ca and cb must have the same size and dtype")
+    code = _dtype_code(ca.dtype)
+    out = _check_out(out, tuple(ca.shape), ca.dtype, ca.device)
+    mu = complex(mu)
+    st = _native.lib().ptd_linear_combination(n, code, mu.real, mu.imag, _ptr(ca), _ptr(cb), _ptr(out),
+                                              _stream_handle(ca.device, stream))
+    _native.check(st, "ptd_linear_combination")
+    return out
+
+
 def _debug_decompose_path(A: torch.Tensor, path: int, hermitian: bool = False) -> torch.Tensor:
     """Run a specific dense schedule (1 = single pass, 2 = two passes); for tests."""
     code = _dtype_code(A.dtype)

@@ -185,6 +185,82 @@ ptd_status ptd_parseval_residual(int n, ptd_dtype dtype, unsigned flags, const v
                                            (hipStream_t)stream));
 }
 
+}  // extern "C"
+
+namespace {
+
+// Do the byte ranges [a, a + na) and [b, b + nb) meet?
+bool overlap(const void* a, size_t na, const void* b, size_t nb)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+size_t elem_bytes(ptd_dtype dt) { return dt == PTD_C128 ? 16 : 8; }
+
+// Outputs whose zero rows are written with 16-byte stores.
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+ptd_status ptd_block_diagonal(int k, int m, ptd_dtype dtype, unsigned flags, const void* blocks, void* coeff_out,
+                              ptd_stream stream)
+{
+    if (k < 1 || m < 1 || m > 5 || k + m > 16 || !valid_dtype(dtype) || !blocks || !coeff_out) return PTD_EINVAL;
+    if (flags & ~PTD_COMPACT) return PTD_EINVAL;
+    if (!aligned16(coeff_out)) return PTD_EINVAL;
+    const bool compact = flags & PTD_COMPACT;
+    const size_t blk = elem_bytes(dtype) << (2 * k);
+    const size_t out_rows = compact ? ((size_t)1 << k) : ((size_t)1 << (k + m));
+    const size_t out_bytes = out_rows * (elem_bytes(dtype) << (k + m));
+    if (overlap(blocks, blk << m, coeff_out, out_bytes)) return PTD_EINVAL;
+    ptd::BlockPtrs p{};
+    for (int i = 0; i < (1 << m); ++i) p.p[i] = (const unsigned char*)blocks + (size_t)i * blk;
+    return hip_status(ptd::launch_block_diagonal(k, m, dtype, compact, p, coeff_out, (hipStream_t)stream));
+}
+
+ptd_status ptd_direct_sum(int n, ptd_dtype dtype, unsigned flags, const void* ca, const void* cb, void* coeff_out,
+                          ptd_stream stream)
+{
+    if (n < 1 || n + 1 > 16 || !valid_dtype(dtype) || !ca || !cb || !coeff_out) return PTD_EINVAL;
+    if (flags & ~PTD_COMPACT) return PTD_EINVAL;
+    if (!aligned16(coeff_out)) return PTD_EINVAL;
+    const bool compact = flags & PTD_COMPACT;
+    const size_t blk = elem_bytes(dtype) << (2 * n);
+    const size_t out_bytes = (compact ? ((size_t)1 << n) : ((size_t)2 << n)) * (elem_bytes(dtype) << (n + 1));
+    if (overlap(ca, blk, coeff_out, out_bytes) || overlap(cb, blk, coeff_out, out_bytes)) return PTD_EINVAL;
+    ptd::BlockPtrs p{};
+    p.p[0] = ca;
+    p.p[1] = cb;
+    return hip_status(ptd::launch_block_diagonal(n, 1, dtype, compact, p, coeff_out, (hipStream_t)stream));
+}
+
+ptd_status ptd_hermitian_augment(int n, ptd_dtype dtype, unsigned flags, const void* coeff, void* coeff_out,
+                                 ptd_stream stream)
+{
+    if (n < 1 || n + 1 > 16 || !valid_dtype(dtype) || !coeff || !coeff_out) return PTD_EINVAL;
+    if (flags & ~PTD_COMPACT) return PTD_EINVAL;
+    if (!aligned16(coeff_out)) return PTD_EINVAL;
+    const bool compact = flags & PTD_COMPACT;
+    const size_t in_bytes = elem_bytes(dtype) << (2 * n);
+    const size_t out_bytes = (compact ? ((size_t)1 << n) : ((size_t)2 << n)) * ((elem_bytes(dtype) / 2) << (n + 1));
+    if (overlap(coeff, in_bytes, coeff_out, out_bytes)) return PTD_EINVAL;
+    return hip_status(ptd::launch_hermitian_augment(n, dtype, compact, coeff, coeff_out, (hipStream_t)stream));
+}
+
+ptd_status ptd_linear_combination(int n, ptd_dtype dtype, double mu_re, double mu_im, const void* ca, const void* cb,
+                                  void* c_out, ptd_stream stream)
+{
+    if (n < 1 || n > 16 || !valid_dtype(dtype) || !ca || !cb || !c_out) return PTD_EINVAL;
+    const size_t bytes = elem_bytes(dtype) << (2 * n);
+    // elementwise: c_out may be c_a or c_b, but not a shifted view of either
+    if ((c_out != ca && overlap(ca, bytes, c_out, bytes)) || (c_out != cb && overlap(cb, bytes, c_out, bytes)))
+        return PTD_EINVAL;
+    return hip_status(ptd::launch_linear_combination(n, dtype, mu_re, mu_im, ca, cb, c_out, (hipStream_t)stream));
+}
+
 // Testing hook: force the single-pass (path 1) or two-pass (path 2) schedule.
 ptd_status ptd_debug_decompose_path(int n, ptd_dtype dtype, unsigned flags, const void* A, int64_t lda,
                                     void* coeff, int path, ptd_stream stream)

@@ -116,6 +116,17 @@ void batched_fill(int count, ptd_dtype dt, bool herm, bool rec, const int32_t* n
 hipError_t batched_launch(ptd_dtype dt, bool herm, bool rec, bool adjoint, const void* in_base, void* out_base,
                           void* buf, int count, const BatchLaunch& bl, int cus, hipStream_t st);
 
+// Combinations of decompositions (algebra.hip).  Block i of a block-diagonal
+// assembly is read from blocks.p[i] (4^k elements each, 2^m blocks, m <= 5).
+struct BlockPtrs {
+    const void* p[32];
+};
+hipError_t launch_block_diagonal(int k, int m, ptd_dtype dt, bool compact, const BlockPtrs& blocks, void* out,
+                                 hipStream_t st);
+hipError_t launch_hermitian_augment(int n, ptd_dtype dt, bool compact, const void* in, void* out, hipStream_t st);
+hipError_t launch_linear_combination(int n, ptd_dtype dt, double mu_re, double mu_im, const void* a, const void* b,
+                                     void* out, hipStream_t st);
+
 // Parseval residual: out_host[0] = ||A||_F^2, [1] = 2^n sum|c|^2, [2] = relative gap.
 size_t reduce_workspace_bytes();
 hipError_t launch_parseval(int n, ptd_dtype dt, bool real_coeff, const void* A, int64_t lda, const void* coeff,

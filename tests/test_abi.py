@@ -201,3 +201,44 @@ def test_empty_batch():
     from paper_2403_11644_amd import api
 
     assert api.decompose_batched([]) == []
+
+
+def test_combination_argument_errors(lib):
+    """Sec. IV-B combinations: every bad argument is refused on the host,
+    before any device call (bogus addresses never reach a kernel)."""
+    EINVAL = -1
+    big, far = 1 << 40, 1 << 41  # distinct, far-apart fake device addresses
+    bd = lambda k=3, m=2, dt=0, flags=0, b=big, o=far: lib.ptd_block_diagonal(k, m, dt, flags, b, o, None)
+    assert bd(k=0) == EINVAL
+    assert bd(m=0) == EINVAL
+    assert bd(m=6) == EINVAL
+    assert bd(k=12, m=5) == EINVAL  # k + m <= 16
+    assert bd(dt=2) == EINVAL
+    assert bd(flags=1) == EINVAL  # only PTD_COMPACT
+    assert bd(b=0) == EINVAL
+    assert bd(o=0) == EINVAL
+    assert bd(b=big, o=big + 64) == EINVAL  # output overlaps the blocks
+    assert bd(o=far + 8) == EINVAL  # output not 16-byte aligned
+    ds = lambda n=3, dt=0, flags=0, a=big, b=big + (1 << 20), o=far: lib.ptd_direct_sum(n, dt, flags, a, b, o, None)
+    assert ds(n=0) == EINVAL
+    assert ds(n=16) == EINVAL  # the result has n + 1 qubits
+    assert ds(flags=2) == EINVAL
+    assert ds(a=0) == EINVAL
+    assert ds(o=big + 16) == EINVAL
+    assert ds(o=big + (1 << 20) + 8) == EINVAL
+    ha = lambda n=3, dt=1, flags=0, c=big, o=far: lib.ptd_hermitian_augment(n, dt, flags, c, o, None)
+    assert ha(n=0) == EINVAL
+    assert ha(n=16) == EINVAL
+    assert ha(dt=5) == EINVAL
+    assert ha(flags=1) == EINVAL
+    assert ha(c=0) == EINVAL
+    assert ha(o=big) == EINVAL
+    assert ha(o=far + 4) == EINVAL
+    lc = lambda n=3, dt=0, a=big, b=big + (1 << 20), o=far: lib.ptd_linear_combination(n, dt, 1.0, 0.5, a, b, o,
+                                                                                        None)
+    assert lc(n=0) == EINVAL
+    assert lc(n=17) == EINVAL
+    assert lc(dt=2) == EINVAL
+    assert lc(a=0) == EINVAL
+    assert lc(o=0) == EINVAL
+    assert lc(o=big + 16) == EINVAL  # a shifted view of c_a

@@ -1,0 +1,125 @@
+"""GPU parity of the Sec. IV-B combinations (direct sum, block-diagonal
+assembly, Hermitian augmentation, linear combination) against the oracle's
+versions on the same coefficient arrays, and end to end against decomposing
+the assembled matrix on the device."""
+import numpy as np
+import pytest
+
+import synth
+from tests.helpers import rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ptd():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_11644_amd as p
+
+    return p
+
+
+def _coeffs(n, seed, dt):
+    return synth.complex_normal((1 << n, 1 << n), seed=seed, dtype=dt)
+
+
+def _int_coeffs(n, seed, dt):
+    # small integers times 2^-n: every sum and halving below stays exact
+    re, im = synth.gaussian_int(n, seed=seed)
+    return (synth.int_to_complex(re, im, np.complex128) / (1 << n)).astype(dt)
+
+
+DTS = [np.complex128, np.complex64]
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("n", [1, 3, 6, 9, 11])
+@pytest.mark.parametrize("compact", [False, True])
+def test_direct_sum(ptd, oracle_mod, dt, n, compact):
+    ca, cb = _coeffs(n, 10 + n, dt), _coeffs(n, 20 + n, dt)
+    got = to_host(ptd.direct_sum(to_dev(ca), to_dev(cb), compact=compact))
+    want = oracle_mod.direct_sum(ca, cb)
+    # the same two roundings ((a +- b), then an exact halving) on both sides
+    np.testing.assert_array_equal(got, want[:1 << n] if compact else want)
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("k,m", [(1, 1), (1, 5), (2, 3), (4, 2), (5, 4), (7, 3), (9, 1), (6, 5)])
+def test_block_diagonal_integer_exact(ptd, oracle_mod, dt, k, m):
+    blocks = np.stack([_int_coeffs(k, 100 + 7 * k + i, dt) for i in range(1 << m)])
+    got = to_host(ptd.block_diagonal(to_dev(blocks)))
+    np.testing.assert_array_equal(got, oracle_mod.block_diagonal(list(blocks)))
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("k,m,compact", [(3, 2, False), (8, 3, True), (5, 5, False), (10, 2, True)])
+def test_block_diagonal_float(ptd, oracle_mod, dt, k, m, compact):
+    blocks = [_coeffs(k, 200 + i, dt) for i in range(1 << m)]
+    got = to_host(ptd.block_diagonal([to_dev(b) for b in blocks], compact=compact))
+    want = oracle_mod.block_diagonal(blocks)
+    if compact:
+        want = want[:1 << k]
+    else:
+        assert np.all(got[1 << k:] == 0)
+    assert rel_err(got, want) <= (1e-15 if dt == np.complex128 else 1e-6)
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("n", [1, 4, 8, 12])
+@pytest.mark.parametrize("compact", [False, True])
+def test_hermitian_augment(ptd, oracle_mod, dt, n, compact):
+    c = _coeffs(n, 30 + n, dt)
+    got = to_host(ptd.hermitian_augment(to_dev(c), compact=compact))
+    want = oracle_mod.hermitian_augment(c)
+    assert got.dtype == want.dtype
+    np.testing.assert_array_equal(got, want[1 << n:] if compact else want)
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("n", [1, 5, 10, 13])
+def test_linear_combination(ptd, oracle_mod, dt, n):
+    mu = 0.75 - 1.25j
+    ca, cb = _coeffs(n, 40 + n, dt), _coeffs(n, 50 + n, dt)
+    dca, dcb = to_dev(ca), to_dev(cb)
+    want = oracle_mod.linear_combination(mu, ca, cb)
+    # the same roundings in the same order (no fused multiply-add anywhere)
+    np.testing.assert_array_equal(to_host(ptd.linear_combination(mu, dca, dcb)), want)
+    # in place into c_b
+    ptd.linear_combination(mu, dca, dcb, out=dcb)
+    np.testing.assert_array_equal(to_host(dcb), want)
+
+
+@pytest.mark.parametrize("dt", DTS)
+def test_end_to_end_against_decomposition(ptd, dt):
+    """The combinations of decomposed blocks equal the decomposition of the
+    assembled matrices, all on the device (Sec. IV-B identities)."""
+    import torch
+
+    n = 6
+    N = 1 << n
+    A = synth.dense(n, seed=1, dtype=dt)
+    B = synth.dense(n, seed=2, dtype=dt)
+    dA, dB = to_dev(A), to_dev(B)
+    cA, cB = ptd.decompose(dA), ptd.decompose(dB)
+    tol = 1e-14 if dt == np.complex128 else 1e-6
+    # direct sum and four-block diagonal
+    C = torch.zeros((2 * N, 2 * N), dtype=dA.dtype, device=dA.device)
+    C[:N, :N], C[N:, N:] = dA, dB
+    assert rel_err(to_host(ptd.direct_sum(cA, cB)), to_host(ptd.decompose(C))) <= tol
+    D = torch.zeros((4 * N, 4 * N), dtype=dA.dtype, device=dA.device)
+    for i, M in enumerate([dA, dB, dB, dA]):
+        D[i * N:(i + 1) * N, i * N:(i + 1) * N] = M
+    got = to_host(ptd.block_diagonal([cA, cB, cB, cA]))
+    assert rel_err(got, to_host(ptd.decompose(D))) <= tol
+    # Hermitian augmentation: [[0, A^H], [A, 0]] through the Hermitian path
+    H = torch.zeros((2 * N, 2 * N), dtype=dA.dtype, device=dA.device)
+    H[:N, N:] = dA.conj().T
+    H[N:, :N] = dA
+    assert rel_err(to_host(ptd.hermitian_augment(cA)), to_host(ptd.decompose(H, hermitian=True))) <= tol
+    # linear combination
+    mu = -0.5 + 2.0j
+    got = to_host(ptd.linear_combination(mu, cA, cB))
+    assert rel_err(got, to_host(ptd.decompose(mu * dA + dB))) <= tol
