@@ -381,7 +381,7 @@ def main() -> int:
         torch.cuda.empty_cache()
     if "band" in want_legs:
         # n = 14 structured inputs: the skip path over the nonempty X-patterns
-        # only (1 / 15 / 96 of 16384), from compressed bands with compact
+        # only (1 / 15 / 96 / 1 of 16384), from compressed bands with compact
         # output, and for s = 8 also from the dense matrix (reading only the
         # band) with compact and with zero-filled dense output
         wsd = torch.empty(16, dtype=torch.uint8, device=dev)
@@ -410,6 +410,12 @@ def main() -> int:
                                         "from_dense_zero_filled_us": round(us_dd, 2),
                                         "speedup_vs_dense_f64": round(ms128 * 1e3 / us, 1)})
             del bd, bout
+        # anti-diagonal: the one X-pattern 2^n - 1, from the vector A[k][N-1-k]
+        adv = torch.from_numpy(synth.antidiagonal_complex(n, seed=3).reshape(1, N).copy()).to(dev)
+        aout = torch.empty((1, N), dtype=torch.complex128, device=dev)
+        us = _call_us(skip_call(adv, api.ANTIDIAGONAL | api.BANDS_IN | api.COMPACT, 0, aout, N), 20, 5, stream)
+        band_legs["antidiag"] = {"nonempty_x": 1, "from_vector_compact_us": round(us, 2)}
+        del adv, aout
         legs["structured_n14"] = band_legs
     if "algebra" in want_legs:
         # Sec. IV-B combinations on coefficient arrays: one HBM pass each

@@ -87,6 +87,13 @@ typedef void *ptd_stream;
 #define PTD_ADJOINT (1u << 6)
 /* ptd_batch_plan_create only: the plan reconstructs (coefficients -> matrices). */
 #define PTD_PLAN_RECONSTRUCT (1u << 7)
+/* A is anti-diagonal: a[r][c] = 0 unless r + c = 2^n - 1 (the remark after
+ * the diagonal case of Sec. IV-A: I and Z give way to X and Y).  Only
+ * x = 2^n - 1 can be nonzero, every string having X or Y on every qubit.
+ * With PTD_BANDS_IN, A is the vector ad[k] = A[k][2^n - 1 - k]; PTD_COMPACT
+ * writes the one row.  Not combined with PTD_DIAGONAL or PTD_BANDED; s is
+ * ignored. */
+#define PTD_ANTIDIAGONAL (1u << 8)
 
 /* Workspace (device bytes) a pauli_decompose call with these arguments
  * needs: a few KiB of queue counters for dense decompositions with

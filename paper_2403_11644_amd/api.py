@@ -20,6 +20,7 @@ DIAGONAL = 1 << 1
 BANDED = 1 << 2
 BANDS_IN = 1 << 3
 COMPACT = 1 << 4
+ANTIDIAGONAL = 1 << 8
 COMPENSATED = 1 << 5
 ADJOINT = 1 << 6
 
@@ -63,9 +64,10 @@ def _require_device(t: torch.Tensor, name: str) -> None:
 
 def _rows(t: torch.Tensor, name: str) -> int:
     """Row pitch in elements of a 2-D tensor whose rows are contiguous."""
-    if t.dim() != 2 or t.stride(1) != 1:
+    if t.dim() != 2 or (t.stride(1) != 1 and t.shape[1] > 1):
         raise ValueError("%s must be 2-D with contiguous rows" % name)
-    return t.stride(0)
+    # a single row may carry any stride (numpy and torch give new axes 0)
+    return t.stride(0) if t.shape[0] > 1 else t.shape[1]
 
 
 def pad_to_power_of_two(A: torch.Tensor) -> torch.Tensor:
@@ -86,7 +88,7 @@ def pad_to_power_of_two(A: torch.Tensor) -> torch.Tensor:
 
 
 def num_nonempty_x(n: int, structure: str | None = None, s: int = 0) -> int:
-    flags = {None: 0, "diagonal": DIAGONAL, "banded": BANDED}[structure]
+    flags = {None: 0, "diagonal": DIAGONAL, "banded": BANDED, "antidiagonal": ANTIDIAGONAL}[structure]
     v = _native.lib().ptd_num_nonempty_x(n, flags, s)
     if v < 0:
         raise ValueError("bad (n, structure, s) = (%d, %r, %d)" % (n, structure, s))
@@ -97,7 +99,7 @@ def nonempty_x(n: int, structure: str | None = None, s: int = 0) -> list[int]:
     """X-patterns that can carry a nonzero coefficient, ascending (Sec. IV-A)."""
     import numpy as np
 
-    flags = {None: 0, "diagonal": DIAGONAL, "banded": BANDED}[structure]
+    flags = {None: 0, "diagonal": DIAGONAL, "banded": BANDED, "antidiagonal": ANTIDIAGONAL}[structure]
     cnt = num_nonempty_x(n, structure, s)
     buf = np.empty(cnt, dtype=np.uint32)
     _native.check(_native.lib().ptd_nonempty_x(n, flags, s, ctypes.c_void_p(buf.ctypes.data)), "ptd_nonempty_x")
@@ -110,8 +112,10 @@ def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None
     """Pauli coefficients of A, as a (2^n, 2^n) tensor c[x, z].
 
     hermitian   A == A^*: return the (real) coefficients as float64/float32.
-    structure   None, 'diagonal' or 'banded' (with half-bandwidth s).
-    bands       A is the row-indexed band array band[d + s][k] = A[k][k + d].
+    structure   None, 'diagonal', 'banded' (with half-bandwidth s) or
+                'antidiagonal'.
+    bands       A is the row-indexed band array band[d + s][k] = A[k][k + d]
+                (anti-diagonal: the one row ad[k] = A[k][2^n - 1 - k]).
     compact     structured only: return rows of the nonempty X-patterns only.
     compensated complex64 only: TwoSum butterflies.
     pad         zero-pad a non-power-of-two A (top-left embedding).
@@ -127,8 +131,10 @@ def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None
             raise ValueError("banded structure needs s >= 1")
         flags |= BANDED
         sv = int(s)
+    elif structure == "antidiagonal":
+        flags |= ANTIDIAGONAL
     elif structure is not None:
-        raise ValueError("structure must be None, 'diagonal' or 'banded'")
+        raise ValueError("structure must be None, 'diagonal', 'banded' or 'antidiagonal'")
     if bands:
         if structure is None:
             raise ValueError("bands=True needs a structure")

@@ -15,7 +15,8 @@ namespace {
 thread_local int g_last_hip_error = 0;
 
 constexpr unsigned kAllFlags = PTD_HERMITIAN | PTD_DIAGONAL | PTD_BANDED | PTD_BANDS_IN | PTD_COMPACT |
-                               PTD_COMPENSATED | PTD_ADJOINT;
+                               PTD_COMPENSATED | PTD_ADJOINT | PTD_ANTIDIAGONAL;
+constexpr unsigned kStructure = PTD_DIAGONAL | PTD_BANDED | PTD_ANTIDIAGONAL;
 
 ptd_status hip_status(hipError_t e)
 {
@@ -29,9 +30,9 @@ bool valid_dtype(ptd_dtype dt) { return dt == PTD_C128 || dt == PTD_C64; }
 // Structured-flag checks shared by the decompose entry points.
 ptd_status check_structure(int n, unsigned flags, int s)
 {
-    const bool diag = flags & PTD_DIAGONAL, band = flags & PTD_BANDED;
-    if (diag && band) return PTD_EINVAL;
-    if ((flags & (PTD_BANDS_IN | PTD_COMPACT)) && !(diag || band)) return PTD_EINVAL;
+    const bool diag = flags & PTD_DIAGONAL, band = flags & PTD_BANDED, anti = flags & PTD_ANTIDIAGONAL;
+    if ((int)diag + (int)band + (int)anti > 1) return PTD_EINVAL;
+    if ((flags & (PTD_BANDS_IN | PTD_COMPACT)) && !(diag || band || anti)) return PTD_EINVAL;
     if (band && (s < 1 || s >= (1 << n))) return PTD_EINVAL;
     return PTD_OK;
 }
@@ -45,7 +46,7 @@ bool use_fused_rec(int n) { return n >= 11 && n <= 14; }
 
 bool use_fused(int n, ptd_dtype dt, unsigned flags)
 {
-    if (flags & (PTD_DIAGONAL | PTD_BANDED | PTD_COMPENSATED)) return false;
+    if (flags & (kStructure | PTD_COMPENSATED)) return false;
     if (n < 11 || n > 15) return false;
     if (n == 15 && (dt == PTD_C128 || (flags & PTD_HERMITIAN))) return false;
     return true;
@@ -77,7 +78,7 @@ size_t ptd_workspace_bytes(int n, ptd_dtype dtype, unsigned flags, int s)
 {
     (void)s;
     if (n < 1 || n > 16 || !valid_dtype(dtype)) return 0;
-    if (flags & (PTD_DIAGONAL | PTD_BANDED | PTD_ADJOINT)) return 0;
+    if (flags & (kStructure | PTD_ADJOINT)) return 0;
     if (use_fused(n, dtype, flags)) return ptd::fused_workspace_bytes(n, dtype);
     return 0;
 }
@@ -85,6 +86,7 @@ size_t ptd_workspace_bytes(int n, ptd_dtype dtype, unsigned flags, int s)
 int ptd_num_nonempty_x(int n, unsigned flags, int s)
 {
     if (n < 1 || n > 16 || (flags & ~kAllFlags)) return -1;
+    if (flags & PTD_ANTIDIAGONAL) return (flags & (PTD_DIAGONAL | PTD_BANDED)) ? -1 : 1;
     if (flags & PTD_DIAGONAL) return (flags & PTD_BANDED) ? -1 : 1;
     if (flags & PTD_BANDED) {
         if (s < 1 || s >= (1 << n)) return -1;
@@ -99,6 +101,10 @@ ptd_status ptd_nonempty_x(int n, unsigned flags, int s, uint32_t* xs_host)
 {
     const int cnt = ptd_num_nonempty_x(n, flags, s);
     if (cnt < 0 || !xs_host) return PTD_EINVAL;
+    if (flags & PTD_ANTIDIAGONAL) {
+        xs_host[0] = (uint32_t)((1u << n) - 1u);
+        return PTD_OK;
+    }
     if (!(flags & (PTD_DIAGONAL | PTD_BANDED))) {
         for (int i = 0; i < cnt; ++i) xs_host[i] = (uint32_t)i;
         return PTD_OK;
@@ -131,9 +137,10 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
     if (A == coeff) return PTD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     const bool herm = flags & PTD_HERMITIAN;
-    if (flags & (PTD_DIAGONAL | PTD_BANDED)) {
+    if (flags & kStructure) {
         if (flags & PTD_COMPENSATED) return PTD_EUNSUP;
-        const int se = (flags & PTD_DIAGONAL) ? 0 : s;
+        // s < 0 codes the anti-diagonal for the structured kernels
+        const int se = (flags & PTD_ANTIDIAGONAL) ? -1 : (flags & PTD_DIAGONAL) ? 0 : s;
         const int count = ptd_num_nonempty_x(n, flags, s);
         if (count < 1) return PTD_EINVAL;
         return hip_status(ptd::launch_structured(n, dtype, herm, flags & PTD_BANDS_IN, flags & PTD_COMPACT, se, count,

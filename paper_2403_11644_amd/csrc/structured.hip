@@ -1,4 +1,5 @@
-// structured.hip -- diagonal and banded inputs: only nonempty X-patterns.
+// structured.hip -- diagonal, banded and anti-diagonal inputs: only
+// nonempty X-patterns.
 //
 // For a band matrix with half-bandwidth s (a[r][c] = 0 when |r - c| > s;
 // s = 0 diagonal, s = 1 tridiagonal; paper Sec. IV-A) the strings with
@@ -12,7 +13,11 @@
 // Each listed x gets d_x[k] = A[k][k ^ x] for in-band entries and 0 outside
 // the band, read either from the dense matrix (touching only in-band
 // entries) or from the row-indexed bands band[d + s][k] = A[k][k + d], then
-// one length-2^n WHT and the fused phase/scale.  n <= 10: one pass, several
+// one length-2^n WHT and the fused phase/scale.  An anti-diagonal matrix
+// (a[r][c] = 0 unless r + c = 2^n - 1) reads only the entries (k, k ^ x)
+// with x = 2^n - 1, so that is its one X-pattern: every string has X or Y on
+// every qubit (the remark after the diagonal case in Sec. IV-A); it is coded
+// as s < 0 below, with the compressed input ad[k] = A[k][2^n - 1 - k].  n <= 10: one pass, several
 // X-patterns per workgroup in LDS.  n >= 11: a 1024-position pass and a
 // strided pass over the remaining bits, in place in the output rows.
 #include "engine.hpp"
@@ -26,9 +31,11 @@ constexpr int SM_THREADS = 256;
 constexpr int SM_VECS = 4;  // X-patterns per workgroup for n <= 10
 constexpr int SP_KAP = 10;  // positions per first-pass item for n >= 11
 
-// i-th nonempty X-pattern (ascending); s = 0 means diagonal.
+// i-th nonempty X-pattern (ascending); s = 0 means diagonal, s < 0
+// anti-diagonal (the single X-pattern 2^n - 1: X or Y on every qubit).
 __device__ __forceinline__ uint32_t listed_x(int i, int n, int s)
 {
+    if (s < 0) return (1u << n) - 1u;
     if (i == 0) return 0u;
     int r = i - 1;
     for (int h = 0; h < n; ++h) {
@@ -39,8 +46,9 @@ __device__ __forceinline__ uint32_t listed_x(int i, int n, int s)
     return 0u;  // unreachable for i < count
 }
 
-__device__ __forceinline__ bool is_listed(uint32_t x, int s)
+__device__ __forceinline__ bool is_listed(uint32_t x, int n, int s)
 {
+    if (s < 0) return x == (1u << n) - 1u;
     if (x == 0u) return true;
     const int h = 31 - __clz(x);
     const int y = (int)x - (1 << h);
@@ -48,11 +56,19 @@ __device__ __forceinline__ bool is_listed(uint32_t x, int s)
 }
 
 // d_x[k] from the dense matrix or from the row-indexed bands; 0 off band.
+// Anti-diagonal (s < 0): A[k][k ^ x] with x = 2^n - 1, or entry k of the
+// compressed vector ad[k] = A[k][2^n - 1 - k].
 template <class V, bool BANDS>
 __device__ __forceinline__ void band_entry(const cplx<V>* __restrict__ A, int64_t lda, int s, int k, uint32_t x,
                                            V& re, V& im)
 {
     const int c = k ^ (int)x;
+    if (s < 0) {
+        const cplx<V> v = BANDS ? A[k] : A[(int64_t)k * lda + c];
+        re = v.re;
+        im = v.im;
+        return;
+    }
     const int d = c - k;
     if (d > s || d < -s) {
         re = (V)0;
@@ -234,7 +250,7 @@ __global__ void k_zero_unlisted(void* __restrict__ out, int n, int s)
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t x = (uint32_t)(e >> n);
-        if (!is_listed(x, s)) put_final<V, HERM>(out, e, (V)0, (V)0);
+        if (!is_listed(x, n, s)) put_final<V, HERM>(out, e, (V)0, (V)0);
     }
 }
 

@@ -128,6 +128,27 @@ def dense_from_bands(band: np.ndarray, dtype=None) -> np.ndarray:
     return A
 
 
+def antidiagonal_complex(n: int, seed: int, dtype=np.complex128, hermitian: bool = False) -> np.ndarray:
+    """Anti-diagonal entries ad[k] = A[k][N - 1 - k], complex N(0, 1); with
+    hermitian=True the second half mirrors the first, ad[N - 1 - k] =
+    conj(ad[k]) (A[N-1-k][k] = conj(A[k][N-1-k]))."""
+    N = 1 << n
+    ad = complex_normal(N, seed, dtype)
+    if hermitian:
+        ad[N // 2:] = np.conj(ad[:N // 2][::-1])
+    return ad
+
+
+def dense_from_antidiagonal(ad: np.ndarray) -> np.ndarray:
+    """Dense matrix with A[k][N - 1 - k] = ad[k], zero elsewhere."""
+    ad = np.asarray(ad)
+    N = ad.shape[0]
+    A = np.zeros((N, N), dtype=ad.dtype)
+    k = np.arange(N)
+    A[k, N - 1 - k] = ad
+    return A
+
+
 def batched_ns(count: int = 4096, seed: int = 0, lo: int = 2, hi: int = 10) -> np.ndarray:
     """Qubit counts of a batch, uniform on [lo, hi]."""
     return np.random.default_rng(seed).integers(lo, hi + 1, size=count)

@@ -70,6 +70,8 @@ def test_nonempty_counts_match_bruteforce(lib, oracle_mod):
         assert got == oracle_mod.nonempty_x_bruteforce(n, s)
         assert len(got) * (1 << n) == oracle_mod.band_term_bound(n, s)
     assert api.nonempty_x(6, "diagonal") == [0]
+    assert api.nonempty_x(6, "antidiagonal") == [63]
+    assert lib.ptd_num_nonempty_x(6, (1 << 8) | (1 << 1), 0) == -1  # anti-diagonal and diagonal
     assert api.num_nonempty_x(14, "banded", 8) == 96
     assert api.num_nonempty_x(14, "banded", 1) == 15
     assert api.num_nonempty_x(5) == 32
@@ -96,6 +98,8 @@ def test_decompose_argument_errors(lib):
     assert _dec(lib, flags=(1 << 3)) == EINVAL  # bands-in without structure
     assert _dec(lib, flags=(1 << 4)) == EINVAL  # compact without structure
     assert _dec(lib, flags=(1 << 6)) == EINVAL  # adjoint is a reconstruct flag
+    assert _dec(lib, flags=(1 << 8) | (1 << 2), s=1) == EINVAL  # anti-diagonal + banded
+    assert _dec(lib, flags=(1 << 8) | (1 << 5), dt=1) == -3  # compensated structured: unsupported
     assert _dec(lib, flags=(1 << 5), dt=0) == EUNSUP  # compensated is complex64 only
     assert _dec(lib, A=5, C=5) == EINVAL  # in place is not allowed
     ENOSPC = -2
@@ -242,3 +246,18 @@ def test_combination_argument_errors(lib):
     assert lc(a=0) == EINVAL
     assert lc(o=0) == EINVAL
     assert lc(o=big + 16) == EINVAL  # a shifted view of c_a
+
+
+def test_row_pitch_of_a_single_row():
+    """A one-row band array (diagonal / anti-diagonal input) made with a new
+    axis has stride 0 on it; its pitch is taken as the row length."""
+    import numpy as np
+    import torch
+
+    from paper_2403_11644_amd import api
+
+    v = torch.from_numpy(np.arange(8.0)[None, :])
+    assert v.stride(0) in (0, 8)
+    assert api._rows(v, "v") == 8
+    assert api._rows(torch.zeros(3, 8), "m") == 8
+    assert api._rows(torch.zeros(8, 16)[:, :8], "m") == 16

@@ -125,3 +125,54 @@ def test_large_band_edge(ptd, oracle_mod):
     got = to_host(ptd.decompose(to_dev(band), structure="banded", s=s, bands=True, compact=True))
     want = oracle_mod.decompose(A)[xs]
     assert rel_err(got, want) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# anti-diagonal input: the one X-pattern 2^n - 1 (remark in Sec. IV-A)
+
+@pytest.mark.parametrize("dt", [np.complex128, np.complex64])
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 10, 11, 13])
+@pytest.mark.parametrize("hermitian", [False, True])
+def test_antidiagonal_vs_oracle(ptd, oracle_mod, dt, n, hermitian):
+    N = 1 << n
+    ad = synth.antidiagonal_complex(n, seed=90 + n, dtype=dt, hermitian=hermitian)
+    A = synth.dense_from_antidiagonal(ad)
+    assert ptd.nonempty_x(n, "antidiagonal") == [N - 1]
+    want = oracle_mod.rows(A.astype(np.complex128), np.array([N - 1], dtype=np.uint32))
+    if hermitian:
+        want = want.real
+    Ad, vd = to_dev(A), to_dev(ad[None, :])
+    comp_dense = to_host(ptd.decompose(Ad, structure="antidiagonal", hermitian=hermitian, compact=True))
+    comp_vec = to_host(ptd.decompose(vd, structure="antidiagonal", hermitian=hermitian, bands=True, compact=True))
+    np.testing.assert_array_equal(comp_dense, comp_vec)
+    assert comp_dense.shape == (1, N)
+    assert rel_err(comp_dense, want) <= TOL[dt]
+    full = to_host(ptd.decompose(vd, structure="antidiagonal", hermitian=hermitian, bands=True))
+    np.testing.assert_array_equal(full[N - 1], comp_dense[0])
+    assert np.all(full[:N - 1] == 0)
+    # the dense path: same row, zeros elsewhere
+    dense = to_host(ptd.decompose(Ad, hermitian=hermitian))
+    assert rel_err(dense[N - 1:], comp_dense) <= TOL[dt]
+    assert np.all(dense[:N - 1] == 0)
+
+
+@pytest.mark.parametrize("n", [3, 9, 12])
+def test_antidiagonal_integer_exact(ptd, oracle_mod, n):
+    N = 1 << n
+    re, im = synth.gaussian_int(n, seed=95)
+    ad_int = (re[0], im[0])  # first row of a Gaussian-integer matrix as the anti-diagonal
+    A_re = np.zeros((N, N), dtype=np.int64)
+    A_im = np.zeros((N, N), dtype=np.int64)
+    k = np.arange(N)
+    A_re[k, N - 1 - k] = ad_int[0]
+    A_im[k, N - 1 - k] = ad_int[1]
+    want_re, want_im = oracle_mod.decompose_int(A_re, A_im) if n <= 9 else (None, None)
+    vec = (ad_int[0] + 1j * ad_int[1]).astype(np.complex64)
+    got = to_host(ptd.decompose(to_dev(vec[None, :]), structure="antidiagonal", bands=True, compact=True))
+    scaled = got[0].astype(np.complex128) * N
+    if want_re is not None:
+        np.testing.assert_array_equal(scaled.real, want_re[N - 1].astype(np.float64))
+        np.testing.assert_array_equal(scaled.imag, want_im[N - 1].astype(np.float64))
+    else:
+        rows = oracle_mod.rows((A_re + 1j * A_im).astype(np.complex128), np.array([N - 1], dtype=np.uint32))[0]
+        np.testing.assert_array_equal(scaled, np.round(rows * N))

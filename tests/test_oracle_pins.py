@@ -250,6 +250,20 @@ def test_band_support(oracle_mod, n, s):
     assert len(allowed) * (1 << n) == oracle_mod.band_term_bound(n, s)
 
 
+def test_antidiagonal_support(oracle_mod):
+    # remark after the diagonal case (Sec. IV-A): replacing I, Z by X, Y, an
+    # anti-diagonal matrix has coefficients only on strings with X or Y on
+    # every qubit, x = 2^n - 1; brute force over the entries agrees
+    n = 4
+    N = 1 << n
+    ad = synth.antidiagonal_complex(n, seed=80)
+    c = oracle_mod.decompose(synth.dense_from_antidiagonal(ad))
+    assert np.all(c[:N - 1] == 0) and np.any(c[N - 1] != 0)
+    k = np.arange(N)
+    xs = sorted({int(x) for x in (k ^ (N - 1 - k))})
+    assert xs == [N - 1]
+
+
 # -- Sec. IV-B combinations --------------------------------------------------
 
 def test_kronecker_factorisation(oracle_mod):
