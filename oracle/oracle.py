@@ -338,3 +338,15 @@ def linear_combination(mu: complex, ca: np.ndarray, cb: np.ndarray) -> np.ndarra
     out.real = (mr * ca.real - mi * ca.imag) + cb.real
     out.imag = (mr * ca.imag + mi * ca.real) + cb.imag
     return out
+
+
+# --------------------------------------------------------------------------
+# block-encoding by a linear combination of the strings (Sec. VI-C)
+
+def lcu_amplitudes(c: np.ndarray):
+    """Amplitudes of the ancilla state sum_i sqrt(|alpha_i|) |i> /
+    sqrt(sum_j |alpha_j|) over the strings, in float64, and the 1-norm
+    lambda = sum_j |alpha_j|; the phase of each alpha goes with its string."""
+    a = np.abs(np.asarray(c).astype(np.complex128))
+    lam = float(a.sum())
+    return (np.sqrt(a / lam) if lam > 0 else np.zeros_like(a)), lam

@@ -364,3 +364,27 @@ def test_linearity(oracle_mod):
     got32 = oracle_mod.linear_combination(mu, cA.astype(np.complex64), cB.astype(np.complex64))
     assert got32.dtype == np.complex64
     np.testing.assert_allclose(got32, mu * cA + cB, rtol=0, atol=1e-5)
+
+
+# -- Sec. VI-C: block-encoding by a linear combination of the strings --------
+
+@pytest.mark.parametrize("hermitian", [False, True])
+def test_lcu_amplitudes_block_encode(oracle_mod, hermitian):
+    # PREP prepares sum_i sqrt(|alpha_i|/lambda) |i>, SELECT applies
+    # (alpha_i/|alpha_i|) P_i; the top-left block of PREP^H SELECT PREP is
+    # sum_i (|alpha_i|/lambda) (alpha_i/|alpha_i|) P_i = A / lambda.  So the
+    # squared amplitudes, with the coefficients' phases put back and scaled by
+    # lambda, must rebuild A by the textbook Kronecker expansion, and they
+    # must form a unit vector.
+    n = 3
+    A = synth.hermitian(n, seed=81) if hermitian else synth.dense(n, seed=81)
+    c = oracle_mod.decompose(A)
+    amp, lam = oracle_mod.lcu_amplitudes(c.real if hermitian else c)
+    assert abs(float(np.sum(amp ** 2)) - 1.0) <= 1e-14
+    assert lam == pytest.approx(float(np.abs(c).sum()), rel=1e-15)
+    phase = np.where(np.abs(c) > 0, c / np.where(np.abs(c) > 0, np.abs(c), 1), 0)
+    back = oracle_mod.reconstruct_textbook(amp ** 2 * phase) * lam
+    np.testing.assert_allclose(back, A, rtol=0, atol=1e-13)
+    # an all-zero array has no normalisation: amplitudes zero, lambda zero
+    z, lz = oracle_mod.lcu_amplitudes(np.zeros((4, 4), dtype=np.complex128))
+    assert lz == 0.0 and np.all(z == 0)
