@@ -450,6 +450,14 @@ def main() -> int:
         byt = 3.0 * 16 * 4 ** n13
         alg["linear_combination_n13"] = {"ms": round(ms_lc, 4), "GBps": round(byt / ms_lc / 1e6, 1),
                                          "hbm_frac": round(byt / (ms_lc * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+        # Sec. VI-C preparation amplitudes: a float64 1-norm pass over c, then
+        # one pass writing the real amplitudes
+        amp = torch.empty((N13, N13), dtype=torch.float64, device=dev)
+        ms_lcu = _time(lambda: ptd.lcu_amplitudes(ca, out=amp), 10, 3, stream)
+        byt = 2 * 16.0 * 4 ** n13 + 8.0 * 4 ** n13
+        alg["lcu_amplitudes_n13"] = {"ms": round(ms_lcu, 4), "GBps": round(byt / ms_lcu / 1e6, 1),
+                                     "hbm_frac": round(byt / (ms_lcu * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+        del amp
         legs["algebra_c128"] = alg
         del ca, cb, lco
         torch.cuda.empty_cache()

@@ -250,6 +250,22 @@ ptd_status ptd_linear_combination(int n, ptd_dtype dtype, double mu_re, double m
                                   void *c_out, ptd_stream stream);
 
 /*
+ * State preparation for a block-encoding by a linear combination of the
+ * Pauli strings (Sec. VI-C, "Block-encoding using Pauli decomposition"): the
+ * ancilla state sum_i sqrt(|alpha_i|) |i> / sqrt(sum_j |alpha_j|), one real
+ * amplitude per coefficient of the dense array coeff (zero coefficients get
+ * amplitude zero; the phase of alpha_i is carried by the controlled string,
+ * as the paper absorbs signs into V_i).  amp_out[P] = sqrt(|c_P| / lambda)
+ * with lambda = sum_P |c_P| (|c| = sqrt(re^2 + im^2)), all in float64 and
+ * rounded once to the output type (float64 for PTD_C128, float32 for
+ * PTD_C64); lambda, the block-encoding's normalisation, is written to
+ * *lambda_host.  flags: PTD_HERMITIAN means coeff is real.  ws holds
+ * ptd_reduce_workspace_bytes() bytes; the call synchronises `stream`.
+ */
+ptd_status ptd_lcu_amplitudes(int n, ptd_dtype dtype, unsigned flags, const void *coeff, void *amp_out,
+                              double *lambda_host, void *ws, size_t ws_bytes, ptd_stream stream);
+
+/*
  * Parseval check (Theorem 1: the strings are orthogonal with Tr(P^* P) = 2^n,
  * so ||A||_F^2 = 2^n sum_P |c_P|^2).  Reduces both sides in float64 on the
  * device (also for PTD_C64 data) and copies them to out_host[0] =

@@ -5,8 +5,8 @@ computed by hand-written gfx950 HIP kernels behind a C ABI (include/ptd.h).
 """
 from .api import (  # noqa: F401
     ADJOINT, ANTIDIAGONAL, BANDED, BANDS_IN, C64, C128, COMPACT, COMPENSATED, DIAGONAL, HERMITIAN, BatchPlan,
-    block_diagonal, decompose, decompose_batched, direct_sum, hermitian_augment, linear_combination, nonempty_x,
-    num_nonempty_x, pad_to_power_of_two, parseval, reconstruct,
+    block_diagonal, decompose, decompose_batched, direct_sum, hermitian_augment, lcu_amplitudes,
+    linear_combination, nonempty_x, num_nonempty_x, pad_to_power_of_two, parseval, reconstruct,
 )
 from .labels import flat_index, index, label  # noqa: F401
 from .autograd import PauliDecompose, PauliReconstruct, pauli_decompose, pauli_reconstruct  # noqa: F401

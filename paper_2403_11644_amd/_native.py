@@ -43,6 +43,7 @@ SIGNATURES = {
     "ptd_direct_sum": (I, [I, I, U, P, P, P, P]),
     "ptd_hermitian_augment": (I, [I, I, U, P, P, P]),
     "ptd_linear_combination": (I, [I, I, D, D, P, P, P, P]),
+    "ptd_lcu_amplitudes": (I, [I, I, U, P, P, P, P, SZ, P]),
     "ptd_autotune": (I, [I, I, U, I, P, P, P, P, P, P]),
     "ptd_set_tuning": (I, [I, I, U, I, I]),
     "ptd_get_tuning": (I, [I, I, U, P, P]),

@@ -311,6 +311,31 @@ def linear_combination(mu, ca: torch.Tensor, cb: torch.Tensor, *, out: torch.Ten
     return out
 
 
+def lcu_amplitudes(c: torch.Tensor, *, hermitian: bool = False, out: torch.Tensor | None = None, stream=None):
+    """Amplitudes sqrt(|c_P| / lambda) of the ancilla state that prepares a
+    block-encoding by a linear combination of the strings, and lambda =
+    sum_P |c_P| (float64 sums on the device).  Returns (amplitudes, lambda);
+    c is complex, or real with hermitian=True."""
+    import numpy as np
+
+    n = _coeff_square(c, "c")
+    if hermitian:
+        if c.dtype not in (torch.float64, torch.float32):
+            raise TypeError("hermitian=True takes real float64/float32 coefficients")
+        code = C128 if c.dtype == torch.float64 else C64
+    else:
+        code = _dtype_code(c.dtype)
+    out = _check_out(out, tuple(c.shape), _real_dtype(code), c.device)
+    L = _native.lib()
+    wsb = L.ptd_reduce_workspace_bytes()
+    ws = torch.empty(wsb, dtype=torch.uint8, device=c.device)
+    lam = np.zeros(1, dtype=np.float64)
+    st = L.ptd_lcu_amplitudes(n, code, HERMITIAN if hermitian else 0, _ptr(c), _ptr(out),
+                              ctypes.c_void_p(lam.ctypes.data), _ptr(ws), wsb, _stream_handle(c.device, stream))
+    _native.check(st, "ptd_lcu_amplitudes")
+    return out, float(lam[0])
+
+
 def _debug_decompose_path(A: torch.Tensor, path: int, hermitian: bool = False) -> torch.Tensor:
     """Run a specific dense schedule (1 = single pass, 2 = two passes); for tests."""
     code = _dtype_code(A.dtype)

@@ -268,6 +268,17 @@ ptd_status ptd_linear_combination(int n, ptd_dtype dtype, double mu_re, double m
     return hip_status(ptd::launch_linear_combination(n, dtype, mu_re, mu_im, ca, cb, c_out, (hipStream_t)stream));
 }
 
+ptd_status ptd_lcu_amplitudes(int n, ptd_dtype dtype, unsigned flags, const void* coeff, void* amp_out,
+                              double* lambda_host, void* ws, size_t ws_bytes, ptd_stream stream)
+{
+    if (n < 1 || n > 16 || !valid_dtype(dtype) || !coeff || !amp_out || !lambda_host) return PTD_EINVAL;
+    if (flags & ~PTD_HERMITIAN) return PTD_EINVAL;
+    if (coeff == amp_out) return PTD_EINVAL;
+    if (!ws || ws_bytes < ptd::reduce_workspace_bytes()) return PTD_ENOSPC;
+    return hip_status(ptd::launch_lcu_amplitudes(n, dtype, flags & PTD_HERMITIAN, coeff, amp_out, ws, lambda_host,
+                                                 (hipStream_t)stream));
+}
+
 // Testing hook: force the single-pass (path 1) or two-pass (path 2) schedule.
 ptd_status ptd_debug_decompose_path(int n, ptd_dtype dtype, unsigned flags, const void* A, int64_t lda,
                                     void* coeff, int path, ptd_stream stream)

@@ -127,6 +127,10 @@ hipError_t launch_hermitian_augment(int n, ptd_dtype dt, bool compact, const voi
 hipError_t launch_linear_combination(int n, ptd_dtype dt, double mu_re, double mu_im, const void* a, const void* b,
                                      void* out, hipStream_t st);
 
+// LCU preparation amplitudes amp = sqrt(|c| / sum|c|) (ws: reduce_workspace_bytes()).
+hipError_t launch_lcu_amplitudes(int n, ptd_dtype dt, bool real_coeff, const void* coeff, void* amp, void* ws,
+                                 double* lambda_host, hipStream_t st);
+
 // Parseval residual: out_host[0] = ||A||_F^2, [1] = 2^n sum|c|^2, [2] = relative gap.
 size_t reduce_workspace_bytes();
 hipError_t launch_parseval(int n, ptd_dtype dt, bool real_coeff, const void* A, int64_t lda, const void* coeff,

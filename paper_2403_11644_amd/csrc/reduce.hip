@@ -1,4 +1,5 @@
-// reduce.hip -- float64 norm reductions for the Parseval residual.
+// reduce.hip -- float64 norm reductions: the Parseval residual and the
+// 1-norm behind the LCU state preparation.
 //
 // Theorem 1 of the paper makes the Pauli strings orthogonal with
 // Tr(P^* P) = 2^n, hence ||A||_F^2 = 2^n sum_P |c_P|^2.  Both sides are summed
@@ -125,6 +126,72 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish(const double* __restrict
     }
 }
 
+// 1-norm sum_P |c_P| in float64: |c| = sqrt(re^2 + im^2) for complex c, the
+// absolute value for real c (count values of the array's element type)
+template <class V, bool REAL>
+__global__ __launch_bounds__(RED_THREADS) void k_abssum(const void* __restrict__ c, int64_t count,
+                                                         double* __restrict__ partial)
+{
+    __shared__ double sh[RED_THREADS];
+    const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < count; i += stride) {
+        if constexpr (REAL) {
+            const double a = (double)((const V*)c)[i];
+            acc += a < 0 ? -a : a;
+        } else {
+            const cplx<V> v = ((const cplx<V>*)c)[i];
+            const double a = (double)v.re, b = (double)v.im;
+            acc += sqrt(a * a + b * b);
+        }
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_finish1(const double* __restrict__ p, int nblk,
+                                                         double* __restrict__ out)
+{
+    __shared__ double sh[RED_THREADS];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += RED_THREADS) a += p[i];
+    const double s = block_sum(a, sh);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+// amp[i] = sqrt(|c_i| / lambda), lambda = *norm1 (0 for an all-zero array),
+// evaluated in float64 and rounded once to V
+template <class V, bool REAL>
+__global__ __launch_bounds__(RED_THREADS) void k_lcu_amp(const void* __restrict__ c, V* __restrict__ amp,
+                                                          int64_t count, const double* __restrict__ norm1)
+{
+    const double lam = *norm1;
+    const double inv = lam > 0.0 ? 1.0 / lam : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * RED_THREADS) {
+        double a;
+        if constexpr (REAL) {
+            a = (double)((const V*)c)[i];
+            a = a < 0 ? -a : a;
+        } else {
+            const cplx<V> v = ((const cplx<V>*)c)[i];
+            const double x = (double)v.re, y = (double)v.im;
+            a = sqrt(x * x + y * y);
+        }
+        amp[i] = (V)sqrt(a * inv);
+    }
+}
+
+template <class V, bool REAL>
+hipError_t lcu_t(int64_t count, const void* c, void* amp, double* partial, double* fin, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_abssum<V, REAL>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, c, count, partial);
+    hipLaunchKernelGGL(k_finish1, dim3(1), dim3(RED_THREADS), 0, st, partial, RED_BLOCKS, fin);
+    hipLaunchKernelGGL((k_lcu_amp<V, REAL>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, c, (V*)amp, count,
+                       (const double*)fin);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 size_t reduce_workspace_bytes() { return (size_t)(2 * RED_BLOCKS + 2) * sizeof(double); }
@@ -159,6 +226,29 @@ hipError_t launch_parseval(int n, ptd_dtype dt, bool real_coeff, const void* A, 
     out_host[1] = h[1] * (double)((int64_t)1 << n);
     const double d = out_host[0] - out_host[1];
     out_host[2] = (d < 0 ? -d : d) / (out_host[0] > 0 ? out_host[0] : 1.0);
+    return hipSuccess;
+}
+
+hipError_t launch_lcu_amplitudes(int n, ptd_dtype dt, bool real_coeff, const void* coeff, void* amp, void* ws,
+                                 double* lambda_host, hipStream_t st)
+{
+    double* partial = (double*)ws;
+    double* fin = partial + RED_BLOCKS;
+    const int64_t count = (int64_t)1 << (2 * n);
+    hipError_t e;
+    if (dt == PTD_C128)
+        e = real_coeff ? lcu_t<double, true>(count, coeff, amp, partial, fin, st)
+                       : lcu_t<double, false>(count, coeff, amp, partial, fin, st);
+    else
+        e = real_coeff ? lcu_t<float, true>(count, coeff, amp, partial, fin, st)
+                       : lcu_t<float, false>(count, coeff, amp, partial, fin, st);
+    if (e != hipSuccess) return e;
+    double h = 0.0;
+    e = hipMemcpyAsync(&h, fin, sizeof h, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    *lambda_host = h;
     return hipSuccess;
 }
 

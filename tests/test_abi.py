@@ -261,3 +261,22 @@ def test_row_pitch_of_a_single_row():
     assert api._rows(v, "v") == 8
     assert api._rows(torch.zeros(3, 8), "m") == 8
     assert api._rows(torch.zeros(8, 16)[:, :8], "m") == 16
+
+
+def test_lcu_argument_errors(lib):
+    EINVAL, ENOSPC = -1, -2
+    big, far, ws = 1 << 40, 1 << 41, 1 << 42
+    lam = ctypes.c_double()
+    wsb = lib.ptd_reduce_workspace_bytes()
+    f = lambda n=3, dt=0, flags=0, c=big, o=far, lp=ctypes.byref(lam), w=ws, wb=wsb: lib.ptd_lcu_amplitudes(
+        n, dt, flags, c, o, lp, w, wb, None)
+    assert f(n=0) == EINVAL
+    assert f(n=17) == EINVAL
+    assert f(dt=4) == EINVAL
+    assert f(flags=2) == EINVAL  # only PTD_HERMITIAN
+    assert f(c=0) == EINVAL
+    assert f(o=0) == EINVAL
+    assert f(lp=None) == EINVAL
+    assert f(o=big) == EINVAL  # in place is not allowed
+    assert f(w=0) == ENOSPC
+    assert f(wb=wsb - 8) == ENOSPC

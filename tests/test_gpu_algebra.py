@@ -1,7 +1,8 @@
 """GPU parity of the Sec. IV-B combinations (direct sum, block-diagonal
 assembly, Hermitian augmentation, linear combination) against the oracle's
 versions on the same coefficient arrays, and end to end against decomposing
-the assembled matrix on the device."""
+the assembled matrix on the device; and of the Sec. VI-C preparation
+amplitudes of a block-encoding by a linear combination of the strings."""
 import numpy as np
 import pytest
 
@@ -123,3 +124,37 @@ def test_end_to_end_against_decomposition(ptd, dt):
     mu = -0.5 + 2.0j
     got = to_host(ptd.linear_combination(mu, cA, cB))
     assert rel_err(got, to_host(ptd.decompose(mu * dA + dB))) <= tol
+
+
+# --------------------------------------------------------------------------
+# Sec. VI-C: amplitudes of the LCU preparation state
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("n", [1, 5, 10, 13])
+@pytest.mark.parametrize("hermitian", [False, True])
+def test_lcu_amplitudes(ptd, oracle_mod, dt, n, hermitian):
+    c = _coeffs(n, 60 + n, dt)
+    if hermitian:
+        c = np.ascontiguousarray(c.real)
+    amp, lam = ptd.lcu_amplitudes(to_dev(c), hermitian=hermitian)
+    want, wlam = oracle_mod.lcu_amplitudes(c)
+    assert lam == pytest.approx(wlam, rel=1e-13)
+    got = to_host(amp)
+    assert got.dtype == (np.float64 if dt == np.complex128 else np.float32)
+    assert rel_err(got, want) <= (1e-14 if dt == np.complex128 else 1e-6)
+    assert abs(float(np.sum(got.astype(np.float64) ** 2)) - 1.0) <= (1e-12 if dt == np.complex128 else 1e-5)
+
+
+def test_lcu_amplitudes_zero_and_sparse(ptd, oracle_mod):
+    import torch
+
+    z = torch.zeros((16, 16), dtype=torch.complex128, device="cuda")
+    amp, lam = ptd.lcu_amplitudes(z)
+    assert lam == 0.0 and float(amp.abs().max()) == 0.0
+    # a few nonzero coefficients: their amplitudes exactly as the oracle's
+    c = np.zeros((16, 16), dtype=np.complex128)
+    c[3, 5], c[0, 0], c[15, 15] = -4.0, 1.0, 3.0j
+    amp, lam = ptd.lcu_amplitudes(to_dev(c))
+    want, wlam = oracle_mod.lcu_amplitudes(c)
+    assert lam == wlam == 8.0
+    np.testing.assert_array_equal(to_host(amp), want)
