@@ -350,3 +350,17 @@ def lcu_amplitudes(c: np.ndarray):
     a = np.abs(np.asarray(c).astype(np.complex128))
     lam = float(a.sum())
     return (np.sqrt(a / lam) if lam > 0 else np.zeros_like(a)), lam
+
+
+# --------------------------------------------------------------------------
+# matrix-free input: a Toeplitz matrix from its 2^(n+1) - 1 defining entries
+
+def toeplitz_matrix(t: np.ndarray) -> np.ndarray:
+    """Dense A with A[r][c] = t[c - r + N - 1] (t[0] the bottom-left entry,
+    t[N - 1] the diagonal, t[2N - 2] the top-right), for the oracle to
+    decompose by the definition."""
+    t = np.asarray(t)
+    N = (t.shape[0] + 1) // 2
+    r = np.arange(N)[:, None]
+    c = np.arange(N)[None, :]
+    return t[c - r + N - 1]

@@ -388,3 +388,18 @@ def test_lcu_amplitudes_block_encode(oracle_mod, hermitian):
     # an all-zero array has no normalisation: amplitudes zero, lambda zero
     z, lz = oracle_mod.lcu_amplitudes(np.zeros((4, 4), dtype=np.complex128))
     assert lz == 0.0 and np.all(z == 0)
+
+
+def test_toeplitz_matrix(oracle_mod):
+    # A[r][c] = t[c - r + N - 1] is scipy's Toeplitz matrix with first column
+    # t[N-1], t[N-2], ..., t[0] and first row t[N-1], ..., t[2N-2]; its
+    # decomposition has the Toeplitz structure's symmetry: conj-reversing t
+    # gives A^H, whose coefficients are the conjugates (P Hermitian)
+    n = 3
+    N = 1 << n
+    t = synth.complex_normal(2 * N - 1, seed=85)
+    A = oracle_mod.toeplitz_matrix(t)
+    np.testing.assert_array_equal(A, scipy.linalg.toeplitz(t[N - 1::-1], t[N - 1:]))
+    cA = oracle_mod.decompose(A)
+    cH = oracle_mod.decompose(oracle_mod.toeplitz_matrix(np.conj(t[::-1])))
+    np.testing.assert_allclose(cH, np.conj(cA), rtol=0, atol=1e-15)
