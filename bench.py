@@ -197,7 +197,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="all",
                     help="comma list of reported legs to run: complex64, two_pass, copy, reconstruct, parseval, "
-                         "small, hermitian, band, algebra, n15, batched; 'all' or 'none'")
+                         "small, hermitian, band, toeplitz, algebra, n15, batched; 'all' or 'none'")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc folders (FETCH_SIZE, WRITE_SIZE) "
@@ -258,7 +258,7 @@ def main() -> int:
     want_legs = set()
     if args.legs == "all":
         want_legs = {"complex64", "two_pass", "copy", "reconstruct", "parseval", "small", "hermitian", "band",
-                     "algebra", "n15", "batched"}
+                     "toeplitz", "algebra", "n15", "batched"}
     elif args.legs != "none":
         want_legs = set(args.legs.split(","))
     if "reconstruct" in want_legs:
@@ -417,6 +417,23 @@ def main() -> int:
         band_legs["antidiag"] = {"nonempty_x": 1, "from_vector_compact_us": round(us, 2)}
         del adv, aout
         legs["structured_n14"] = band_legs
+    if "toeplitz" in want_legs:
+        # matrix-free Toeplitz input at the headline size: the kernels read the
+        # 2^15 - 1 defining entries (0.5 MiB, cache-resident) instead of A;
+        # same output, same arithmetic as the dense call
+        g.manual_seed(141)
+        tv = torch.randn(2 * N - 1, dtype=torch.complex128, device=dev, generator=g)
+        ms_t = _time(lambda: ptd.decompose(tv, toeplitz=True, out=out128), args.steps, args.warmup, stream)
+        leg = {"ms": round(ms_t, 4), "GCoeff_s": round(ncoef / ms_t / 1e6, 2),
+               "write_only_hbm_frac": round(16 * ncoef / (ms_t * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+               "speedup_vs_dense_f64": round(ms128 / ms_t, 3)}
+        tv64 = tv.to(torch.complex64)
+        o64 = torch.empty((N, N), dtype=torch.complex64, device=dev)
+        leg["complex64_ms"] = round(_time(lambda: ptd.decompose(tv64, toeplitz=True, out=o64), args.steps,
+                                          args.warmup, stream), 4)
+        legs["toeplitz_n14"] = leg
+        del tv, tv64, o64
+        torch.cuda.empty_cache()
     if "algebra" in want_legs:
         # Sec. IV-B combinations on coefficient arrays: one HBM pass each
         # (bytes = inputs read once + output written once)

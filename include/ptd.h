@@ -94,6 +94,15 @@ typedef void *ptd_stream;
  * writes the one row.  Not combined with PTD_DIAGONAL or PTD_BANDED; s is
  * ignored. */
 #define PTD_ANTIDIAGONAL (1u << 8)
+/* Matrix-free Toeplitz input (the paper's note that A may be evaluated from
+ * a function instead of stored, Sec. V-B): A is the vector t of 2^(n+1) - 1
+ * elements with A[r][c] = t[c - r + 2^n - 1] (t[0] is the bottom-left entry,
+ * t[2^n - 1] the diagonal, t[2^(n+1) - 2] the top-right); lda is ignored.
+ * The kernels read t (a few MiB at most, cache-resident) instead of 4^n
+ * entries.  Dense decompositions only: n <= 14, or n = 15 for complex64
+ * without PTD_HERMITIAN; PTD_EUNSUP beyond, and with structure flags or
+ * PTD_COMPENSATED.  With PTD_HERMITIAN, t[2^n - 1 - d] = conj(t[2^n - 1 + d]). */
+#define PTD_TOEPLITZ (1u << 9)
 
 /* Workspace (device bytes) a pauli_decompose call with these arguments
  * needs: a few KiB of queue counters for dense decompositions with

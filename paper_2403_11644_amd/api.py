@@ -21,6 +21,7 @@ BANDED = 1 << 2
 BANDS_IN = 1 << 3
 COMPACT = 1 << 4
 ANTIDIAGONAL = 1 << 8
+TOEPLITZ = 1 << 9
 COMPENSATED = 1 << 5
 ADJOINT = 1 << 6
 
@@ -108,7 +109,7 @@ def nonempty_x(n: int, structure: str | None = None, s: int = 0) -> list[int]:
 
 def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None = None, s: int | None = None,
               bands: bool = False, compact: bool = False, compensated: bool = False, pad: bool = False,
-              out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+              toeplitz: bool = False, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Pauli coefficients of A, as a (2^n, 2^n) tensor c[x, z].
 
     hermitian   A == A^*: return the (real) coefficients as float64/float32.
@@ -119,9 +120,28 @@ def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None
     compact     structured only: return rows of the nonempty X-patterns only.
     compensated complex64 only: TwoSum butterflies.
     pad         zero-pad a non-power-of-two A (top-left embedding).
+    toeplitz    A is the 1-D vector t of 2^(n+1) - 1 entries of a Toeplitz
+                matrix, A[r][c] = t[c - r + 2^n - 1] (matrix-free input).
     """
     _require_device(A, "A")
     code = _dtype_code(A.dtype)
+    if toeplitz:
+        if structure is not None or bands or pad or compact or compensated:
+            raise ValueError("toeplitz=True takes a dense decomposition only")
+        if A.dim() != 1 or not A.is_contiguous() or (A.shape[0] + 1) & A.shape[0] or A.shape[0] < 3:
+            raise ValueError("a Toeplitz input is a contiguous vector of 2^(n+1) - 1 entries")
+        N = (A.shape[0] + 1) // 2
+        n = _nqubits(N)
+        flags = TOEPLITZ | (HERMITIAN if hermitian else 0)
+        odt = _real_dtype(code) if hermitian else _complex_dtype(code)
+        out = _check_out(out, (N, N), odt, A.device)
+        L = _native.lib()
+        wsb = L.ptd_workspace_bytes(n, code, flags, 0)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=A.device) if wsb else None
+        st = L.pauli_decompose(n, code, flags, 0, _ptr(A), 0, _ptr(out), _ptr(ws) if ws is not None else None, wsb,
+                               _stream_handle(A.device, stream))
+        _native.check(st, "pauli_decompose")
+        return out
     flags = 0
     sv = 0
     if structure == "diagonal":

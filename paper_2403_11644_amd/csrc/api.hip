@@ -15,7 +15,7 @@ namespace {
 thread_local int g_last_hip_error = 0;
 
 constexpr unsigned kAllFlags = PTD_HERMITIAN | PTD_DIAGONAL | PTD_BANDED | PTD_BANDS_IN | PTD_COMPACT |
-                               PTD_COMPENSATED | PTD_ADJOINT | PTD_ANTIDIAGONAL;
+                               PTD_COMPENSATED | PTD_ADJOINT | PTD_ANTIDIAGONAL | PTD_TOEPLITZ;
 constexpr unsigned kStructure = PTD_DIAGONAL | PTD_BANDED | PTD_ANTIDIAGONAL;
 
 ptd_status hip_status(hipError_t e)
@@ -130,13 +130,22 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
     if (flags & PTD_ADJOINT) return PTD_EINVAL;
     const ptd_status sst = check_structure(n, flags, s);
     if (sst != PTD_OK) return sst;
-    if (lda < ((int64_t)1 << n)) return PTD_EINVAL;
+    const bool toep = flags & PTD_TOEPLITZ;
+    if (!toep && lda < ((int64_t)1 << n)) return PTD_EINVAL;
     if ((flags & PTD_COMPENSATED) && dtype != PTD_C64) return PTD_EUNSUP;
     if (ws_bytes < ptd_workspace_bytes(n, dtype, flags, s)) return PTD_ENOSPC;
     (void)ws;
     if (A == coeff) return PTD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     const bool herm = flags & PTD_HERMITIAN;
+    if (toep) {
+        if (flags & (kStructure | PTD_COMPENSATED)) return PTD_EUNSUP;
+        if (n <= 10) return hip_status(ptd::launch_group_toeplitz(n, dtype, herm, A, coeff, st));
+        if (!use_fused(n, dtype, flags)) return PTD_EUNSUP;
+        if (!ws) return PTD_ENOSPC;
+        return hip_status(ptd::launch_fused_toeplitz(n, dtype, herm, A, coeff, ws, ptd::fused_default(n, dtype, herm).la,
+                                                     st));
+    }
     if (flags & kStructure) {
         if (flags & PTD_COMPENSATED) return PTD_EUNSUP;
         // s < 0 codes the anti-diagonal for the structured kernels

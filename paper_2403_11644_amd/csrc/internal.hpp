@@ -59,6 +59,16 @@ hipError_t fused_rec_c128_herm(int n, const void* coeff, void* A, int64_t lda, v
                                hipStream_t st);
 hipError_t launch_fused_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const void* coeff, void* A, int64_t lda,
                             void* ws, int la, hipStream_t st);
+// Matrix-free Toeplitz input t (A[r][c] = t[c - r + 2^n - 1]): the
+// single-launch schedule (n = 11..15 where it applies) and the single-pass
+// group kernel (n <= 10).
+hipError_t fused_toeplitz_c64(int n, const void* t, void* out, void* ws, int la, hipStream_t st);
+hipError_t fused_toeplitz_c128(int n, const void* t, void* out, void* ws, int la, hipStream_t st);
+hipError_t fused_toeplitz_c64h(int n, const void* t, void* out, void* ws, int la, hipStream_t st);
+hipError_t fused_toeplitz_c128h(int n, const void* t, void* out, void* ws, int la, hipStream_t st);
+hipError_t launch_fused_toeplitz(int n, ptd_dtype dt, bool herm, const void* t, void* out, void* ws, int la,
+                                 hipStream_t st);
+hipError_t launch_group_toeplitz(int n, ptd_dtype dt, bool herm, const void* t, void* out, hipStream_t st);
 // Zero `count` uint32 words with a small kernel (capturable, unlike a memset node).
 hipError_t launch_zero_words(uint32_t* p, int count, hipStream_t st);
 // Plain 16-byte-per-lane device copy (bandwidth reference).

@@ -432,3 +432,76 @@ def test_max_size_n16_strings(ptd, oracle_mod, dt):
     assert int((R != 0).sum().item()) == len(strings) * N
     del R, rows
     torch.cuda.empty_cache()
+
+
+# --------------------------------------------------------------------------
+# matrix-free Toeplitz input (PTD_TOEPLITZ): A[r][c] = t[c - r + 2^n - 1]
+
+def _toeplitz_vec(n, seed, dt, hermitian):
+    N = 1 << n
+    t = synth.complex_normal(2 * N - 1, seed=seed, dtype=dt)
+    if hermitian:
+        t[N - 1] = t[N - 1].real
+        t[:N - 1] = np.conj(t[N:][::-1])  # t[N-1-d] = conj(t[N-1+d])
+    return t
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 3, 6, 10, 11, 12, 13, 14])
+@pytest.mark.parametrize("hermitian", [False, True])
+def test_toeplitz_matches_dense(ptd, oracle_mod, dt, n, hermitian):
+    """The matrix-free path gathers the same values as the dense path and
+    runs the same butterflies, so it equals the dense decomposition of the
+    materialised matrix bit for bit; sampled coefficients against the oracle."""
+    import torch
+
+    N = 1 << n
+    t = _toeplitz_vec(n, 300 + n, _np_dtype(dt), hermitian)
+    td = to_dev(t)
+    got = ptd.decompose(td, toeplitz=True, hermitian=hermitian)
+    idx = torch.arange(N, device="cuda")[None, :] - torch.arange(N, device="cuda")[:, None] + (N - 1)
+    Ad = td[idx]
+    del idx
+    dense = ptd.decompose(Ad, hermitian=hermitian)
+    assert bool(torch.equal(got, dense))
+    del dense
+    if n <= 12:
+        A = oracle_mod.toeplitz_matrix(t.astype(np.complex128))
+        xs, zs = synth.sample_strings(n, 500, seed=11)
+        want = oracle_mod.coeffs(A, xs, zs)
+        if hermitian:
+            want = want.real
+        g = to_host(got[to_dev(xs.astype(np.int64)), to_dev(zs.astype(np.int64))])
+        assert rel_err(g, want) <= TOL[dt]
+    del got, Ad
+    torch.cuda.empty_cache()
+
+
+def test_toeplitz_n15_complex64(ptd):
+    import torch
+
+    n, N = 15, 1 << 15
+    t = _toeplitz_vec(n, 315, np.complex64, False)
+    td = to_dev(t)
+    got = ptd.decompose(td, toeplitz=True)
+    idx = torch.arange(N, device="cuda")[None, :] - torch.arange(N, device="cuda")[:, None] + (N - 1)
+    Ad = td[idx]
+    del idx
+    assert bool(torch.equal(got, ptd.decompose(Ad)))
+    del got, Ad
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n", [2, 5, 8])
+def test_toeplitz_integer_exact(ptd, oracle_mod, n):
+    N = 1 << n
+    rng = np.random.default_rng(330 + n)
+    tre = rng.integers(-8, 9, size=2 * N - 1)
+    tim = rng.integers(-8, 9, size=2 * N - 1)
+    t = (tre + 1j * tim).astype(np.complex64)
+    got = to_host(ptd.decompose(to_dev(t), toeplitz=True)).astype(np.complex128) * N
+    A = oracle_mod.toeplitz_matrix(t.astype(np.complex128))
+    wr, wi = oracle_mod.decompose_int(A.real.astype(np.int64), A.imag.astype(np.int64))
+    np.testing.assert_array_equal(got.real, wr.astype(np.float64))
+    np.testing.assert_array_equal(got.imag, wi.astype(np.float64))
+
