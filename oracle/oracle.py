@@ -364,3 +364,29 @@ def toeplitz_matrix(t: np.ndarray) -> np.ndarray:
     r = np.arange(N)[:, None]
     c = np.arange(N)[None, :]
     return t[c - r + N - 1]
+
+
+# --------------------------------------------------------------------------
+# sparse input (the structured-case argument of Sec. IV-A, for any pattern)
+
+def sparse_to_dense(n: int, rows, cols, vals) -> np.ndarray:
+    """The 2^n x 2^n matrix with the coordinate entries added up; entries
+    outside [0, 2^n) are dropped."""
+    N = 1 << n
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    vals = np.asarray(vals)
+    ok = (rows >= 0) & (rows < N) & (cols >= 0) & (cols < N)
+    A = np.zeros((N, N), dtype=np.complex128)
+    np.add.at(A, (rows[ok], cols[ok]), vals[ok].astype(np.complex128))
+    return A
+
+
+def sparse_nonempty_x(n: int, rows, cols) -> list[int]:
+    """The X-patterns r ^ c of the entries in range, ascending: the strings
+    with X-pattern x read only the entries (k, k ^ x)."""
+    N = 1 << n
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    ok = (rows >= 0) & (rows < N) & (cols >= 0) & (cols < N)
+    return sorted({int(x) for x in (rows[ok] ^ cols[ok])})

@@ -403,3 +403,19 @@ def test_toeplitz_matrix(oracle_mod):
     cA = oracle_mod.decompose(A)
     cH = oracle_mod.decompose(oracle_mod.toeplitz_matrix(np.conj(t[::-1])))
     np.testing.assert_allclose(cH, np.conj(cA), rtol=0, atol=1e-15)
+
+
+def test_sparse_support(oracle_mod):
+    # any sparsity pattern: the rows x of nonzero coefficients are exactly the
+    # r ^ c of the entries (generic values), the others are exactly zero
+    n = 5
+    N = 1 << n
+    rng = np.random.default_rng(86)
+    rows = rng.integers(0, N, size=12)
+    cols = rng.integers(0, N, size=12)
+    vals = rng.standard_normal(12) + 1j * rng.standard_normal(12)
+    A = oracle_mod.sparse_to_dense(n, np.append(rows, [N, -1]), np.append(cols, [0, 3]), np.append(vals, [1, 1]))
+    assert np.count_nonzero(A) == len({(r, c) for r, c in zip(rows, cols)})
+    c = oracle_mod.decompose(A)
+    nz = [x for x in range(N) if np.any(c[x] != 0)]
+    assert nz == oracle_mod.sparse_nonempty_x(n, rows, cols)
