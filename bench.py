@@ -416,6 +416,22 @@ def main() -> int:
         us = _call_us(skip_call(adv, api.ANTIDIAGONAL | api.BANDS_IN | api.COMPACT, 0, aout, N), 20, 5, stream)
         band_legs["antidiag"] = {"nonempty_x": 1, "from_vector_compact_us": round(us, 2)}
         del adv, aout
+        # sparse coordinate input: 7 entries per row within distance 3 of the
+        # diagonal plus 64 scattered ones; the call lists its X-patterns and
+        # checks them (two host synchronisations), then fills and transforms
+        rng = np.random.default_rng(17)
+        r = np.repeat(np.arange(N), 7)
+        c = np.clip(r + np.tile(np.arange(-3, 4), N), 0, N - 1)
+        r = np.append(r, rng.integers(0, N, 64))
+        c = np.append(c, rng.integers(0, N, 64))
+        rd = torch.from_numpy(r.astype(np.int32)).to(dev)
+        cd = torch.from_numpy(c.astype(np.int32)).to(dev)
+        vd = torch.randn(r.shape[0], dtype=torch.complex128, device=dev, generator=g)
+        sp_out, sp_xs = ptd.decompose_sparse(rd, cd, vd, n, compact=True)
+        us = _call_us(lambda: ptd.decompose_sparse(rd, cd, vd, n, compact=True, out=sp_out), 10, 3, stream)
+        band_legs["sparse"] = {"nnz": int(r.shape[0]), "nonempty_x": int(sp_xs.numel()),
+                               "call_compact_us": round(us, 2)}
+        del rd, cd, vd, sp_out, sp_xs
         legs["structured_n14"] = band_legs
     if "toeplitz" in want_legs:
         # matrix-free Toeplitz input at the headline size: the kernels read the

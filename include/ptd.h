@@ -201,6 +201,35 @@ ptd_status ptd_batch_plan_launch(ptd_plan *plan, ptd_stream stream);
 void ptd_batch_plan_destroy(ptd_plan *plan);
 
 /*
+ * Sparse input.  The argument of Sec. IV-A for diagonal and band matrices
+ * holds for any sparsity pattern: the strings with X-pattern x read only the
+ * entries (k, k ^ x), so only the x = r ^ c of nonzero entries (r, c) can
+ * carry a coefficient.  The matrix is given as nnz coordinate entries in
+ * device memory: rows[i], cols[i] (int32) and vals[i] (complex of dtype);
+ * repeated coordinates are summed, entries outside [0, 2^n) ignored.
+ *
+ * ptd_sparse_nonempty_x writes those X-patterns, ascending, to the device
+ * array xs_out (room for min(nnz, 2^n) entries) and their number to
+ * *count_host; it synchronises `stream`.
+ *
+ * pauli_decompose_sparse computes the coefficients of the listed X-patterns
+ * xs[0..count) (device array, strictly ascending in [0, 2^n), as
+ * ptd_sparse_nonempty_x gives them; else PTD_EINVAL after a device-side check
+ * that synchronises `stream` once): the entries are added into their zeroed
+ * output rows, then transformed in place.  Output: the dense 2^n x 2^n
+ * coefficient array (rows not listed are zero), or with PTD_COMPACT the
+ * count x 2^n rows of the listed X-patterns.  Entries whose X-pattern is
+ * not listed are ignored.  flags: 0 or PTD_COMPACT.  ws holds
+ * ptd_sparse_workspace_bytes(n) bytes (both calls).
+ */
+size_t ptd_sparse_workspace_bytes(int n);
+ptd_status ptd_sparse_nonempty_x(int n, int64_t nnz, const int32_t *rows, const int32_t *cols, uint32_t *xs_out,
+                                 int *count_host, void *ws, size_t ws_bytes, ptd_stream stream);
+ptd_status pauli_decompose_sparse(int n, ptd_dtype dtype, unsigned flags, int64_t nnz, const int32_t *rows,
+                                  const int32_t *cols, const void *vals, const uint32_t *xs, int count, void *coeff,
+                                  void *ws, size_t ws_bytes, ptd_stream stream);
+
+/*
  * Combinations of decompositions (Sec. IV-B, "Combinations of matrices"):
  * the coefficients of a matrix assembled from matrices whose coefficients
  * are known, computed from those coefficients alone, with no matrix formed

@@ -44,6 +44,9 @@ SIGNATURES = {
     "ptd_hermitian_augment": (I, [I, I, U, P, P, P]),
     "ptd_linear_combination": (I, [I, I, D, D, P, P, P, P]),
     "ptd_lcu_amplitudes": (I, [I, I, U, P, P, P, P, SZ, P]),
+    "ptd_sparse_workspace_bytes": (SZ, [I]),
+    "ptd_sparse_nonempty_x": (I, [I, I64, P, P, P, P, P, SZ, P]),
+    "pauli_decompose_sparse": (I, [I, I, U, I64, P, P, P, P, I, P, P, SZ, P]),
     "ptd_autotune": (I, [I, I, U, I, P, P, P, P, P, P]),
     "ptd_set_tuning": (I, [I, I, U, I, I]),
     "ptd_get_tuning": (I, [I, I, U, P, P]),

@@ -331,6 +331,47 @@ def linear_combination(mu, ca: torch.Tensor, cb: torch.Tensor, *, out: torch.Ten
     return out
 
 
+def decompose_sparse(rows: torch.Tensor, cols: torch.Tensor, vals: torch.Tensor, n: int, *, compact: bool = False,
+                     out: torch.Tensor | None = None, stream=None):
+    """Coefficients of a sparse 2^n x 2^n matrix given by coordinate entries
+    (int32 rows and cols, complex vals, all on the GPU; repeated coordinates
+    are summed).  Only the X-patterns r ^ c of its entries can be nonzero;
+    returns (coefficients, xs): the dense (2^n, 2^n) array, or with
+    compact=True the rows of those X-patterns only, and their ascending list
+    xs (an int64 tensor on the device)."""
+    import numpy as np
+
+    for t, name in ((rows, "rows"), (cols, "cols"), (vals, "vals")):
+        _require_device(t, name)
+        if t.dim() != 1 or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous 1-D tensor" % name)
+    if rows.dtype != torch.int32 or cols.dtype != torch.int32:
+        raise TypeError("rows and cols must be int32")
+    nnz = rows.shape[0]
+    if cols.shape[0] != nnz or vals.shape[0] != nnz:
+        raise ValueError("rows, cols and vals must have the same length")
+    code = _dtype_code(vals.dtype)
+    N = 1 << n
+    L = _native.lib()
+    wsb = L.ptd_sparse_workspace_bytes(n)
+    if wsb == 0:
+        raise ValueError("n must lie in 1..16")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=vals.device)
+    xs = torch.empty(max(1, min(nnz, N)), dtype=torch.int32, device=vals.device)
+    cnt = ctypes.c_int()
+    st = L.ptd_sparse_nonempty_x(n, nnz, _ptr(rows), _ptr(cols), _ptr(xs), ctypes.byref(cnt), _ptr(ws), wsb,
+                                 _stream_handle(vals.device, stream))
+    _native.check(st, "ptd_sparse_nonempty_x")
+    count = cnt.value
+    out = _check_out(out, ((count if compact else N), N), vals.dtype, vals.device)
+    if compact and count == 0:
+        return out, xs[:0].to(torch.int64)
+    st = L.pauli_decompose_sparse(n, code, COMPACT if compact else 0, nnz, _ptr(rows), _ptr(cols), _ptr(vals),
+                                  _ptr(xs), count, _ptr(out), _ptr(ws), wsb, _stream_handle(vals.device, stream))
+    _native.check(st, "pauli_decompose_sparse")
+    return out, xs[:count].to(torch.int64)
+
+
 def lcu_amplitudes(c: torch.Tensor, *, hermitian: bool = False, out: torch.Tensor | None = None, stream=None):
     """Amplitudes sqrt(|c_P| / lambda) of the ancilla state that prepares a
     block-encoding by a linear combination of the strings, and lambda =

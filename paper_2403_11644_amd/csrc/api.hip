@@ -277,6 +277,38 @@ ptd_status ptd_linear_combination(int n, ptd_dtype dtype, double mu_re, double m
     return hip_status(ptd::launch_linear_combination(n, dtype, mu_re, mu_im, ca, cb, c_out, (hipStream_t)stream));
 }
 
+size_t ptd_sparse_workspace_bytes(int n)
+{
+    if (n < 1 || n > 16) return 0;
+    return ptd::sparse_workspace_bytes(n);
+}
+
+ptd_status ptd_sparse_nonempty_x(int n, int64_t nnz, const int32_t* rows, const int32_t* cols, uint32_t* xs_out,
+                                 int* count_host, void* ws, size_t ws_bytes, ptd_stream stream)
+{
+    if (n < 1 || n > 16 || nnz < 0 || !xs_out || !count_host) return PTD_EINVAL;
+    if (nnz > 0 && (!rows || !cols)) return PTD_EINVAL;
+    if (!ws || ws_bytes < ptd::sparse_workspace_bytes(n)) return PTD_ENOSPC;
+    return hip_status(ptd::launch_sparse_nonempty_x(n, nnz, rows, cols, xs_out, count_host, ws, (hipStream_t)stream));
+}
+
+ptd_status pauli_decompose_sparse(int n, ptd_dtype dtype, unsigned flags, int64_t nnz, const int32_t* rows,
+                                  const int32_t* cols, const void* vals, const uint32_t* xs, int count, void* coeff,
+                                  void* ws, size_t ws_bytes, ptd_stream stream)
+{
+    if (n < 1 || n > 16 || !valid_dtype(dtype) || nnz < 0 || !coeff) return PTD_EINVAL;
+    if (flags & ~PTD_COMPACT) return PTD_EINVAL;
+    if (nnz > 0 && (!rows || !cols || !vals)) return PTD_EINVAL;
+    if (count < 0 || count > (1 << n) || (count > 0 && !xs)) return PTD_EINVAL;
+    if (coeff == vals) return PTD_EINVAL;
+    if (!ws || ws_bytes < ptd::sparse_workspace_bytes(n)) return PTD_ENOSPC;
+    bool bad = false;
+    const ptd_status st = hip_status(ptd::launch_sparse(n, dtype, flags & PTD_COMPACT, nnz, rows, cols, vals, xs,
+                                                        count, coeff, ws, &bad, (hipStream_t)stream));
+    if (st != PTD_OK) return st;
+    return bad ? PTD_EINVAL : PTD_OK;
+}
+
 ptd_status ptd_lcu_amplitudes(int n, ptd_dtype dtype, unsigned flags, const void* coeff, void* amp_out,
                               double* lambda_host, void* ws, size_t ws_bytes, ptd_stream stream)
 {

@@ -1,0 +1,128 @@
+"""GPU parity of the sparse-input path: the X-pattern set r ^ c of the
+entries, and the coefficients of those rows, against the oracle on the
+assembled matrix (rows not listed must be exactly zero)."""
+import numpy as np
+import pytest
+
+import synth
+from tests.helpers import rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL = {np.complex128: 1e-12, np.complex64: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def ptd():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_11644_amd as p
+
+    return p
+
+
+def _entries(n, nnz, seed, dt, clustered=False):
+    N = 1 << n
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(0, N, size=nnz).astype(np.int32)
+    if clustered:  # a band-like pattern plus scattered entries: few X-patterns
+        cols = np.clip(rows + rng.integers(-3, 4, size=nnz), 0, N - 1).astype(np.int32)
+    else:
+        cols = rng.integers(0, N, size=nnz).astype(np.int32)
+    vals = synth.complex_normal(nnz, seed=seed + 1, dtype=dt)
+    return rows, cols, vals
+
+
+@pytest.mark.parametrize("dt", [np.complex128, np.complex64])
+@pytest.mark.parametrize("n,clustered", [(1, False), (2, False), (5, False), (9, True), (10, False), (11, True),
+                                         (12, False), (13, True)])
+@pytest.mark.parametrize("compact", [True, False])
+def test_sparse_vs_oracle(ptd, oracle_mod, dt, n, clustered, compact):
+    N = 1 << n
+    rows, cols, vals = _entries(n, 3 * N, 500 + n, dt, clustered)
+    got, xs = ptd.decompose_sparse(to_dev(rows), to_dev(cols), to_dev(vals), n, compact=compact)
+    want_xs = oracle_mod.sparse_nonempty_x(n, rows, cols)
+    assert to_host(xs).tolist() == want_xs
+    A = oracle_mod.sparse_to_dense(n, rows, cols, vals)
+    # rows of the listed X-patterns (a sample of them beyond n = 10)
+    pick = np.array(want_xs, dtype=np.uint32)
+    if n > 10:
+        pick = pick[np.random.default_rng(7).choice(len(pick), size=min(len(pick), 24), replace=False)]
+    want = oracle_mod.rows(A, pick)
+    g = to_host(got)
+    if compact:
+        assert g.shape == (len(want_xs), N)
+        idx = np.searchsorted(np.array(want_xs), pick)
+        assert rel_err(g[idx], want) <= TOL[dt]
+    else:
+        assert rel_err(g[pick.astype(np.int64)], want) <= TOL[dt]
+        mask = np.ones(N, dtype=bool)
+        mask[want_xs] = False
+        assert np.all(g[mask] == 0)
+
+
+@pytest.mark.parametrize("n", [3, 8, 11])
+def test_sparse_integer_exact_with_repeats(ptd, oracle_mod, n):
+    """Gaussian-integer entries, with repeated coordinates (summed) and
+    entries outside the matrix (ignored): exact against the oracle."""
+    N = 1 << n
+    rng = np.random.default_rng(600 + n)
+    nnz = 2 * N
+    rows = rng.integers(0, N, size=nnz)
+    cols = rng.integers(0, N, size=nnz)
+    rows[:8] = rows[8:16]  # repeats
+    cols[:8] = cols[8:16]
+    rows[-3:] = [N, -1, 2]  # out of range
+    cols[-3:] = [0, 1, N + 5]
+    vals = (rng.integers(-8, 9, size=nnz) + 1j * rng.integers(-8, 9, size=nnz)).astype(np.complex64)
+    got, xs = ptd.decompose_sparse(to_dev(rows.astype(np.int32)), to_dev(cols.astype(np.int32)), to_dev(vals), n)
+    A = oracle_mod.sparse_to_dense(n, rows, cols, vals)
+    wr, wi = oracle_mod.decompose_int(A.real.astype(np.int64), A.imag.astype(np.int64)) if n <= 8 else (None, None)
+    g = to_host(got).astype(np.complex128) * N
+    if wr is not None:
+        np.testing.assert_array_equal(g.real, wr.astype(np.float64))
+        np.testing.assert_array_equal(g.imag, wi.astype(np.float64))
+    else:
+        pick = to_host(xs)[:16].astype(np.uint32)
+        np.testing.assert_array_equal(g[pick.astype(np.int64)], np.round(oracle_mod.rows(A, pick) * N))
+
+
+def test_sparse_empty_and_bad_list(ptd):
+    import torch
+
+    from paper_2403_11644_amd import _native, api
+
+    e32 = torch.empty(0, dtype=torch.int32, device="cuda")
+    ev = torch.empty(0, dtype=torch.complex128, device="cuda")
+    got, xs = ptd.decompose_sparse(e32, e32, ev, 4)
+    assert xs.numel() == 0 and float(got.abs().max()) == 0.0
+    got, xs = ptd.decompose_sparse(e32, e32, ev, 4, compact=True)
+    assert got.shape == (0, 16) and xs.numel() == 0
+    # a list that is not strictly ascending, or leaves the matrix, is refused
+    # by the device-side check before anything is written
+    L = _native.lib()
+    wsb = L.ptd_sparse_workspace_bytes(4)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    out = torch.empty((16, 16), dtype=torch.complex128, device="cuda")
+    for bad in ([3, 3], [5, 2], [1, 16]):
+        xs_bad = torch.tensor(bad, dtype=torch.int32, device="cuda")
+        st = L.pauli_decompose_sparse(4, api.C128, 0, 0, None, None, None, api._ptr(xs_bad), len(bad),
+                                      api._ptr(out), api._ptr(ws), wsb, None)
+        assert st == -1
+
+
+@pytest.mark.parametrize("dt", [np.complex128, np.complex64])
+def test_sparse_band_matches_structured(ptd, dt):
+    """A band matrix given as sparse entries: the same X-patterns and the
+    same rows as the band path (within rounding)."""
+    n, s = 10, 3
+    band = synth.banded_complex(n, s, seed=12, dtype=dt)
+    A = synth.dense_from_bands(band)
+    r, c = np.nonzero(A)
+    v = A[r, c]
+    got, xs = ptd.decompose_sparse(to_dev(r.astype(np.int32)), to_dev(c.astype(np.int32)), to_dev(v), n, compact=True)
+    want = to_host(ptd.decompose(to_dev(band), structure="banded", s=s, bands=True, compact=True))
+    assert to_host(xs).tolist() == ptd.nonempty_x(n, "banded", s)
+    assert rel_err(to_host(got), want) <= TOL[dt]
