@@ -390,3 +390,11 @@ def sparse_nonempty_x(n: int, rows, cols) -> list[int]:
     cols = np.asarray(cols, dtype=np.int64)
     ok = (rows >= 0) & (rows < N) & (cols >= 0) & (cols < N)
     return sorted({int(x) for x in (rows[ok] ^ cols[ok])})
+
+
+def pure_density(psi: np.ndarray) -> np.ndarray:
+    """The density matrix |psi><psi| of a state vector, A[r][c] = psi[r]
+    conj(psi[c]); its coefficients are the Pauli expectation values
+    <psi|P|psi> / 2^n (c_P = 2^-n Tr(P |psi><psi|))."""
+    psi = np.asarray(psi).astype(np.complex128)
+    return np.outer(psi, np.conj(psi))

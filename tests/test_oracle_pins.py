@@ -419,3 +419,21 @@ def test_sparse_support(oracle_mod):
     c = oracle_mod.decompose(A)
     nz = [x for x in range(N) if np.any(c[x] != 0)]
     assert nz == oracle_mod.sparse_nonempty_x(n, rows, cols)
+
+
+def test_pure_state_expectations(oracle_mod):
+    # the coefficients of |psi><psi| are <psi|P|psi> / 2^n (textbook: P from
+    # np.kron applied to psi), real; c_I = |psi|^2 / 2^n and Parseval gives
+    # 2^n sum |c|^2 = |psi|^4
+    n = 3
+    N = 1 << n
+    psi = synth.complex_normal(N, seed=87)
+    c = oracle_mod.decompose(oracle_mod.pure_density(psi))
+    for x in range(N):
+        for z in range(N):
+            P = oracle_mod.pauli_matrix(oracle_mod.label(x, z, n))
+            assert abs(c[x, z] - np.vdot(psi, P @ psi) / N) <= 1e-14
+    np.testing.assert_allclose(c.imag, 0, atol=1e-15)
+    nrm = float(np.vdot(psi, psi).real)
+    assert c[0, 0].real == pytest.approx(nrm / N, rel=1e-14)
+    assert N * float(np.sum(np.abs(c) ** 2)) == pytest.approx(nrm ** 2, rel=1e-13)
