@@ -447,7 +447,15 @@ def main() -> int:
         o64 = torch.empty((N, N), dtype=torch.complex64, device=dev)
         leg["complex64_ms"] = round(_time(lambda: ptd.decompose(tv64, toeplitz=True, out=o64), args.steps,
                                           args.warmup, stream), 4)
-        legs["toeplitz_n14"] = leg
+        # pure state |psi><psi|: all 4^14 Pauli expectation values of a state vector
+        g.manual_seed(142)
+        psi = torch.randn(N, dtype=torch.complex128, device=dev, generator=g)
+        hout14 = torch.empty((N, N), dtype=torch.float64, device=dev)
+        ms_p = _time(lambda: ptd.decompose(psi, pure_state=True, hermitian=True, out=hout14), args.steps,
+                     args.warmup, stream)
+        leg["pure_state_expectations_f64_ms"] = round(ms_p, 4)
+        del psi, hout14
+        legs["matrix_free_n14"] = leg
         del tv, tv64, o64
         torch.cuda.empty_cache()
     if "algebra" in want_legs:

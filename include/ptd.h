@@ -103,6 +103,15 @@ typedef void *ptd_stream;
  * without PTD_HERMITIAN; PTD_EUNSUP beyond, and with structure flags or
  * PTD_COMPENSATED.  With PTD_HERMITIAN, t[2^n - 1 - d] = conj(t[2^n - 1 + d]). */
 #define PTD_TOEPLITZ (1u << 9)
+/* Matrix-free pure-state input: A is the density matrix |psi><psi| of the
+ * state vector psi (2^n elements of dtype at A), A[r][c] = psi[r]
+ * conj(psi[c]), formed on the fly (per entry: re = a.re b.re + a.im b.im,
+ * im = a.im b.re - a.re b.im for a = psi[r], b = psi[c], no fused
+ * multiply-add); lda is ignored.  The coefficients are the Pauli expectation
+ * values <psi|P|psi> / 2^n, real (exactly zero imaginary parts in the complex
+ * output; PTD_HERMITIAN gives the real array).  Same sizes and exclusions as
+ * PTD_TOEPLITZ, with which it does not combine. */
+#define PTD_PURE_STATE (1u << 10)
 
 /* Workspace (device bytes) a pauli_decompose call with these arguments
  * needs: a few KiB of queue counters for dense decompositions with

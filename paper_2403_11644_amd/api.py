@@ -22,6 +22,7 @@ BANDS_IN = 1 << 3
 COMPACT = 1 << 4
 ANTIDIAGONAL = 1 << 8
 TOEPLITZ = 1 << 9
+PURE_STATE = 1 << 10
 COMPENSATED = 1 << 5
 ADJOINT = 1 << 6
 
@@ -109,7 +110,8 @@ def nonempty_x(n: int, structure: str | None = None, s: int = 0) -> list[int]:
 
 def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None = None, s: int | None = None,
               bands: bool = False, compact: bool = False, compensated: bool = False, pad: bool = False,
-              toeplitz: bool = False, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+              toeplitz: bool = False, pure_state: bool = False, out: torch.Tensor | None = None,
+              stream=None) -> torch.Tensor:
     """Pauli coefficients of A, as a (2^n, 2^n) tensor c[x, z].
 
     hermitian   A == A^*: return the (real) coefficients as float64/float32.
@@ -122,17 +124,27 @@ def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None
     pad         zero-pad a non-power-of-two A (top-left embedding).
     toeplitz    A is the 1-D vector t of 2^(n+1) - 1 entries of a Toeplitz
                 matrix, A[r][c] = t[c - r + 2^n - 1] (matrix-free input).
+    pure_state  A is a state vector psi of 2^n entries and the matrix is
+                |psi><psi| (matrix-free): the coefficients are the Pauli
+                expectation values <psi|P|psi> / 2^n.
     """
     _require_device(A, "A")
     code = _dtype_code(A.dtype)
-    if toeplitz:
+    if toeplitz or pure_state:
+        if toeplitz and pure_state:
+            raise ValueError("toeplitz and pure_state exclude each other")
         if structure is not None or bands or pad or compact or compensated:
-            raise ValueError("toeplitz=True takes a dense decomposition only")
-        if A.dim() != 1 or not A.is_contiguous() or (A.shape[0] + 1) & A.shape[0] or A.shape[0] < 3:
-            raise ValueError("a Toeplitz input is a contiguous vector of 2^(n+1) - 1 entries")
-        N = (A.shape[0] + 1) // 2
+            raise ValueError("matrix-free input takes a dense decomposition only")
+        if A.dim() != 1 or not A.is_contiguous():
+            raise ValueError("matrix-free input is a contiguous vector")
+        if toeplitz:
+            if (A.shape[0] + 1) & A.shape[0] or A.shape[0] < 3:
+                raise ValueError("a Toeplitz input has 2^(n+1) - 1 entries")
+            N = (A.shape[0] + 1) // 2
+        else:
+            N = A.shape[0]
         n = _nqubits(N)
-        flags = TOEPLITZ | (HERMITIAN if hermitian else 0)
+        flags = (TOEPLITZ if toeplitz else PURE_STATE) | (HERMITIAN if hermitian else 0)
         odt = _real_dtype(code) if hermitian else _complex_dtype(code)
         out = _check_out(out, (N, N), odt, A.device)
         L = _native.lib()

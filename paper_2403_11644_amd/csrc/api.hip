@@ -15,7 +15,7 @@ namespace {
 thread_local int g_last_hip_error = 0;
 
 constexpr unsigned kAllFlags = PTD_HERMITIAN | PTD_DIAGONAL | PTD_BANDED | PTD_BANDS_IN | PTD_COMPACT |
-                               PTD_COMPENSATED | PTD_ADJOINT | PTD_ANTIDIAGONAL | PTD_TOEPLITZ;
+                               PTD_COMPENSATED | PTD_ADJOINT | PTD_ANTIDIAGONAL | PTD_TOEPLITZ | PTD_PURE_STATE;
 constexpr unsigned kStructure = PTD_DIAGONAL | PTD_BANDED | PTD_ANTIDIAGONAL;
 
 ptd_status hip_status(hipError_t e)
@@ -130,21 +130,24 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
     if (flags & PTD_ADJOINT) return PTD_EINVAL;
     const ptd_status sst = check_structure(n, flags, s);
     if (sst != PTD_OK) return sst;
-    const bool toep = flags & PTD_TOEPLITZ;
-    if (!toep && lda < ((int64_t)1 << n)) return PTD_EINVAL;
+    // matrix-free input: a defining vector instead of the matrix
+    const bool mfree = flags & (PTD_TOEPLITZ | PTD_PURE_STATE);
+    if ((flags & PTD_TOEPLITZ) && (flags & PTD_PURE_STATE)) return PTD_EINVAL;
+    if (!mfree && lda < ((int64_t)1 << n)) return PTD_EINVAL;
     if ((flags & PTD_COMPENSATED) && dtype != PTD_C64) return PTD_EUNSUP;
     if (ws_bytes < ptd_workspace_bytes(n, dtype, flags, s)) return PTD_ENOSPC;
     (void)ws;
     if (A == coeff) return PTD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     const bool herm = flags & PTD_HERMITIAN;
-    if (toep) {
+    if (mfree) {
         if (flags & (kStructure | PTD_COMPENSATED)) return PTD_EUNSUP;
-        if (n <= 10) return hip_status(ptd::launch_group_toeplitz(n, dtype, herm, A, coeff, st));
+        const int src = (flags & PTD_TOEPLITZ) ? ptd::SRC_TOEPLITZ : ptd::SRC_PURE;
+        if (n <= 10) return hip_status(ptd::launch_group_src(n, dtype, herm, src, A, coeff, st));
         if (!use_fused(n, dtype, flags)) return PTD_EUNSUP;
         if (!ws) return PTD_ENOSPC;
-        return hip_status(ptd::launch_fused_toeplitz(n, dtype, herm, A, coeff, ws, ptd::fused_default(n, dtype, herm).la,
-                                                     st));
+        return hip_status(ptd::launch_fused_src(n, dtype, herm, src, A, coeff, ws,
+                                                ptd::fused_default(n, dtype, herm).la, st));
     }
     if (flags & kStructure) {
         if (flags & PTD_COMPENSATED) return PTD_EUNSUP;

@@ -69,13 +69,13 @@ constexpr int row_threads()
 // ------------------------------------------------------------------------
 // single pass, n <= 10
 
-template <class V, int LOGN, bool REAL_OUT, int NT, int RMAX, bool TOEP = false>
+template <class V, int LOGN, bool REAL_OUT, int NT, int RMAX, int SRC = SRC_MATRIX>
 __global__ __launch_bounds__(NT) void k_group_fwd(const cplx<V>* __restrict__ A, int64_t lda,
                                                   void* __restrict__ out, int64_t ldo)
 {
     constexpr int LOGT = group_logt<V>(LOGN);
     __shared__ cplx<V> lds[(1 << LOGT) * ((1 << LOGN) + 1)];
-    group_fwd<V, LOGN, LOGT, REAL_OUT, NT, RMAX, TOEP>(A, lda, out, ldo, blockIdx.x, lds);
+    group_fwd<V, LOGN, LOGT, REAL_OUT, NT, RMAX, SRC>(A, lda, out, ldo, blockIdx.x, lds);
 }
 
 template <class V, int LOGN, bool REAL_IN>
@@ -542,37 +542,41 @@ hipError_t launch_dense_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const 
     return herm ? rec_group<float, true>(n, coeff, A, lda, sc, st) : rec_group<float, false>(n, coeff, A, lda, sc, st);
 }
 
-// Toeplitz input for n <= 10: the single-pass group kernel with 512-thread
-// workgroups and radix-16 rounds (the results do not depend on the plan).
-hipError_t launch_group_toeplitz(int n, ptd_dtype dt, bool herm, const void* t, void* out, hipStream_t st)
+// Matrix-free input for n <= 10 (src: SRC_TOEPLITZ or SRC_PURE): the
+// single-pass group kernel with 512-thread workgroups and radix-16 rounds
+// (the results do not depend on the plan).
+template <class V, int SRC>
+hipError_t group_src_t(int n, bool herm, const void* src, void* out, hipStream_t st)
 {
-    if (n < 1 || n > 10) return hipErrorInvalidValue;
     const int N = 1 << n;
-    const dim3 grid(N >> (dt == PTD_C128 ? group_logt<double>(n) : group_logt<float>(n)));
+    const dim3 grid(N >> group_logt<V>(n));
     switch (n) {
-#define PTD_T(NN)                                                                                                  \
-    case NN:                                                                                                       \
-        if (dt == PTD_C128) {                                                                                      \
-            if (herm)                                                                                              \
-                hipLaunchKernelGGL((k_group_fwd<double, NN, true, 512, 4, true>), grid, dim3(512), 0, st,          \
-                                   (const cplx<double>*)t, (int64_t)0, out, (int64_t)N);                           \
-            else                                                                                                   \
-                hipLaunchKernelGGL((k_group_fwd<double, NN, false, 512, 4, true>), grid, dim3(512), 0, st,         \
-                                   (const cplx<double>*)t, (int64_t)0, out, (int64_t)N);                           \
-        } else {                                                                                                   \
-            if (herm)                                                                                              \
-                hipLaunchKernelGGL((k_group_fwd<float, NN, true, 512, 4, true>), grid, dim3(512), 0, st,           \
-                                   (const cplx<float>*)t, (int64_t)0, out, (int64_t)N);                            \
-            else                                                                                                   \
-                hipLaunchKernelGGL((k_group_fwd<float, NN, false, 512, 4, true>), grid, dim3(512), 0, st,          \
-                                   (const cplx<float>*)t, (int64_t)0, out, (int64_t)N);                            \
-        }                                                                                                          \
+#define PTD_T(NN)                                                                                             \
+    case NN:                                                                                                  \
+        if (herm)                                                                                             \
+            hipLaunchKernelGGL((k_group_fwd<V, NN, true, 512, 4, SRC>), grid, dim3(512), 0, st,               \
+                               (const cplx<V>*)src, (int64_t)0, out, (int64_t)N);                             \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_group_fwd<V, NN, false, 512, 4, SRC>), grid, dim3(512), 0, st,              \
+                               (const cplx<V>*)src, (int64_t)0, out, (int64_t)N);                             \
         break;
         PTD_T(1) PTD_T(2) PTD_T(3) PTD_T(4) PTD_T(5) PTD_T(6) PTD_T(7) PTD_T(8) PTD_T(9) PTD_T(10)
 #undef PTD_T
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_group_src(int n, ptd_dtype dt, bool herm, int src, const void* ptr, void* out, hipStream_t st)
+{
+    if (n < 1 || n > 10) return hipErrorInvalidValue;
+    if (src == SRC_TOEPLITZ)
+        return dt == PTD_C128 ? group_src_t<double, SRC_TOEPLITZ>(n, herm, ptr, out, st)
+                              : group_src_t<float, SRC_TOEPLITZ>(n, herm, ptr, out, st);
+    if (src == SRC_PURE)
+        return dt == PTD_C128 ? group_src_t<double, SRC_PURE>(n, herm, ptr, out, st)
+                              : group_src_t<float, SRC_PURE>(n, herm, ptr, out, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace ptd

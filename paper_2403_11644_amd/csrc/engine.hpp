@@ -26,6 +26,7 @@
 // phase is a swap/negation and the scale an exact power of two.
 #pragma once
 
+#include "internal.hpp"
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -131,6 +132,23 @@ struct LdsVecsW {
         p[vec * PITCH + pos] = v;
     }
 };
+
+// d_x[k] = A[k][k ^ x] from the source kind SRC (internal.hpp).
+template <class V, int SRC>
+__device__ __forceinline__ cplx<V> source_entry(const cplx<V>* __restrict__ A, int64_t lda, int logn, int k, int col)
+{
+    if constexpr (SRC == SRC_TOEPLITZ) {
+        return A[col - k + ((1 << logn) - 1)];
+    } else if constexpr (SRC == SRC_PURE) {
+        const cplx<V> a = A[k], b = A[col];
+        cplx<V> v;  // a * conj(b), two products and one sum per part
+        v.re = a.re * b.re + a.im * b.im;
+        v.im = a.im * b.re - a.re * b.im;
+        return v;
+    } else {
+        return A[(int64_t)k * lda + col];
+    }
+}
 
 template <class V>
 __device__ __forceinline__ V exp2_neg(int n)

@@ -105,9 +105,9 @@ __device__ __forceinline__ void group_rounds(const G& gather, const St& store, c
     }
 }
 
-// TOEP: A holds the Toeplitz vector t, A[r][c] = t[c - r + 2^LOGN - 1]
-// (matrix-free input; lda unused).
-template <class V, int LOGN, int LOGT, bool REAL_OUT, int NT = GROUP_THREADS, int RMAX = 4, bool TOEP = false>
+// SRC: where the matrix entries come from (engine.hpp, source_entry); for the
+// matrix-free kinds A holds their defining vector and lda is unused.
+template <class V, int LOGN, int LOGT, bool REAL_OUT, int NT = GROUP_THREADS, int RMAX = 4, int SRC = SRC_MATRIX>
 __device__ __forceinline__ void group_fwd(const cplx<V>* __restrict__ A, int64_t lda, void* __restrict__ out,
                                           int64_t ldo, int g, cplx<V>* lds)
 {
@@ -115,8 +115,7 @@ __device__ __forceinline__ void group_fwd(const cplx<V>* __restrict__ A, int64_t
     const uint32_t xg = (uint32_t)g << LOGT;
     const V scale = exp2_neg<V>(LOGN);
     auto gather = [&](int vec, int pos, V& re, V& im) {
-        const int col = pos ^ (int)(xg | vec);
-        const cplx<V> v = TOEP ? A[col - pos + ((1 << LOGN) - 1)] : A[(int64_t)pos * lda + col];
+        const cplx<V> v = source_entry<V, SRC>(A, lda, LOGN, pos, pos ^ (int)(xg | vec));
         re = v.re;
         im = v.im;
     };

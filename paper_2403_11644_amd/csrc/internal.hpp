@@ -10,6 +10,15 @@
 
 namespace ptd {
 
+// Where a decomposition reads the entries d_x[k] = A[k][k ^ x].  SRC_MATRIX:
+// the dense matrix (row pitch lda).  Matrix-free inputs, whose few defining
+// values stay in cache: SRC_TOEPLITZ, A[r][c] = t[c - r + 2^n - 1] with t at
+// A; SRC_PURE, the density matrix of a pure state, A[r][c] = psi[r]
+// conj(psi[c]) with psi at A.
+constexpr int SRC_MATRIX = 0;
+constexpr int SRC_TOEPLITZ = 1;
+constexpr int SRC_PURE = 2;
+
 // Dense decompose: coeff[x][z] (complex, or real when herm) for n in 1..16.
 // path: 0 = automatic, 1 = force the single-pass group kernel (n <= 10),
 // 2 = force the two-pass tile + high kernels (n >= 7).
@@ -72,16 +81,16 @@ hipError_t fused_rec_c128_herm(int n, const void* coeff, void* A, int64_t lda, v
                                hipStream_t st);
 hipError_t launch_fused_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const void* coeff, void* A, int64_t lda,
                             void* ws, int la, hipStream_t st);
-// Matrix-free Toeplitz input t (A[r][c] = t[c - r + 2^n - 1]): the
-// single-launch schedule (n = 11..15 where it applies) and the single-pass
-// group kernel (n <= 10).
-hipError_t fused_toeplitz_c64(int n, const void* t, void* out, void* ws, int la, hipStream_t st);
-hipError_t fused_toeplitz_c128(int n, const void* t, void* out, void* ws, int la, hipStream_t st);
-hipError_t fused_toeplitz_c64h(int n, const void* t, void* out, void* ws, int la, hipStream_t st);
-hipError_t fused_toeplitz_c128h(int n, const void* t, void* out, void* ws, int la, hipStream_t st);
-hipError_t launch_fused_toeplitz(int n, ptd_dtype dt, bool herm, const void* t, void* out, void* ws, int la,
-                                 hipStream_t st);
-hipError_t launch_group_toeplitz(int n, ptd_dtype dt, bool herm, const void* t, void* out, hipStream_t st);
+// Matrix-free input (src: SRC_TOEPLITZ or SRC_PURE, engine.hpp) given by its
+// defining vector: the single-launch schedule (n = 11..15 where it applies)
+// and the single-pass group kernel (n <= 10).
+hipError_t fused_src_c64(int n, int src, const void* t, void* out, void* ws, int la, hipStream_t st);
+hipError_t fused_src_c128(int n, int src, const void* t, void* out, void* ws, int la, hipStream_t st);
+hipError_t fused_src_c64h(int n, int src, const void* t, void* out, void* ws, int la, hipStream_t st);
+hipError_t fused_src_c128h(int n, int src, const void* t, void* out, void* ws, int la, hipStream_t st);
+hipError_t launch_fused_src(int n, ptd_dtype dt, bool herm, int src, const void* t, void* out, void* ws, int la,
+                            hipStream_t st);
+hipError_t launch_group_src(int n, ptd_dtype dt, bool herm, int src, const void* t, void* out, hipStream_t st);
 // Zero `count` uint32 words with a small kernel (capturable, unlike a memset node).
 hipError_t launch_zero_words(uint32_t* p, int count, hipStream_t st);
 // Plain 16-byte-per-lane device copy (bandwidth reference).

@@ -505,3 +505,52 @@ def test_toeplitz_integer_exact(ptd, oracle_mod, n):
     np.testing.assert_array_equal(got.real, wr.astype(np.float64))
     np.testing.assert_array_equal(got.imag, wi.astype(np.float64))
 
+
+
+# --------------------------------------------------------------------------
+# matrix-free pure-state input (PTD_PURE_STATE): A = |psi><psi|
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 4, 7, 10, 11, 13, 14])
+@pytest.mark.parametrize("hermitian", [False, True])
+def test_pure_state_expectations(ptd, oracle_mod, dt, n, hermitian):
+    """Pauli expectation values <psi|P|psi> / 2^n: sampled against the oracle
+    on |psi><psi|, real (imaginary parts exactly zero in the complex output),
+    and against the dense decomposition of the materialised density matrix."""
+    import torch
+
+    N = 1 << n
+    psi = synth.complex_normal(N, seed=700 + n, dtype=_np_dtype(dt))
+    pd = to_dev(psi)
+    got = ptd.decompose(pd, pure_state=True, hermitian=hermitian)
+    if not hermitian:
+        assert float(got.imag.abs().max()) == 0.0
+    xs, zs = synth.sample_strings(n, 500, seed=13)
+    ix, iz = to_dev(xs.astype(np.int64)), to_dev(zs.astype(np.int64))
+    g = to_host(got[ix, iz])
+    if n <= 12:
+        want = oracle_mod.coeffs(oracle_mod.pure_density(psi), xs, zs)
+        assert rel_err(g, want.real if hermitian else want) <= TOL[dt]
+    # the same butterflies on the materialised matrix (formed by torch, whose
+    # products may round differently, so within the bar rather than bit for bit)
+    rho = torch.outer(pd, pd.conj())
+    dense = ptd.decompose(rho, hermitian=hermitian)
+    assert rel_err(to_host(got), to_host(dense)) <= TOL[dt]
+    del rho, dense, got
+    torch.cuda.empty_cache()
+
+
+def test_pure_state_basis_state(ptd):
+    """|k><k| for a basis state k: the coefficient of (x, z) is
+    (-1)^popcount(z & k) / 2^n for x = 0 and zero otherwise, exactly."""
+    import torch
+
+    n, k = 9, 0b101100110
+    N = 1 << n
+    psi = torch.zeros(N, dtype=torch.complex128, device="cuda")
+    psi[k] = 1.0
+    got = to_host(ptd.decompose(psi, pure_state=True, hermitian=True))
+    z = np.arange(N)
+    sign = 1.0 - 2.0 * (np.array([bin(v & k).count("1") for v in z]) & 1)
+    np.testing.assert_array_equal(got[0], sign / N)
+    assert np.all(got[1:] == 0)
