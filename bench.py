@@ -12,6 +12,8 @@ Prints ONE JSON line.  Besides the contract fields it carries:
                 stream it runs on; algorithmic bytes = read A once + write
                 c once (32 B per coefficient for complex128)
   cpu_baseline  the oracle on this host's cores, on a bounded sample
+  cpu_tree_baseline  the paper's own tree method (native host code, forest
+                of Sec. V-B) on the same cores, on a bounded sample of trees
   legs          complex64 (with its error against the float64 oracle), the
                 two-pass schedule, the reconstruction A = sum_P c_P P and
                 the float64 Parseval reductions, n = 13 Hermitian (float64 and float32
@@ -36,10 +38,12 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
 
 def _kernel_hash() -> str:
+    """Hash of the device sources (*.hip, *.hpp); host-only C++ is left out."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2403_11644_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        h.update(open(os.path.join(csrc, f), "rb").read())
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -586,6 +590,39 @@ def main() -> int:
                "sample": "%d of %d X-pattern rows (all %d strings each) of the n=%d matrix in %.1f s; the full "
                          "decomposition would take about %.0f s" % (rows, N, N, n, t_cpu, t_cpu * N / rows)}
 
+    # The paper's own method on the same cores: the tree walk cut into a
+    # forest (Sec. V-B), a bounded sample of its trees at split 7 (4^7 trees
+    # of 4^(n-7) strings each), with a few of the strings it wrote checked
+    # against the oracle
+    tree = None
+    if not args.no_cpu_baseline and n > 7:
+        from paper_2403_11644_amd import host_tree
+
+        split = 7
+        ntrees = 2 * threads
+        hout = np.zeros((N, N), dtype=np.complex128)  # pages are touched only where written
+        t0 = time.time()
+        _, ops = host_tree.host_tree_decompose(A_host, split=split, trees=(0, ntrees), threads=threads, out=hout)
+        t_tree = time.time() - t0
+        strings = ntrees * 4 ** (n - split)
+        rng = np.random.default_rng(7)
+        bits = ((0, 0), (1, 0), (1, 1), (0, 1))  # I, X, Y, Z -> (x, z) bits
+        hx, hz = [], []
+        for _ in range(64):
+            t = int(rng.integers(ntrees))
+            letters = [(t >> (2 * (split - 1 - q))) & 3 for q in range(split)] + \
+                list(rng.integers(0, 4, n - split))
+            hx.append(sum(bits[l][0] << q for q, l in enumerate(letters)))
+            hz.append(sum(bits[l][1] << q for q, l in enumerate(letters)))
+        hx, hz = np.array(hx, dtype=np.int64), np.array(hz, dtype=np.int64)
+        hwant = O.coeffs(A_host, hx, hz)
+        tree = {"value": strings / t_tree / 1e9, "unit": "GCoeff/s", "cores": threads, "kind": "paper tree method",
+                "sample": "trees 0..%d of the %d-tree forest cut at depth %d (%d strings) of the n=%d matrix in "
+                          "%.1f s; the full decomposition would take about %.0f s"
+                          % (ntrees - 1, 4 ** split, split, strings, n, t_tree, t_tree * ncoef / strings),
+                "update_ops": ops, "err_rel_sampled_vs_oracle": _rel(hout[hx, hz], hwant)}
+        del hout
+
     bytes128 = 32.0 * ncoef  # read A (16 B) + write c (16 B) per coefficient
     achieved = bytes128 / (ms128 * 1e-3) / 1e9
     line = {
@@ -611,6 +648,7 @@ def main() -> int:
         "parseval_residual": pars128,
         "legs": legs,
         "cpu_baseline": cpu,
+        "cpu_tree_baseline": tree,
         "input_gen_s": round(gen_s, 1),
         "kernel_hash": _kernel_hash(),
     }

@@ -356,6 +356,34 @@ ptd_status ptd_set_tuning(int n, ptd_dtype dtype, unsigned flags, int cfg, int l
 int ptd_get_tuning(int n, ptd_dtype dtype, unsigned flags, int *cfg, int *lookahead);
 void ptd_clear_tuning(void);
 
+/*
+ * The paper's own method on the host's cores, as a baseline beside the
+ * device path (no HIP call; no other entry point uses it): the Pauli tree
+ * walk of Sec. III-A (Algorithms 1-4: arrays k, m updated child by child in
+ * the order I, X, Y, Z, one trace per leaf) and the forest of Sec. V-B that
+ * cuts every branch at depth `split` into independent trees run by
+ * `threads` host threads (0 = one per hardware thread).  With PTD_DIAGONAL
+ * only I and Z children are visited and only m is kept (Sec. IV-A); flags
+ * otherwise 0.
+ *
+ * A: host complex128 matrix (interleaved re, im), row-major, row pitch lda
+ * >= 2^n elements; n = 1..16.  coeff_out: host complex128 array of 2^n x
+ * 2^n, c[x][z] as for pauli_decompose; only the strings of trees
+ * [tree_begin, tree_end) are written (the x = 0 row's strings with
+ * PTD_DIAGONAL), everything else is left as it was.  The forest has 4^split
+ * trees (2^split with PTD_DIAGONAL), 0 <= split <= n, numbered in the order
+ * the single walk reaches their roots.  Every coefficient is summed in the
+ * same order whatever the split, the range and the thread count, so results
+ * agree bit for bit.  *ops_out (if not null) receives the elementary
+ * operations of the updates, counted as Sec. III-B and IV-A count them:
+ * 9/7 + 5/7 8^n for split 0, 4/3 + 2/3 4^n with PTD_DIAGONAL; each tree of
+ * a forest adds the replay of its path.  Blocks the calling thread.
+ * PTD_EINVAL on a bad argument, PTD_ENOMEM if a worker cannot allocate its
+ * arrays (its trees may then be missing).
+ */
+ptd_status ptd_host_tree_decompose(int n, unsigned flags, const void *A, int64_t lda, void *coeff_out, int split,
+                                   int64_t tree_begin, int64_t tree_end, int threads, uint64_t *ops_out);
+
 /* Human-readable name of a status code (static string). */
 const char *ptd_status_str(ptd_status st);
 /* HIP error code of the most recent PTD_EHIP on this thread (0 if none). */

@@ -10,6 +10,7 @@ from .api import (  # noqa: F401
     linear_combination, nonempty_x, num_nonempty_x, pad_to_power_of_two, parseval, reconstruct,
 )
 from .labels import flat_index, index, label  # noqa: F401
+from .host_tree import host_tree_decompose  # noqa: F401
 from .autograd import PauliDecompose, PauliReconstruct, pauli_decompose, pauli_reconstruct  # noqa: F401
 from . import tuning  # noqa: F401
 

@@ -1,5 +1,8 @@
 """Build the HIP library libptd.so for gfx950 with hipcc (in-tree).
 
+The host-only C++ sources (csrc/*.cpp) compile with the system C++ compiler
+and link into the same library.
+
 Run as ``python -m paper_2403_11644_amd.build``.  hipcc cross-compiles for
 gfx950 without a GPU present.  Packed FP32 instructions are switched off
 (``-packed-fp32-ops``) and FMA contraction is disabled so the butterfly
@@ -32,6 +35,16 @@ HIPCC_FLAGS = [
 ]
 
 
+CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-ffp-contract=off", "-Wall"]
+
+
+def cxx() -> str:
+    for cand in (os.environ.get("CXX"), shutil.which("g++"), "/usr/bin/g++"):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("no host C++ compiler found (g++)")
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):
@@ -40,7 +53,7 @@ def hipcc() -> str:
 
 
 def sources() -> list[str]:
-    return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + sorted(glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
 def _jobs() -> int:
@@ -70,13 +83,16 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(src: str) -> str:
         obj = os.path.join(objdir, os.path.splitext(os.path.basename(src))[0] + ".o")
-        cmd = [hipcc()] + compile_flags + [inc, "-c", src, "-o", obj]
+        if src.endswith(".cpp"):
+            cmd = [cxx()] + CXX_FLAGS + [inc, "-c", src, "-o", obj]
+        else:
+            cmd = [hipcc()] + compile_flags + [inc, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         res = subprocess.run(cmd, capture_output=True, text=True)
         err = _filter(res.stderr)
         if res.returncode != 0:
-            raise RuntimeError("hipcc failed on %s:\n%s" % (os.path.basename(src), err))
+            raise RuntimeError("%s failed on %s:\n%s" % (os.path.basename(cmd[0]), os.path.basename(src), err))
         if verbose and err.strip():
             print(err, file=sys.stderr)
         return obj
@@ -85,7 +101,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(_jobs(), len(srcs))) as ex:
         objs = list(ex.map(compile_one, srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", tmp]
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread"] + objs + ["-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc link failed:\n" + _filter(res.stderr))

@@ -1,0 +1,168 @@
+"""The paper's tree method on the host (ptd_host_tree_decompose): the walk
+of Sec. III-A (Algorithms 1-4) and its forest of Sec. V-B, against the
+oracle and against the operation counts the paper derives in closed form
+(Sec. III-B for the whole tree, Sec. IV-A for the diagonal variant).
+
+These run on the CPU: the entry point makes no HIP call."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+
+N_MAX = 8
+
+
+@pytest.fixture(scope="module")
+def ht():
+    from paper_2403_11644_amd import host_tree
+
+    return host_tree
+
+
+def _int_matrix(n, seed):
+    re, im = synth.gaussian_int(n, seed=seed)
+    return synth.int_to_complex(re, im, np.complex128)
+
+
+@pytest.mark.parametrize("n", range(1, N_MAX + 1))
+def test_gaussian_integer_exact(ht, oracle_mod, n):
+    # integer sums stay exact, so both sides agree bit for bit
+    A = _int_matrix(n, 300 + n)
+    got, _ = ht.host_tree_decompose(A, threads=2)
+    np.testing.assert_array_equal(got, oracle_mod.decompose(A))
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 7])
+def test_float_against_oracle(ht, oracle_mod, n):
+    A = synth.dense(n, seed=310 + n)
+    got, _ = ht.host_tree_decompose(A, split=min(n, 2), threads=3)
+    want = oracle_mod.decompose(A)
+    assert np.abs(got - want).max() <= 1e-14 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("n", range(1, 10))
+def test_operation_counts_match_the_paper(ht, n):
+    # whole tree: 2 + sum_l 5 2^(l-1) 4^(l-1) = 9/7 + 5/7 8^n; diagonal:
+    # 2 + sum_l 2 2^(l-1) 2^(l-1) = 4/3 + 2/3 4^n
+    A = np.zeros((1 << n, 1 << n), dtype=np.complex128)
+    _, ops = ht.host_tree_decompose(A, threads=1)
+    assert 7 * ops == 9 + 5 * 8 ** n
+    _, ops_d = ht.host_tree_decompose(A, diagonal=True, threads=1)
+    assert 3 * ops_d == 4 + 2 * 4 ** n
+    # the no-tree count 2 8^n is 14/5 times the tree's, up to the constant
+    assert abs(2 * 8 ** n / ops - 14 / 5) < 14 / 5 * 2 / 8 ** n + 1e-12
+
+
+@pytest.mark.parametrize("n", [3, 6])
+def test_forest_operation_count(ht, n):
+    # every tree re-initialises its root and replays its path (letter L of
+    # qubit q costs (2 + L) 2^q with I, X, Y, Z = 0..3); below the cut the
+    # trees together do exactly what the whole walk does there
+    A = np.zeros((1 << n, 1 << n), dtype=np.complex128)
+    for s in range(0, n + 1):
+        _, ops = ht.host_tree_decompose(A, split=s, threads=2)
+        replay = sum(sum((2 + ((t >> (2 * (s - 1 - q))) & 3)) << q for q in range(s)) for t in range(4 ** s))
+        below = sum(5 * 8 ** q for q in range(s, n))
+        assert ops == 2 * 4 ** s + replay + below
+
+
+@pytest.mark.parametrize("n", [4, 6])
+def test_split_and_threads_do_not_change_a_bit(ht, n):
+    # Sec. V-B: the forest adds no error; here every coefficient is summed in
+    # the same order whatever the cut and the thread count
+    A = synth.dense(n, seed=320 + n)
+    ref, _ = ht.host_tree_decompose(A, threads=1)
+    for s in range(0, n + 1):
+        for threads in (1, 3, 4):
+            got, _ = ht.host_tree_decompose(A, split=s, threads=threads)
+            np.testing.assert_array_equal(got, ref)
+    for s in range(0, n + 1):
+        got, _ = ht.host_tree_decompose(A, diagonal=True, split=s, threads=2)
+        ref_d, _ = ht.host_tree_decompose(A, diagonal=True, threads=1)
+        np.testing.assert_array_equal(got, ref_d)
+
+
+def test_tree_ranges_cover_exactly_their_strings(ht, oracle_mod):
+    n, s = 5, 2
+    A = synth.dense(n, seed=330)
+    want = oracle_mod.decompose(A)
+    sentinel = complex(1e300, -1e300)
+    out = np.full((1 << n, 1 << n), sentinel, dtype=np.complex128)
+    covered = np.zeros((1 << n, 1 << n), dtype=bool)
+    bits = {0: (0, 0), 1: (1, 0), 2: (1, 1), 3: (0, 1)}  # I, X, Y, Z -> (x, z) bits
+    for begin, end in [(0, 3), (3, 4), (4, 11), (11, 16)]:
+        before = out.copy()
+        ht.host_tree_decompose(A, split=s, trees=(begin, end), threads=2, out=out)
+        changed = out != before
+        # the strings of trees [begin, end): qubits 0 .. s-1 fixed by the tree index
+        mask = np.zeros_like(covered)
+        for t in range(begin, end):
+            fx = fz = 0
+            for q in range(s):
+                bx, bz = bits[(t >> (2 * (s - 1 - q))) & 3]
+                fx |= bx << q
+                fz |= bz << q
+            low = (1 << s) - 1
+            xs = np.arange(1 << n)
+            mask[np.ix_((xs & low) == fx, (xs & low) == fz)] = True
+        # a coefficient never equals the sentinel, so "written" is "changed"
+        np.testing.assert_array_equal(changed, mask)
+        assert not np.any(covered & mask)
+        covered |= mask
+    assert covered.all()
+    assert np.abs(out - want).max() <= 1e-14 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("n", [1, 3, 6])
+def test_diagonal_variant(ht, oracle_mod, n):
+    # only I/Z strings, only A's diagonal read: the off-diagonal part of A
+    # must not matter, and every other string is left as it was
+    A = synth.dense(n, seed=340 + n)
+    D = np.diag(np.diag(A))
+    sentinel = complex(7.0, -7.0)
+    out = np.full((1 << n, 1 << n), sentinel, dtype=np.complex128)
+    ht.host_tree_decompose(A, diagonal=True, threads=2, out=out)
+    want = oracle_mod.decompose(D)
+    assert np.abs(out[0] - want[0]).max() <= 1e-14 * np.abs(want[0]).max()
+    assert np.all(out[1:] == sentinel)
+    assert np.abs(want[1:]).max() == 0.0
+
+
+def test_row_pitch(ht, oracle_mod):
+    big = synth.dense(5, seed=350)
+    A = big[:16, 3:19]  # a 16 x 16 block inside rows of 32
+    got, _ = ht.host_tree_decompose(A, threads=2)
+    np.testing.assert_array_equal(got, ht.host_tree_decompose(np.ascontiguousarray(A), threads=2)[0])
+    want = oracle_mod.decompose(np.ascontiguousarray(A))
+    assert np.abs(got - want).max() <= 1e-14 * np.abs(want).max()
+
+
+def test_argument_errors(ht):
+    from paper_2403_11644_amd import _native
+
+    L = _native.lib()
+    A = np.zeros((8, 8), dtype=np.complex128)
+    c = np.zeros((8, 8), dtype=np.complex128)
+    pa, pc = ctypes.c_void_p(A.ctypes.data), ctypes.c_void_p(c.ctypes.data)
+    call = L.ptd_host_tree_decompose
+    assert call(3, 0, pa, 8, pc, 0, 0, 1, 1, None) == 0
+    assert call(0, 0, pa, 8, pc, 0, 0, 1, 1, None) == -1  # n
+    assert call(17, 0, pa, 8, pc, 0, 0, 1, 1, None) == -1
+    assert call(3, 1, pa, 8, pc, 0, 0, 1, 1, None) == -1  # flag other than PTD_DIAGONAL
+    assert call(3, 0, None, 8, pc, 0, 0, 1, 1, None) == -1
+    assert call(3, 0, pa, 8, None, 0, 0, 1, 1, None) == -1
+    assert call(3, 0, pa, 7, pc, 0, 0, 1, 1, None) == -1  # lda < 2^n
+    assert call(3, 0, pa, 8, pc, 4, 0, 1, 1, None) == -1  # split > n
+    assert call(3, 0, pa, 8, pc, -1, 0, 1, 1, None) == -1
+    assert call(3, 0, pa, 8, pc, 1, 0, 5, 1, None) == -1  # 4 trees at split 1
+    assert call(3, 2, pa, 8, pc, 1, 0, 3, 1, None) == -1  # 2 diagonal trees at split 1
+    assert call(3, 0, pa, 8, pc, 1, 3, 2, 1, None) == -1  # end < begin
+    assert call(3, 0, pa, 8, pc, 1, -1, 2, 1, None) == -1
+    assert call(3, 0, pa, 8, pc, 1, 0, 4, -1, None) == -1  # threads
+    assert call(3, 0, pa, 8, pc, 1, 2, 2, 1, None) == 0  # empty range
+    with pytest.raises(ValueError):
+        ht.host_tree_decompose(np.zeros((6, 6), dtype=np.complex128))
+    with pytest.raises(ValueError):
+        ht.host_tree_decompose(np.zeros((8, 8), dtype=np.complex64))
