@@ -37,6 +37,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def _kernel_hash() -> str:
     """Hash of the device sources (*.hip, *.hpp); host-only C++ is left out."""
     h = hashlib.sha256()
@@ -234,8 +244,13 @@ def main() -> int:
 
     t_gen = time.time()
     A_host = synth.dense(n, seed=0)  # complex128, re then im, N(0, 1)
-    A = torch.from_numpy(A_host).to(dev)
     gen_s = time.time() - t_gen
+    # host-to-device copy of the input (pageable numpy memory), outside every timed region
+    torch.cuda.synchronize()
+    t0 = time.time()
+    A = torch.from_numpy(A_host).to(dev)
+    torch.cuda.synchronize()
+    h2d_s = time.time() - t0
     out128 = torch.empty((N, N), dtype=torch.complex128, device=dev)
     wsb = L.ptd_workspace_bytes(n, api.C128, 0, 0)
     ws = torch.zeros(max(wsb, 16), dtype=torch.uint8, device=dev)
@@ -257,6 +272,14 @@ def main() -> int:
     iz = torch.from_numpy(zs.astype(np.int64)).to(dev)
     err128 = _rel(out128[ix, iz].cpu().numpy(), want)
     _, _, pars128 = ptd.parseval(A, out128)
+    # device-to-host copy of the coefficients into pageable memory, timed apart
+    t0 = time.time()
+    c_host = out128.cpu()
+    d2h_s = time.time() - t0
+    del c_host
+    transfers = {"h2d_A_s": round(h2d_s, 3), "h2d_GBps": round(16 * ncoef / h2d_s / 1e9, 1),
+                 "d2h_c_s": round(d2h_s, 3), "d2h_GBps": round(16 * ncoef / d2h_s / 1e9, 1),
+                 "host_to_host_GCoeff_s": round(ncoef / (h2d_s + ms128 * 1e-3 + d2h_s) / 1e9, 3)}
 
     legs = {}
     want_legs = set()
@@ -284,8 +307,12 @@ def main() -> int:
         legs["parseval_f64"] = {"ms": round(msp_, 4),
                                 "path_hbm_frac": round(32 * ncoef / (msp_ * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
     if "complex64" in want_legs:
-        # complex64 cast of the same matrix (cast excluded from the time)
+        # complex64 cast of the same matrix (cast excluded from the time, reported apart)
+        torch.cuda.synchronize()
+        t0 = time.time()
         A64 = A.to(torch.complex64)
+        torch.cuda.synchronize()
+        cast_ms = (time.time() - t0) * 1e3
         out64 = torch.empty((N, N), dtype=torch.complex64, device=dev)
         wsb64 = L.ptd_workspace_bytes(n, api.C64, 0, 0)
         ws64 = torch.zeros(max(wsb64, 16), dtype=torch.uint8, device=dev)
@@ -297,12 +324,17 @@ def main() -> int:
         ms64 = _time(run64, args.steps, args.warmup, stream)
         run64()
         torch.cuda.synchronize()
-        err64 = _rel(out64[ix, iz].cpu().numpy().astype(np.complex128), want)
+        got64 = out64[ix, iz].cpu().numpy().astype(np.complex128)
+        err64 = _rel(got64, want)
+        # the butterflies' error alone: the oracle on the rounded (complex64) input
+        want_cast = O.coeffs(A64.cpu().numpy().astype(np.complex128), xs, zs)
         _, _, pars64 = ptd.parseval(A64, out64)
         legs["complex64"] = {"ms": round(ms64, 4), "GCoeff_s": round(ncoef / ms64 / 1e6, 2),
                              "path_hbm_frac": round(16 * ncoef / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                             "err_rel_sampled_vs_f64_oracle": err64, "parseval_residual": pars64,
-                             "speedup_vs_f64": round(ms128 / ms64, 3)}
+                             "err_rel_sampled_vs_f64_oracle": err64,
+                             "err_rel_sampled_vs_oracle_on_cast_input": _rel(got64, want_cast),
+                             "parseval_residual": pars64, "speedup_vs_f64": round(ms128 / ms64, 3),
+                             "cast_ms": round(cast_ms, 3)}
         del out64, A64
     if "two_pass" in want_legs:
         # the two-pass schedule on the same input (same bytes moved twice)
@@ -586,9 +618,17 @@ def main() -> int:
         t0 = time.time()
         O.rows(A_host, xs_rows, nthreads=threads)
         t_cpu = time.time() - t0
+        # and on one thread, a few rows
+        rows1 = max(1, min(N, int(3.0 / max(t_cal, 1e-3))))
+        t0 = time.time()
+        O.rows(A_host, xs_rows[:rows1], nthreads=1)
+        t_cpu1 = time.time() - t0
         cpu = {"value": rows * N / t_cpu / 1e9, "unit": "GCoeff/s", "cores": threads, "kind": "oracle",
                "sample": "%d of %d X-pattern rows (all %d strings each) of the n=%d matrix in %.1f s; the full "
-                         "decomposition would take about %.0f s" % (rows, N, N, n, t_cpu, t_cpu * N / rows)}
+                         "decomposition would take about %.0f s" % (rows, N, N, n, t_cpu, t_cpu * N / rows),
+               "single_thread_value": rows1 * N / t_cpu1 / 1e9,
+               "single_thread_sample": "%d rows in %.1f s" % (rows1, t_cpu1),
+               "cpu_model": _cpu_model()}
 
     # The paper's own method on the same cores: the tree walk cut into a
     # forest (Sec. V-B), a bounded sample of its trees at split 7 (4^7 trees
@@ -650,6 +690,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "cpu_tree_baseline": tree,
         "input_gen_s": round(gen_s, 1),
+        "transfers": transfers,
         "kernel_hash": _kernel_hash(),
     }
     print(json.dumps(line), flush=True)
