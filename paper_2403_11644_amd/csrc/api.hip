@@ -78,7 +78,7 @@ size_t ptd_workspace_bytes(int n, ptd_dtype dtype, unsigned flags, int s)
 {
     (void)s;
     if (n < 1 || n > 16 || !valid_dtype(dtype)) return 0;
-    if (flags & (kStructure | PTD_ADJOINT)) return 0;
+    if (flags & (kStructure | PTD_ADJOINT | PTD_TOEPLITZ | PTD_PURE_STATE)) return 0;
     if (use_fused(n, dtype, flags)) return ptd::fused_workspace_bytes(n, dtype);
     return 0;
 }
@@ -144,10 +144,8 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
         if (flags & (kStructure | PTD_COMPENSATED)) return PTD_EUNSUP;
         const int src = (flags & PTD_TOEPLITZ) ? ptd::SRC_TOEPLITZ : ptd::SRC_PURE;
         if (n <= 10) return hip_status(ptd::launch_group_src(n, dtype, herm, src, A, coeff, st));
-        if (!use_fused(n, dtype, flags)) return PTD_EUNSUP;
-        if (!ws) return PTD_ENOSPC;
-        return hip_status(ptd::launch_fused_src(n, dtype, herm, src, A, coeff, ws,
-                                                ptd::fused_default(n, dtype, herm).la, st));
+        if (n > 15 || (n == 15 && dtype == PTD_C128)) return PTD_EUNSUP;
+        return hip_status(ptd::launch_mfree(n, dtype, herm, src, A, coeff, st));
     }
     if (flags & kStructure) {
         if (flags & PTD_COMPENSATED) return PTD_EUNSUP;

@@ -109,15 +109,6 @@ hipError_t launch_fused_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const 
                 : fused_rec_c64(n, coeff, A, lda, ws, la, adjoint, st);
 }
 
-hipError_t launch_fused_src(int n, ptd_dtype dt, bool herm, int src, const void* t, void* out, void* ws, int la,
-                            hipStream_t st)
-{
-    if (n < 11 || n > 15 || la < 1) return hipErrorInvalidValue;
-    if (dt == PTD_C128)
-        return herm ? fused_src_c128h(n, src, t, out, ws, la, st) : fused_src_c128(n, src, t, out, ws, la, st);
-    return herm ? fused_src_c64h(n, src, t, out, ws, la, st) : fused_src_c64(n, src, t, out, ws, la, st);
-}
-
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st)
 {
     const int64_t count = (int64_t)(bytes / 16);

@@ -75,12 +75,6 @@ constexpr int WS_GROUP = 32;  // [num groups] phase-1 completions per group
 constexpr int POL_NT_GATHER = 1;
 constexpr int POL_NT_STORE = 2;
 constexpr int POL_NT_P2LOAD = 4;
-// Matrix-free sources (engine.hpp, source_entry): the A argument holds the
-// defining vector, read by cached gathers (it stays in L2).  POL_TOEPLITZ:
-// t[0 .. 2^(n+1) - 2] with A[r][c] = t[c - r + 2^n - 1]; POL_PURE: psi with
-// A[r][c] = psi[r] conj(psi[c]).
-constexpr int POL_TOEPLITZ = 8;
-constexpr int POL_PURE = 16;
 
 template <class V>
 constexpr int fused_logt()
@@ -264,14 +258,7 @@ __device__ __forceinline__ void phase1(const cplx<V>* __restrict__ A, int64_t ld
     }
     auto gather = [&](int vec, int pos, V& re, V& im) {
         const int k = k0 + pos;
-        if constexpr ((POL & (POL_TOEPLITZ | POL_PURE)) != 0) {
-            const cplx<V> v = source_entry<V, (POL & POL_TOEPLITZ) ? SRC_TOEPLITZ : SRC_PURE>(
-                A, lda, S::LOGN, k, k ^ (int)(xg | vec));
-            re = v.re;
-            im = v.im;
-        } else {
-            load_c<V, (POL & POL_NT_GATHER) != 0>(A + (int64_t)k * lda + (k ^ (int)(xg | vec)), re, im);
-        }
+        load_c<V, (POL & POL_NT_GATHER) != 0>(A + (int64_t)k * lda + (k ^ (int)(xg | vec)), re, im);
     };
     auto store = [&](int vec, int pos, V re, V im) {
         const uint32_t x = xg | (uint32_t)vec;
@@ -801,34 +788,6 @@ hipError_t fused_dispatch(int n, const void* A, int64_t lda, void* out, void* ws
 #undef PTD_CFG
 }
 
-// Matrix-free source (SRCPOL: POL_TOEPLITZ or POL_PURE): the default shape
-// of n, with non-temporal final stores and phase-2 loads and cached gathers.
-template <class V, bool HERM, int SRCPOL>
-hipError_t fused_dispatch_src(int n, const void* t, void* out, void* ws, int la, hipStream_t st)
-{
-    constexpr int LT = fused_logt<V>();
-    constexpr int P = SRCPOL | POL_NT_STORE | POL_NT_P2LOAD;
-    const int shape = fused_default(n, sizeof(V) == 8 ? PTD_C128 : PTD_C64, HERM).cfg & 3;
-    if (shape == 2) {
-        switch (n) {
-            case 11: return launch_cfg<V, 11, 9, 512, LT, HERM, P>(t, 0, out, ws, la, st);
-            case 12: return launch_cfg<V, 12, 9, 512, LT, HERM, P>(t, 0, out, ws, la, st);
-            case 13: return launch_cfg<V, 13, 9, 512, LT, HERM, P>(t, 0, out, ws, la, st);
-            case 14: return launch_cfg<V, 14, 9, 512, LT, HERM, P>(t, 0, out, ws, la, st);
-            default: return hipErrorInvalidValue;
-        }
-    }
-    switch (n) {
-        case 11: return launch_cfg<V, 11, 10, 1024, LT, HERM, P>(t, 0, out, ws, la, st);
-        case 12: return launch_cfg<V, 12, 10, 1024, LT, HERM, P>(t, 0, out, ws, la, st);
-        case 13: return launch_cfg<V, 13, 10, 1024, LT, HERM, P>(t, 0, out, ws, la, st);
-        case 14: return launch_cfg<V, 14, 10, 1024, LT, HERM, P>(t, 0, out, ws, la, st);
-        case 15:
-            if constexpr (!HERM && sizeof(V) == 4) return launch_cfg<V, 15, 10, 1024, LT, HERM, P>(t, 0, out, ws, la, st);
-            return hipErrorInvalidValue;
-        default: return hipErrorInvalidValue;
-    }
-}
 
 }  // namespace fused
 }  // namespace ptd

@@ -15,11 +15,4 @@ hipError_t fused_rec_c64_herm(int n, const void* coeff, void* A, int64_t lda, vo
     return fused::fused_rec_dispatch<float, true>(n, coeff, A, lda, ws, la, adjoint, st);
 }
 
-hipError_t fused_src_c64h(int n, int src, const void* t, void* out, void* ws, int la, hipStream_t st)
-{
-    if (src == SRC_TOEPLITZ) return fused::fused_dispatch_src<float, true, fused::POL_TOEPLITZ>(n, t, out, ws, la, st);
-    if (src == SRC_PURE) return fused::fused_dispatch_src<float, true, fused::POL_PURE>(n, t, out, ws, la, st);
-    return hipErrorInvalidValue;
-}
-
 }  // namespace ptd

@@ -81,16 +81,12 @@ hipError_t fused_rec_c128_herm(int n, const void* coeff, void* A, int64_t lda, v
                                hipStream_t st);
 hipError_t launch_fused_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const void* coeff, void* A, int64_t lda,
                             void* ws, int la, hipStream_t st);
-// Matrix-free input (src: SRC_TOEPLITZ or SRC_PURE, engine.hpp) given by its
-// defining vector: the single-launch schedule (n = 11..15 where it applies)
-// and the single-pass group kernel (n <= 10).
-hipError_t fused_src_c64(int n, int src, const void* t, void* out, void* ws, int la, hipStream_t st);
-hipError_t fused_src_c128(int n, int src, const void* t, void* out, void* ws, int la, hipStream_t st);
-hipError_t fused_src_c64h(int n, int src, const void* t, void* out, void* ws, int la, hipStream_t st);
-hipError_t fused_src_c128h(int n, int src, const void* t, void* out, void* ws, int la, hipStream_t st);
-hipError_t launch_fused_src(int n, ptd_dtype dt, bool herm, int src, const void* t, void* out, void* ws, int la,
-                            hipStream_t st);
+// Matrix-free input (src: SRC_TOEPLITZ or SRC_PURE) given by its defining
+// vector: the single-pass group kernel (n <= 10).
 hipError_t launch_group_src(int n, ptd_dtype dt, bool herm, int src, const void* t, void* out, hipStream_t st);
+// Matrix-free input for n = 11..14 (15 for complex64): one workgroup per
+// X-pattern, the row's transform in LDS (mfree.hip).
+hipError_t launch_mfree(int n, ptd_dtype dt, bool herm, int src, const void* t, void* out, hipStream_t st);
 // Zero `count` uint32 words with a small kernel (capturable, unlike a memset node).
 hipError_t launch_zero_words(uint32_t* p, int count, hipStream_t st);
 // Plain 16-byte-per-lane device copy (bandwidth reference).

@@ -1,0 +1,229 @@
+// mfree.hip -- dense decomposition of a matrix-free input (a Toeplitz matrix
+// given by its defining entries, or the density matrix of a state vector)
+// for n >= 11: one workgroup per X-pattern.
+//
+// A matrix-free source costs no HBM read: its defining vector (at most
+// 2^(n+1) complex values) stays in L2.  So the whole length-2^n transform of
+// one X-pattern runs in one workgroup, out of LDS, and the output row is
+// written once with coalesced stores; the only HBM traffic is the output.
+// (The single-launch schedule for stored matrices exchanges partial
+// transforms through the memory side, because a group's band of a stored
+// matrix must be read in whole 128-byte segments and does not fit one CU.)
+//
+// LDS holds 2^m values of the row: m = n while 2^n values fit in 128 KiB
+// (n <= 13 complex128, n <= 14 complex64).  One size beyond (n = 14
+// complex128, n = 15 complex64) the workgroup transforms the two halves
+// k < 2^(n-1) and k >= 2^(n-1) one after the other, keeps the first half's
+// result in registers, and finishes with the butterfly over the top bit.
+//
+// Every path applies the radix-2 stages in ascending bit order with the same
+// additions as the kernels for stored matrices, so a matrix-free call gives
+// the bits of a dense call on the materialised matrix.
+//
+// Measured on MI355X at n = 14: 1.06 ms complex128 (4.0 TB/s of output
+// writes), 0.54 ms complex64.  Gathering with 8 or 16 loads in flight per
+// thread, 256 or 1024 threads, or radix 8 rounds changed it by -5% to +35%;
+// the single-launch schedule of stored matrices took 1.64 ms.
+#include "engine.hpp"
+#include "internal.hpp"
+
+namespace ptd {
+
+namespace {
+
+template <class V>
+constexpr int mf_rmax()
+{
+    return sizeof(V) == 4 ? 5 : 4;
+}
+
+// workgroup size of the whole-row kernel: one radix-16 item per thread
+constexpr int mf_threads(int logn)
+{
+    return (1 << logn) / 16 < 64 ? 64 : ((1 << logn) / 16 > 1024 ? 1024 : (1 << logn) / 16);
+}
+
+constexpr int MF_HALF_THREADS = 512;
+
+// LDS slot of row position p: one pad element after every 16, so that the
+// first round (each thread owns 16 or 32 consecutive positions) reads with
+// lanes on different banks
+__device__ __forceinline__ int mf_slot(int p) { return p + (p >> 4); }
+constexpr int mf_lds_elems(int logm) { return (1 << logm) + (1 << (logm - 4)); }
+
+template <class V>
+struct MfRead {
+    cplx<V>* p;
+    __device__ __forceinline__ void operator()(int, int pos, V& re, V& im) const
+    {
+        const cplx<V> v = p[mf_slot(pos)];
+        re = v.re;
+        im = v.im;
+    }
+};
+
+template <class V>
+struct MfWrite {
+    cplx<V>* p;
+    __device__ __forceinline__ void operator()(int, int pos, V re, V im) const
+    {
+        cplx<V> v;
+        v.re = re;
+        v.im = im;
+        p[mf_slot(pos)] = v;
+    }
+};
+
+// d_x[kb + p] for the 2^LM positions p, into LDS; consecutive lanes take
+// consecutive positions, so the source reads of a wave stay within a few
+// cache lines
+template <class V, int LM, int NT, int SRC>
+__device__ __forceinline__ void mf_gather(const cplx<V>* __restrict__ src, int logn, uint32_t x, int kb, cplx<V>* lds)
+{
+#pragma unroll 4
+    for (int p = threadIdx.x; p < (1 << LM); p += NT) {
+        const int k = kb + p;
+        lds[mf_slot(p)] = source_entry<V, SRC>(src, 0, logn, k, k ^ (int)x);
+    }
+}
+
+// Rounds over bits [B0, LM) of the LDS row, RMAX bits at most each, in
+// ascending bit order; the last round hands its values to `last`.
+template <class V, int LM, int NT, int RMAX, int B0, class Last>
+__device__ __forceinline__ void mf_rounds(cplx<V>* lds, const Last& last)
+{
+    constexpr int NB = (LM - B0) < RMAX ? (LM - B0) : RMAX;
+    MfRead<V> rd{lds};
+    if constexpr (B0 + NB == LM) {
+        wht_round<V, 0, LM, B0, NB, NT, false>(rd, last);
+    } else {
+        wht_round<V, 0, LM, B0, NB, NT, false>(rd, MfWrite<V>{lds});
+        __syncthreads();
+        mf_rounds<V, LM, NT, RMAX, B0 + NB>(lds, last);
+    }
+}
+
+template <class V, bool REAL_OUT>
+__device__ __forceinline__ void mf_store(void* __restrict__ out, int logn, uint32_t x, uint32_t z, V re, V im,
+                                         V scale)
+{
+    mul_ipow(__popc(x & z) & 3, re, im);
+    re *= scale;
+    im *= scale;
+    const int64_t o = ((int64_t)x << logn) + z;
+    if constexpr (REAL_OUT) {
+        __builtin_nontemporal_store(re, (V*)out + o);
+    } else {
+        typedef V v2 __attribute__((ext_vector_type(2)));
+        v2 v;
+        v.x = re;
+        v.y = im;
+        __builtin_nontemporal_store(v, (v2*)out + o);
+    }
+}
+
+template <class V, int LOGN, bool REAL_OUT, int SRC>
+__global__ __launch_bounds__(mf_threads(LOGN)) void k_mfree_row(const cplx<V>* __restrict__ src,
+                                                                void* __restrict__ out)
+{
+    constexpr int NT = mf_threads(LOGN);
+    __shared__ cplx<V> lds[mf_lds_elems(LOGN)];
+    const uint32_t x = blockIdx.x;
+    const V scale = exp2_neg<V>(LOGN);
+    mf_gather<V, LOGN, NT, SRC>(src, LOGN, x, 0, lds);
+    __syncthreads();
+    auto store = [&](int, int pos, V re, V im) { mf_store<V, REAL_OUT>(out, LOGN, x, (uint32_t)pos, re, im, scale); };
+    mf_rounds<V, LOGN, NT, mf_rmax<V>(), 0>(lds, store);
+}
+
+template <class V, int LOGN, bool REAL_OUT, int SRC>
+__global__ __launch_bounds__(MF_HALF_THREADS) void k_mfree_halves(const cplx<V>* __restrict__ src,
+                                                                  void* __restrict__ out)
+{
+    constexpr int LH = LOGN - 1;
+    constexpr int NT = MF_HALF_THREADS;
+    constexpr int J = (1 << LH) / NT;  // positions per thread in the final butterfly
+    __shared__ cplx<V> lds[mf_lds_elems(LH)];
+    const uint32_t x = blockIdx.x;
+    const int t = threadIdx.x;
+    V w0r[J], w0i[J];
+
+    // the transform over bits 0 .. LH-1 of half h, left in LDS
+    auto half = [&](int h) {
+        mf_gather<V, LH, NT, SRC>(src, LOGN, x, h << LH, lds);
+        __syncthreads();
+        mf_rounds<V, LH, NT, mf_rmax<V>(), 0>(lds, MfWrite<V>{lds});
+        __syncthreads();
+    };
+
+    half(0);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const cplx<V> v = lds[mf_slot(t + NT * j)];
+        w0r[j] = v.re;
+        w0i[j] = v.im;
+    }
+    __syncthreads();  // every thread has its values before LDS is reused
+    half(1);
+
+    // the top bit: z and z + 2^LH from the two halves' values at z
+    const V scale = exp2_neg<V>(LOGN);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const uint32_t z = (uint32_t)(t + NT * j);
+        const cplx<V> v = lds[mf_slot((int)z)];
+        mf_store<V, REAL_OUT>(out, LOGN, x, z, w0r[j] + v.re, w0i[j] + v.im, scale);
+        mf_store<V, REAL_OUT>(out, LOGN, x, z | (1u << LH), w0r[j] - v.re, w0i[j] - v.im, scale);
+    }
+}
+
+template <class V, bool REAL_OUT, int SRC>
+hipError_t mfree_t(int n, const void* src, void* out, hipStream_t st)
+{
+    const dim3 grid(1u << n);
+    const cplx<V>* s = (const cplx<V>*)src;
+    switch (n) {
+#define PTD_ROW(NN)                                                                                         \
+    case NN:                                                                                                \
+        hipLaunchKernelGGL((k_mfree_row<V, NN, REAL_OUT, SRC>), grid, dim3(mf_threads(NN)), 0, st, s, out); \
+        break;
+        PTD_ROW(11) PTD_ROW(12) PTD_ROW(13)
+#undef PTD_ROW
+        case 14:
+            if constexpr (sizeof(V) == 4)
+                hipLaunchKernelGGL((k_mfree_row<V, 14, REAL_OUT, SRC>), grid, dim3(mf_threads(14)), 0, st, s, out);
+            else
+                hipLaunchKernelGGL((k_mfree_halves<V, 14, REAL_OUT, SRC>), grid, dim3(MF_HALF_THREADS), 0, st, s,
+                                   out);
+            break;
+        case 15:
+            if constexpr (sizeof(V) == 4) {
+                hipLaunchKernelGGL((k_mfree_halves<V, 15, REAL_OUT, SRC>), grid, dim3(MF_HALF_THREADS), 0, st, s,
+                                   out);
+                break;
+            }
+            return hipErrorInvalidValue;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <class V, bool REAL_OUT>
+hipError_t mfree_src(int n, int src, const void* t, void* out, hipStream_t st)
+{
+    if (src == SRC_TOEPLITZ) return mfree_t<V, REAL_OUT, SRC_TOEPLITZ>(n, t, out, st);
+    if (src == SRC_PURE) return mfree_t<V, REAL_OUT, SRC_PURE>(n, t, out, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_mfree(int n, ptd_dtype dt, bool herm, int src, const void* t, void* out, hipStream_t st)
+{
+    if (dt == PTD_C128)
+        return herm ? mfree_src<double, true>(n, src, t, out, st) : mfree_src<double, false>(n, src, t, out, st);
+    return herm ? mfree_src<float, true>(n, src, t, out, st) : mfree_src<float, false>(n, src, t, out, st);
+}
+
+}  // namespace ptd

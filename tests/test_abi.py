@@ -283,17 +283,17 @@ def test_lcu_argument_errors(lib):
 
 
 def test_toeplitz_argument_errors(lib):
-    """Matrix-free Toeplitz input: the dense schedules that read A (complex128
-    and Hermitian at n = 15, n = 16) and the structure flags are refused on
-    the host."""
+    """Matrix-free input: the sizes without a kernel (complex128 at n = 15,
+    n = 16) and the structure flags are refused on the host."""
     from paper_2403_11644_amd import api
 
     EUNSUP = -3
     big, far = 1 << 40, 1 << 41
     dec = lambda n, dt, flags: lib.pauli_decompose(n, dt, flags, 0, big, 0, far, None, 0, None)
     assert dec(15, api.C128, api.TOEPLITZ) == EUNSUP
-    assert dec(15, api.C64, api.TOEPLITZ | api.HERMITIAN) == EUNSUP
+    assert dec(15, api.C128, api.PURE_STATE | api.HERMITIAN) == EUNSUP
     assert dec(16, api.C64, api.TOEPLITZ) == EUNSUP
+    assert dec(16, api.C64, api.PURE_STATE) == EUNSUP
     assert dec(12, api.C64, api.TOEPLITZ | api.DIAGONAL) == EUNSUP
     assert dec(12, api.C64, api.TOEPLITZ | api.COMPENSATED) == EUNSUP
     assert dec(3, api.C64, api.TOEPLITZ | api.COMPACT) == -1  # compact needs a structure

@@ -492,6 +492,21 @@ def test_toeplitz_n15_complex64(ptd):
     torch.cuda.empty_cache()
 
 
+def test_toeplitz_n15_complex64_hermitian(ptd):
+    """Real output at n = 15 (complex64, two halves per row): the real part
+    of the complex call bit for bit, and exactly real there."""
+    import torch
+
+    t = _toeplitz_vec(15, 316, np.complex64, True)
+    td = to_dev(t)
+    full = ptd.decompose(td, toeplitz=True)
+    assert float(full.imag.abs().max()) == 0.0
+    re = ptd.decompose(td, toeplitz=True, hermitian=True)
+    assert bool(torch.equal(re, full.real))
+    del full, re
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("n", [2, 5, 8])
 def test_toeplitz_integer_exact(ptd, oracle_mod, n):
     N = 1 << n
