@@ -342,6 +342,14 @@ def test_fused_hermitian(ptd, oracle_mod, dt, n, cfg):
         xs, zs = synth.sample_strings(n, 2000, seed=3)
         want = oracle_mod.coeffs(A_h, xs, zs)
         np.testing.assert_array_equal(real[xs, zs], want.real)
+    if n == 13:
+        # every coefficient at once: 2^n c_P is an integer, and Parseval
+        # (Theorem 1) holds exactly in integers, sum (2^n c_P)^2 = 2^n ||A||_F^2
+        C = real.astype(np.float64) * (1 << n)
+        assert np.all(C == np.round(C))
+        Ci = C.astype(np.int64)
+        rhs = (1 << n) * int((re.astype(np.int64) ** 2 + im.astype(np.int64) ** 2).sum())
+        assert int((Ci * Ci).sum()) == rhs
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
