@@ -392,6 +392,18 @@ def sparse_nonempty_x(n: int, rows, cols) -> list[int]:
     return sorted({int(x) for x in (rows[ok] ^ cols[ok])})
 
 
+def mixed_density(U: np.ndarray) -> np.ndarray:
+    """The matrix U U^* = sum_r u_r u_r^* over the columns u_r of the
+    2^n x R factor U: a mixed state (a density matrix of rank <= R, the
+    weights absorbed into the columns) given by its factor.  Its
+    coefficients are sum_r <u_r|P|u_r> / 2^n."""
+    U = np.asarray(U).astype(np.complex128)
+    rho = np.zeros((U.shape[0], U.shape[0]), dtype=np.complex128)
+    for r in range(U.shape[1]):
+        rho += np.outer(U[:, r], np.conj(U[:, r]))
+    return rho
+
+
 def pure_density(psi: np.ndarray) -> np.ndarray:
     """The density matrix |psi><psi| of a state vector, A[r][c] = psi[r]
     conj(psi[c]); its coefficients are the Pauli expectation values

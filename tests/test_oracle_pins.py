@@ -437,3 +437,31 @@ def test_pure_state_expectations(oracle_mod):
     nrm = float(np.vdot(psi, psi).real)
     assert c[0, 0].real == pytest.approx(nrm / N, rel=1e-14)
     assert N * float(np.sum(np.abs(c) ** 2)) == pytest.approx(nrm ** 2, rel=1e-13)
+
+
+def test_mixed_state_expectations(oracle_mod):
+    # U U^* over three columns: the coefficients are the sums over the
+    # columns of <u_r|P|u_r> / 2^n (textbook P from np.kron), real; one column
+    # gives the pure state's density matrix
+    n, R = 3, 3
+    N = 1 << n
+    U = synth.complex_normal((N, R), seed=88)
+    c = oracle_mod.decompose(oracle_mod.mixed_density(U))
+    for x in range(N):
+        for z in range(N):
+            P = oracle_mod.pauli_matrix(oracle_mod.label(x, z, n))
+            want = sum(np.vdot(U[:, r], P @ U[:, r]) for r in range(R)) / N
+            assert abs(c[x, z] - want) <= 1e-14
+    np.testing.assert_allclose(c.imag, 0, atol=1e-15)
+    np.testing.assert_array_equal(oracle_mod.mixed_density(U[:, :1]), oracle_mod.pure_density(U[:, 0]))
+
+
+def test_maximally_mixed_state(oracle_mod):
+    # U = I / 2 on two qubits: rho = I / 4 exactly, so only the identity
+    # string survives, with Tr(rho) / 2^n = 1/4
+    n = 2
+    U = np.eye(4, dtype=np.complex128) / 2
+    c = oracle_mod.decompose(oracle_mod.mixed_density(U))
+    want = np.zeros((4, 4), dtype=np.complex128)
+    want[0, 0] = 0.25
+    np.testing.assert_array_equal(c, want)
