@@ -490,7 +490,13 @@ def main() -> int:
         ms_p = _time(lambda: ptd.decompose(psi, pure_state=True, hermitian=True, out=hout14), args.steps,
                      args.warmup, stream)
         leg["pure_state_expectations_f64_ms"] = round(ms_p, 4)
-        del psi, hout14
+        # mixed state U U^* of rank 4 from its 2^14 x 4 factor
+        g.manual_seed(143)
+        U4 = torch.randn((N, 4), dtype=torch.complex128, device=dev, generator=g)
+        ms_m = _time(lambda: ptd.decompose(U4, low_rank=True, hermitian=True, out=hout14), args.steps, args.warmup,
+                     stream)
+        leg["mixed_state_rank4_expectations_f64_ms"] = round(ms_m, 4)
+        del psi, hout14, U4
         legs["matrix_free_n14"] = leg
         del tv, tv64, o64
         torch.cuda.empty_cache()

@@ -99,9 +99,9 @@ typedef void *ptd_stream;
  * elements with A[r][c] = t[c - r + 2^n - 1] (t[0] is the bottom-left entry,
  * t[2^n - 1] the diagonal, t[2^(n+1) - 2] the top-right); lda is ignored.
  * The kernels read t (a few MiB at most, cache-resident) instead of 4^n
- * entries.  Dense decompositions only: n <= 14, or n = 15 for complex64
- * without PTD_HERMITIAN; PTD_EUNSUP beyond, and with structure flags or
- * PTD_COMPENSATED.  With PTD_HERMITIAN, t[2^n - 1 - d] = conj(t[2^n - 1 + d]). */
+ * entries.  Dense decompositions only: n <= 14, or n = 15 for complex64;
+ * PTD_EUNSUP beyond, and with structure flags or PTD_COMPENSATED.  With
+ * PTD_HERMITIAN, t[2^n - 1 - d] = conj(t[2^n - 1 + d]). */
 #define PTD_TOEPLITZ (1u << 9)
 /* Matrix-free pure-state input: A is the density matrix |psi><psi| of the
  * state vector psi (2^n elements of dtype at A), A[r][c] = psi[r]
@@ -112,6 +112,16 @@ typedef void *ptd_stream;
  * output; PTD_HERMITIAN gives the real array).  Same sizes and exclusions as
  * PTD_TOEPLITZ, with which it does not combine. */
 #define PTD_PURE_STATE (1u << 10)
+/* Matrix-free mixed-state input: A = U U^* for the 2^n x s factor U at A
+ * (dtype elements, row-major, row pitch lda >= s elements, lda <= 2^40),
+ * A[r][c] = sum_j U[r][j] conj(U[c][j]) formed on the fly with the products
+ * of PTD_PURE_STATE summed over ascending j (1 <= s <= 32, PTD_EINVAL
+ * otherwise).  A density matrix of rank <= s, the weights absorbed into the
+ * columns: the coefficients are the Pauli expectation values
+ * sum_j <u_j|P|u_j> / 2^n of the mixed state, real (PTD_HERMITIAN gives
+ * the real array).  Same sizes and exclusions as PTD_TOEPLITZ; one
+ * matrix-free flag per call. */
+#define PTD_LOW_RANK (1u << 11)
 
 /* Workspace (device bytes) a pauli_decompose call with these arguments
  * needs: a few KiB of queue counters for dense decompositions with

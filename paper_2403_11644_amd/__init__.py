@@ -4,8 +4,8 @@ c_P = 2^-n Tr(P A) for all 4^n Pauli strings of a 2^n x 2^n complex matrix,
 computed by hand-written gfx950 HIP kernels behind a C ABI (include/ptd.h).
 """
 from .api import (  # noqa: F401
-    ADJOINT, ANTIDIAGONAL, BANDED, BANDS_IN, C64, C128, COMPACT, COMPENSATED, DIAGONAL, HERMITIAN, PURE_STATE,
-    TOEPLITZ, BatchPlan,
+    ADJOINT, ANTIDIAGONAL, BANDED, BANDS_IN, C64, C128, COMPACT, COMPENSATED, DIAGONAL, HERMITIAN, LOW_RANK,
+    PURE_STATE, TOEPLITZ, BatchPlan,
     block_diagonal, decompose, decompose_batched, decompose_sparse, direct_sum, hermitian_augment, lcu_amplitudes,
     linear_combination, nonempty_x, num_nonempty_x, pad_to_power_of_two, parseval, reconstruct,
 )

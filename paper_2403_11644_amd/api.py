@@ -23,6 +23,7 @@ COMPACT = 1 << 4
 ANTIDIAGONAL = 1 << 8
 TOEPLITZ = 1 << 9
 PURE_STATE = 1 << 10
+LOW_RANK = 1 << 11
 COMPENSATED = 1 << 5
 ADJOINT = 1 << 6
 
@@ -110,8 +111,8 @@ def nonempty_x(n: int, structure: str | None = None, s: int = 0) -> list[int]:
 
 def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None = None, s: int | None = None,
               bands: bool = False, compact: bool = False, compensated: bool = False, pad: bool = False,
-              toeplitz: bool = False, pure_state: bool = False, out: torch.Tensor | None = None,
-              stream=None) -> torch.Tensor:
+              toeplitz: bool = False, pure_state: bool = False, low_rank: bool = False,
+              out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Pauli coefficients of A, as a (2^n, 2^n) tensor c[x, z].
 
     hermitian   A == A^*: return the (real) coefficients as float64/float32.
@@ -127,14 +128,29 @@ def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None
     pure_state  A is a state vector psi of 2^n entries and the matrix is
                 |psi><psi| (matrix-free): the coefficients are the Pauli
                 expectation values <psi|P|psi> / 2^n.
+    low_rank    A is a 2^n x r factor U (r <= 32, rows contiguous) and the
+                matrix is the mixed state U U^* (matrix-free): the
+                coefficients are sum_j <u_j|P|u_j> / 2^n over its columns.
     """
     _require_device(A, "A")
     code = _dtype_code(A.dtype)
-    if toeplitz or pure_state:
-        if toeplitz and pure_state:
-            raise ValueError("toeplitz and pure_state exclude each other")
+    if toeplitz or pure_state or low_rank:
+        if int(toeplitz) + int(pure_state) + int(low_rank) > 1:
+            raise ValueError("toeplitz, pure_state and low_rank exclude each other")
         if structure is not None or bands or pad or compact or compensated:
             raise ValueError("matrix-free input takes a dense decomposition only")
+        if low_rank:
+            if A.dim() != 2 or not 1 <= A.shape[1] <= 32:
+                raise ValueError("a low-rank factor is 2-D with 1..32 columns")
+            N = A.shape[0]
+            n = _nqubits(N)
+            flags = LOW_RANK | (HERMITIAN if hermitian else 0)
+            odt = _real_dtype(code) if hermitian else _complex_dtype(code)
+            out = _check_out(out, (N, N), odt, A.device)
+            st = _native.lib().pauli_decompose(n, code, flags, int(A.shape[1]), _ptr(A), _rows(A, "U"), _ptr(out),
+                                               None, 0, _stream_handle(A.device, stream))
+            _native.check(st, "pauli_decompose")
+            return out
         if A.dim() != 1 or not A.is_contiguous():
             raise ValueError("matrix-free input is a contiguous vector")
         if toeplitz:

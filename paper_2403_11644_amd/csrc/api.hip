@@ -15,7 +15,9 @@ namespace {
 thread_local int g_last_hip_error = 0;
 
 constexpr unsigned kAllFlags = PTD_HERMITIAN | PTD_DIAGONAL | PTD_BANDED | PTD_BANDS_IN | PTD_COMPACT |
-                               PTD_COMPENSATED | PTD_ADJOINT | PTD_ANTIDIAGONAL | PTD_TOEPLITZ | PTD_PURE_STATE;
+                               PTD_COMPENSATED | PTD_ADJOINT | PTD_ANTIDIAGONAL | PTD_TOEPLITZ | PTD_PURE_STATE |
+                               PTD_LOW_RANK;
+constexpr unsigned kMatrixFree = PTD_TOEPLITZ | PTD_PURE_STATE | PTD_LOW_RANK;
 constexpr unsigned kStructure = PTD_DIAGONAL | PTD_BANDED | PTD_ANTIDIAGONAL;
 
 ptd_status hip_status(hipError_t e)
@@ -78,7 +80,7 @@ size_t ptd_workspace_bytes(int n, ptd_dtype dtype, unsigned flags, int s)
 {
     (void)s;
     if (n < 1 || n > 16 || !valid_dtype(dtype)) return 0;
-    if (flags & (kStructure | PTD_ADJOINT | PTD_TOEPLITZ | PTD_PURE_STATE)) return 0;
+    if (flags & (kStructure | PTD_ADJOINT | kMatrixFree)) return 0;
     if (use_fused(n, dtype, flags)) return ptd::fused_workspace_bytes(n, dtype);
     return 0;
 }
@@ -130,10 +132,13 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
     if (flags & PTD_ADJOINT) return PTD_EINVAL;
     const ptd_status sst = check_structure(n, flags, s);
     if (sst != PTD_OK) return sst;
-    // matrix-free input: a defining vector instead of the matrix
-    const bool mfree = flags & (PTD_TOEPLITZ | PTD_PURE_STATE);
-    if ((flags & PTD_TOEPLITZ) && (flags & PTD_PURE_STATE)) return PTD_EINVAL;
+    // matrix-free input: a defining vector or factor instead of the matrix
+    const unsigned mf = flags & kMatrixFree;
+    if (mf & (mf - 1)) return PTD_EINVAL;  // at most one kind
+    const bool mfree = mf != 0;
     if (!mfree && lda < ((int64_t)1 << n)) return PTD_EINVAL;
+    if ((flags & PTD_LOW_RANK) && (s < 1 || s > ptd::LOWRANK_MAX || lda < s || lda > ((int64_t)1 << 40)))
+        return PTD_EINVAL;
     if ((flags & PTD_COMPENSATED) && dtype != PTD_C64) return PTD_EUNSUP;
     if (ws_bytes < ptd_workspace_bytes(n, dtype, flags, s)) return PTD_ENOSPC;
     (void)ws;
@@ -142,10 +147,13 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
     const bool herm = flags & PTD_HERMITIAN;
     if (mfree) {
         if (flags & (kStructure | PTD_COMPENSATED)) return PTD_EUNSUP;
-        const int src = (flags & PTD_TOEPLITZ) ? ptd::SRC_TOEPLITZ : ptd::SRC_PURE;
-        if (n <= 10) return hip_status(ptd::launch_group_src(n, dtype, herm, src, A, coeff, st));
+        const int src = (flags & PTD_TOEPLITZ) ? ptd::SRC_TOEPLITZ
+                        : (flags & PTD_PURE_STATE) ? ptd::SRC_PURE
+                                                   : ptd::SRC_LOWRANK;
+        const int64_t ld = src == ptd::SRC_LOWRANK ? ptd::lowrank_ld(lda, s) : 0;
+        if (n <= 10) return hip_status(ptd::launch_group_src(n, dtype, herm, src, A, ld, coeff, st));
         if (n > 15 || (n == 15 && dtype == PTD_C128)) return PTD_EUNSUP;
-        return hip_status(ptd::launch_mfree(n, dtype, herm, src, A, coeff, st));
+        return hip_status(ptd::launch_mfree(n, dtype, herm, src, A, ld, coeff, st));
     }
     if (flags & kStructure) {
         if (flags & PTD_COMPENSATED) return PTD_EUNSUP;

@@ -546,7 +546,7 @@ hipError_t launch_dense_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const 
 // single-pass group kernel with 512-thread workgroups and radix-16 rounds
 // (the results do not depend on the plan).
 template <class V, int SRC>
-hipError_t group_src_t(int n, bool herm, const void* src, void* out, hipStream_t st)
+hipError_t group_src_t(int n, bool herm, const void* src, int64_t ld, void* out, hipStream_t st)
 {
     const int N = 1 << n;
     const dim3 grid(N >> group_logt<V>(n));
@@ -555,10 +555,10 @@ hipError_t group_src_t(int n, bool herm, const void* src, void* out, hipStream_t
     case NN:                                                                                                  \
         if (herm)                                                                                             \
             hipLaunchKernelGGL((k_group_fwd<V, NN, true, 512, 4, SRC>), grid, dim3(512), 0, st,               \
-                               (const cplx<V>*)src, (int64_t)0, out, (int64_t)N);                             \
+                               (const cplx<V>*)src, ld, out, (int64_t)N);                                     \
         else                                                                                                  \
             hipLaunchKernelGGL((k_group_fwd<V, NN, false, 512, 4, SRC>), grid, dim3(512), 0, st,              \
-                               (const cplx<V>*)src, (int64_t)0, out, (int64_t)N);                             \
+                               (const cplx<V>*)src, ld, out, (int64_t)N);                                     \
         break;
         PTD_T(1) PTD_T(2) PTD_T(3) PTD_T(4) PTD_T(5) PTD_T(6) PTD_T(7) PTD_T(8) PTD_T(9) PTD_T(10)
 #undef PTD_T
@@ -567,15 +567,19 @@ hipError_t group_src_t(int n, bool herm, const void* src, void* out, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_group_src(int n, ptd_dtype dt, bool herm, int src, const void* ptr, void* out, hipStream_t st)
+hipError_t launch_group_src(int n, ptd_dtype dt, bool herm, int src, const void* ptr, int64_t ld, void* out,
+                            hipStream_t st)
 {
     if (n < 1 || n > 10) return hipErrorInvalidValue;
     if (src == SRC_TOEPLITZ)
-        return dt == PTD_C128 ? group_src_t<double, SRC_TOEPLITZ>(n, herm, ptr, out, st)
-                              : group_src_t<float, SRC_TOEPLITZ>(n, herm, ptr, out, st);
+        return dt == PTD_C128 ? group_src_t<double, SRC_TOEPLITZ>(n, herm, ptr, ld, out, st)
+                              : group_src_t<float, SRC_TOEPLITZ>(n, herm, ptr, ld, out, st);
     if (src == SRC_PURE)
-        return dt == PTD_C128 ? group_src_t<double, SRC_PURE>(n, herm, ptr, out, st)
-                              : group_src_t<float, SRC_PURE>(n, herm, ptr, out, st);
+        return dt == PTD_C128 ? group_src_t<double, SRC_PURE>(n, herm, ptr, ld, out, st)
+                              : group_src_t<float, SRC_PURE>(n, herm, ptr, ld, out, st);
+    if (src == SRC_LOWRANK)
+        return dt == PTD_C128 ? group_src_t<double, SRC_LOWRANK>(n, herm, ptr, ld, out, st)
+                              : group_src_t<float, SRC_LOWRANK>(n, herm, ptr, ld, out, st);
     return hipErrorInvalidValue;
 }
 

@@ -145,6 +145,24 @@ __device__ __forceinline__ cplx<V> source_entry(const cplx<V>* __restrict__ A, i
         v.re = a.re * b.re + a.im * b.im;
         v.im = a.im * b.re - a.re * b.im;
         return v;
+    } else if constexpr (SRC == SRC_LOWRANK) {
+        // sum over the factor's columns j of U[k][j] conj(U[col][j]), in
+        // ascending j; the mirror entry (col, k) takes the same products in
+        // the same order, so the matrix is Hermitian bit for bit
+        const int rank = (int)(lda & 63);
+        const int64_t ld = lda >> 6;
+        const cplx<V>* a = A + (int64_t)k * ld;
+        const cplx<V>* b = A + (int64_t)col * ld;
+        cplx<V> v;
+        v.re = (V)0;
+        v.im = (V)0;
+#pragma unroll 4
+        for (int j = 0; j < rank; ++j) {
+            const cplx<V> u = a[j], w = b[j];
+            v.re += u.re * w.re + u.im * w.im;
+            v.im += u.im * w.re - u.re * w.im;
+        }
+        return v;
     } else {
         return A[(int64_t)k * lda + col];
     }

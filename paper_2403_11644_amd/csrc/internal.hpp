@@ -14,10 +14,15 @@ namespace ptd {
 // the dense matrix (row pitch lda).  Matrix-free inputs, whose few defining
 // values stay in cache: SRC_TOEPLITZ, A[r][c] = t[c - r + 2^n - 1] with t at
 // A; SRC_PURE, the density matrix of a pure state, A[r][c] = psi[r]
-// conj(psi[c]) with psi at A.
+// conj(psi[c]) with psi at A; SRC_LOWRANK, a mixed state U U^* given by its
+// 2^n x R factor U at A, A[r][c] = sum_j U[r][j] conj(U[c][j]), whose row
+// pitch and rank travel packed in the lda argument (lowrank_ld).
 constexpr int SRC_MATRIX = 0;
 constexpr int SRC_TOEPLITZ = 1;
 constexpr int SRC_PURE = 2;
+constexpr int SRC_LOWRANK = 3;
+constexpr int LOWRANK_MAX = 32;
+inline int64_t lowrank_ld(int64_t pitch, int rank) { return (pitch << 6) | (int64_t)rank; }
 
 // Dense decompose: coeff[x][z] (complex, or real when herm) for n in 1..16.
 // path: 0 = automatic, 1 = force the single-pass group kernel (n <= 10),
@@ -81,12 +86,15 @@ hipError_t fused_rec_c128_herm(int n, const void* coeff, void* A, int64_t lda, v
                                hipStream_t st);
 hipError_t launch_fused_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const void* coeff, void* A, int64_t lda,
                             void* ws, int la, hipStream_t st);
-// Matrix-free input (src: SRC_TOEPLITZ or SRC_PURE) given by its defining
-// vector: the single-pass group kernel (n <= 10).
-hipError_t launch_group_src(int n, ptd_dtype dt, bool herm, int src, const void* t, void* out, hipStream_t st);
+// Matrix-free input (src: SRC_TOEPLITZ, SRC_PURE or SRC_LOWRANK) given by
+// its defining vector or factor (ld: 0, or lowrank_ld for SRC_LOWRANK): the
+// single-pass group kernel (n <= 10).
+hipError_t launch_group_src(int n, ptd_dtype dt, bool herm, int src, const void* t, int64_t ld, void* out,
+                            hipStream_t st);
 // Matrix-free input for n = 11..14 (15 for complex64): one workgroup per
 // X-pattern, the row's transform in LDS (mfree.hip).
-hipError_t launch_mfree(int n, ptd_dtype dt, bool herm, int src, const void* t, void* out, hipStream_t st);
+hipError_t launch_mfree(int n, ptd_dtype dt, bool herm, int src, const void* t, int64_t ld, void* out,
+                        hipStream_t st);
 // Zero `count` uint32 words with a small kernel (capturable, unlike a memset node).
 hipError_t launch_zero_words(uint32_t* p, int count, hipStream_t st);
 // Plain 16-byte-per-lane device copy (bandwidth reference).

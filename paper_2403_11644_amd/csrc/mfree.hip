@@ -1,9 +1,10 @@
 // mfree.hip -- dense decomposition of a matrix-free input (a Toeplitz matrix
-// given by its defining entries, or the density matrix of a state vector)
+// given by its defining entries, or a density matrix given by a state vector
+// or a low-rank factor)
 // for n >= 11: one workgroup per X-pattern.
 //
 // A matrix-free source costs no HBM read: its defining vector (at most
-// 2^(n+1) complex values) stays in L2.  So the whole length-2^n transform of
+// 2^(n+1) complex values) or low-rank factor stays in L2.  So the whole length-2^n transform of
 // one X-pattern runs in one workgroup, out of LDS, and the output row is
 // written once with coalesced stores; the only HBM traffic is the output.
 // (The single-launch schedule for stored matrices exchanges partial
@@ -78,12 +79,13 @@ struct MfWrite {
 // consecutive positions, so the source reads of a wave stay within a few
 // cache lines
 template <class V, int LM, int NT, int SRC>
-__device__ __forceinline__ void mf_gather(const cplx<V>* __restrict__ src, int logn, uint32_t x, int kb, cplx<V>* lds)
+__device__ __forceinline__ void mf_gather(const cplx<V>* __restrict__ src, int64_t ld, int logn, uint32_t x, int kb,
+                                          cplx<V>* lds)
 {
 #pragma unroll 4
     for (int p = threadIdx.x; p < (1 << LM); p += NT) {
         const int k = kb + p;
-        lds[mf_slot(p)] = source_entry<V, SRC>(src, 0, logn, k, k ^ (int)x);
+        lds[mf_slot(p)] = source_entry<V, SRC>(src, ld, logn, k, k ^ (int)x);
     }
 }
 
@@ -123,21 +125,21 @@ __device__ __forceinline__ void mf_store(void* __restrict__ out, int logn, uint3
 }
 
 template <class V, int LOGN, bool REAL_OUT, int SRC>
-__global__ __launch_bounds__(mf_threads(LOGN)) void k_mfree_row(const cplx<V>* __restrict__ src,
+__global__ __launch_bounds__(mf_threads(LOGN)) void k_mfree_row(const cplx<V>* __restrict__ src, int64_t ld,
                                                                 void* __restrict__ out)
 {
     constexpr int NT = mf_threads(LOGN);
     __shared__ cplx<V> lds[mf_lds_elems(LOGN)];
     const uint32_t x = blockIdx.x;
     const V scale = exp2_neg<V>(LOGN);
-    mf_gather<V, LOGN, NT, SRC>(src, LOGN, x, 0, lds);
+    mf_gather<V, LOGN, NT, SRC>(src, ld, LOGN, x, 0, lds);
     __syncthreads();
     auto store = [&](int, int pos, V re, V im) { mf_store<V, REAL_OUT>(out, LOGN, x, (uint32_t)pos, re, im, scale); };
     mf_rounds<V, LOGN, NT, mf_rmax<V>(), 0>(lds, store);
 }
 
 template <class V, int LOGN, bool REAL_OUT, int SRC>
-__global__ __launch_bounds__(MF_HALF_THREADS) void k_mfree_halves(const cplx<V>* __restrict__ src,
+__global__ __launch_bounds__(MF_HALF_THREADS) void k_mfree_halves(const cplx<V>* __restrict__ src, int64_t ld,
                                                                   void* __restrict__ out)
 {
     constexpr int LH = LOGN - 1;
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(MF_HALF_THREADS) void k_mfree_halves(const cplx<V>*
 
     // the transform over bits 0 .. LH-1 of half h, left in LDS
     auto half = [&](int h) {
-        mf_gather<V, LH, NT, SRC>(src, LOGN, x, h << LH, lds);
+        mf_gather<V, LH, NT, SRC>(src, ld, LOGN, x, h << LH, lds);
         __syncthreads();
         mf_rounds<V, LH, NT, mf_rmax<V>(), 0>(lds, MfWrite<V>{lds});
         __syncthreads();
@@ -178,28 +180,29 @@ __global__ __launch_bounds__(MF_HALF_THREADS) void k_mfree_halves(const cplx<V>*
 }
 
 template <class V, bool REAL_OUT, int SRC>
-hipError_t mfree_t(int n, const void* src, void* out, hipStream_t st)
+hipError_t mfree_t(int n, const void* src, int64_t ld, void* out, hipStream_t st)
 {
     const dim3 grid(1u << n);
     const cplx<V>* s = (const cplx<V>*)src;
     switch (n) {
 #define PTD_ROW(NN)                                                                                         \
     case NN:                                                                                                \
-        hipLaunchKernelGGL((k_mfree_row<V, NN, REAL_OUT, SRC>), grid, dim3(mf_threads(NN)), 0, st, s, out); \
+        hipLaunchKernelGGL((k_mfree_row<V, NN, REAL_OUT, SRC>), grid, dim3(mf_threads(NN)), 0, st, s, ld, out); \
         break;
         PTD_ROW(11) PTD_ROW(12) PTD_ROW(13)
 #undef PTD_ROW
         case 14:
             if constexpr (sizeof(V) == 4)
-                hipLaunchKernelGGL((k_mfree_row<V, 14, REAL_OUT, SRC>), grid, dim3(mf_threads(14)), 0, st, s, out);
+                hipLaunchKernelGGL((k_mfree_row<V, 14, REAL_OUT, SRC>), grid, dim3(mf_threads(14)), 0, st, s, ld,
+                                   out);
             else
                 hipLaunchKernelGGL((k_mfree_halves<V, 14, REAL_OUT, SRC>), grid, dim3(MF_HALF_THREADS), 0, st, s,
-                                   out);
+                                   ld, out);
             break;
         case 15:
             if constexpr (sizeof(V) == 4) {
                 hipLaunchKernelGGL((k_mfree_halves<V, 15, REAL_OUT, SRC>), grid, dim3(MF_HALF_THREADS), 0, st, s,
-                                   out);
+                                   ld, out);
                 break;
             }
             return hipErrorInvalidValue;
@@ -210,20 +213,23 @@ hipError_t mfree_t(int n, const void* src, void* out, hipStream_t st)
 }
 
 template <class V, bool REAL_OUT>
-hipError_t mfree_src(int n, int src, const void* t, void* out, hipStream_t st)
+hipError_t mfree_src(int n, int src, const void* t, int64_t ld, void* out, hipStream_t st)
 {
-    if (src == SRC_TOEPLITZ) return mfree_t<V, REAL_OUT, SRC_TOEPLITZ>(n, t, out, st);
-    if (src == SRC_PURE) return mfree_t<V, REAL_OUT, SRC_PURE>(n, t, out, st);
+    if (src == SRC_TOEPLITZ) return mfree_t<V, REAL_OUT, SRC_TOEPLITZ>(n, t, ld, out, st);
+    if (src == SRC_PURE) return mfree_t<V, REAL_OUT, SRC_PURE>(n, t, ld, out, st);
+    if (src == SRC_LOWRANK) return mfree_t<V, REAL_OUT, SRC_LOWRANK>(n, t, ld, out, st);
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-hipError_t launch_mfree(int n, ptd_dtype dt, bool herm, int src, const void* t, void* out, hipStream_t st)
+hipError_t launch_mfree(int n, ptd_dtype dt, bool herm, int src, const void* t, int64_t ld, void* out,
+                        hipStream_t st)
 {
     if (dt == PTD_C128)
-        return herm ? mfree_src<double, true>(n, src, t, out, st) : mfree_src<double, false>(n, src, t, out, st);
-    return herm ? mfree_src<float, true>(n, src, t, out, st) : mfree_src<float, false>(n, src, t, out, st);
+        return herm ? mfree_src<double, true>(n, src, t, ld, out, st)
+                    : mfree_src<double, false>(n, src, t, ld, out, st);
+    return herm ? mfree_src<float, true>(n, src, t, ld, out, st) : mfree_src<float, false>(n, src, t, ld, out, st);
 }
 
 }  // namespace ptd

@@ -297,3 +297,15 @@ def test_toeplitz_argument_errors(lib):
     assert dec(12, api.C64, api.TOEPLITZ | api.DIAGONAL) == EUNSUP
     assert dec(12, api.C64, api.TOEPLITZ | api.COMPENSATED) == EUNSUP
     assert dec(3, api.C64, api.TOEPLITZ | api.COMPACT) == -1  # compact needs a structure
+    # low-rank factor: rank in 1..32, row pitch >= rank, one matrix-free kind per call
+    lr = lambda n, flags, s, lda: lib.pauli_decompose(n, api.C128, flags, s, big, lda, far, None, 0, None)
+    assert lr(8, api.LOW_RANK, 0, 4) == -1
+    assert lr(8, api.LOW_RANK, 33, 40) == -1
+    assert lr(8, api.LOW_RANK, 4, 3) == -1
+    assert lr(8, api.LOW_RANK, 4, (1 << 40) + 1) == -1
+    assert lr(8, api.LOW_RANK | api.PURE_STATE, 1, 1) == -1
+    assert lr(8, api.LOW_RANK | api.TOEPLITZ, 1, 1) == -1
+    assert lr(8, api.LOW_RANK | api.DIAGONAL, 2, 2) == EUNSUP
+    assert lr(15, api.LOW_RANK, 2, 2) == EUNSUP
+    assert lr(16, api.LOW_RANK, 2, 2) == EUNSUP
+    assert lib.ptd_workspace_bytes(14, api.C128, api.LOW_RANK, 2) == 0

@@ -577,3 +577,61 @@ def test_pure_state_basis_state(ptd):
     sign = 1.0 - 2.0 * (np.array([bin(v & k).count("1") for v in z]) & 1)
     np.testing.assert_array_equal(got[0], sign / N)
     assert np.all(got[1:] == 0)
+
+
+# --------------------------------------------------------------------------
+# matrix-free mixed-state input (PTD_LOW_RANK): A = U U^*
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n,R", [(1, 1), (3, 2), (6, 5), (10, 3), (11, 4), (12, 32), (13, 2), (14, 3)])
+@pytest.mark.parametrize("hermitian", [False, True])
+def test_mixed_state_expectations(ptd, oracle_mod, dt, n, R, hermitian):
+    """sum_j <u_j|P|u_j> / 2^n over the factor's columns: sampled against the
+    oracle on U U^* (n <= 12), real (imaginary parts exactly zero), and equal
+    within the bar to the sum of the columns' pure-state decompositions."""
+    import torch
+
+    N = 1 << n
+    U = synth.complex_normal((N, R), seed=800 + n, dtype=_np_dtype(dt))
+    Ud = to_dev(U)
+    got = ptd.decompose(Ud, low_rank=True, hermitian=hermitian)
+    if not hermitian:
+        assert float(got.imag.abs().max()) == 0.0
+    xs, zs = synth.sample_strings(n, 500, seed=17)
+    ix, iz = to_dev(xs.astype(np.int64)), to_dev(zs.astype(np.int64))
+    if n <= 12:
+        want = oracle_mod.coeffs(oracle_mod.mixed_density(U), xs, zs)
+        assert rel_err(to_host(got[ix, iz]), want.real if hermitian else want) <= TOL[dt]
+    acc = None
+    for j in range(min(R, 4)):
+        cj = ptd.decompose(Ud[:, j].contiguous(), pure_state=True, hermitian=True).to(torch.float64)
+        acc = cj if acc is None else acc + cj
+    if R <= 4:
+        ref = got if hermitian else got.real
+        assert rel_err(to_host(ref.to(torch.float64)), to_host(acc)) <= TOL[dt]
+    del got, acc
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n", [4, 9, 12, 14])
+def test_rank_one_is_the_pure_state(ptd, dt, n):
+    """A one-column factor forms each entry with the pure state's products
+    (plus an exact zero), so both calls agree bit for bit; and a factor with
+    a row pitch wider than its rank reads the same values."""
+    import torch
+
+    N = 1 << n
+    psi = synth.complex_normal(N, seed=820 + n, dtype=_np_dtype(dt))
+    pd = to_dev(psi)
+    a = ptd.decompose(pd[:, None], low_rank=True, hermitian=True)
+    b = ptd.decompose(pd, pure_state=True, hermitian=True)
+    assert bool(torch.equal(a, b))
+    wide = torch.zeros((N, 5), dtype=pd.dtype, device=pd.device)
+    wide[:, 1] = pd
+    wide[:, 2] = 2 * pd
+    c1 = ptd.decompose(wide[:, 1:3], low_rank=True)  # row pitch 5, rank 2
+    c2 = ptd.decompose(wide[:, 1:3].contiguous(), low_rank=True)
+    assert bool(torch.equal(c1, c2))
+    del a, b, c1, c2, wide
+    torch.cuda.empty_cache()
