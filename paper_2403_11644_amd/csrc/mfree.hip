@@ -14,17 +14,21 @@
 // LDS holds 2^m values of the row: m = n while 2^n values fit in 128 KiB
 // (n <= 13 complex128, n <= 14 complex64).  One size beyond (n = 14
 // complex128, n = 15 complex64) the workgroup transforms the two halves
-// k < 2^(n-1) and k >= 2^(n-1) one after the other, keeps the first half's
-// result in registers, and finishes with the butterfly over the top bit.
+// k < 2^(n-1) and k >= 2^(n-1) one after the other, runs each half's last
+// round into registers, and finishes there with the butterfly over the top
+// bit.
 //
 // Every path applies the radix-2 stages in ascending bit order with the same
 // additions as the kernels for stored matrices, so a matrix-free call gives
 // the bits of a dense call on the materialised matrix.
 //
-// Measured on MI355X at n = 14: 1.06 ms complex128 (4.0 TB/s of output
-// writes), 0.54 ms complex64.  Gathering with 8 or 16 loads in flight per
-// thread, 256 or 1024 threads, or radix 8 rounds changed it by -5% to +35%;
-// the single-launch schedule of stored matrices took 1.64 ms.
+// The kernels are bound by LDS traffic as much as by the output writes, so
+// the two-halves kernel keeps each half's last round in registers (the
+// halves join there without another LDS pass).  Measured on MI355X at
+// n = 14: 0.97 ms complex128 (4.4 TB/s of output writes), 0.54 ms
+// complex64; n = 15 complex64 2.11 ms.  Gathering with 8 or 16 loads in
+// flight per thread, 256 or 1024 threads, or radix 8 rounds changed it by
+// -5% to +35%; the single-launch schedule of stored matrices took 1.64 ms.
 #include "engine.hpp"
 #include "internal.hpp"
 
@@ -32,6 +36,9 @@ namespace ptd {
 
 namespace {
 
+// Widest round: radix 32 for complex64, radix 16 for complex128 (radix 32
+// measured no faster for the complex128 row at n = 13, and does not fit
+// beside the register-held half of the two-halves kernel).
 template <class V>
 constexpr int mf_rmax()
 {
@@ -46,11 +53,11 @@ constexpr int mf_threads(int logn)
 
 constexpr int MF_HALF_THREADS = 512;
 
-// LDS slot of row position p: one pad element after every 16, so that the
+// LDS slot of row position p: one pad element after every 32, so that the
 // first round (each thread owns 16 or 32 consecutive positions) reads with
-// lanes on different banks
-__device__ __forceinline__ int mf_slot(int p) { return p + (p >> 4); }
-constexpr int mf_lds_elems(int logm) { return (1 << logm) + (1 << (logm - 4)); }
+// lanes spread over the banks
+__device__ __forceinline__ int mf_slot(int p) { return p + (p >> 5); }
+constexpr int mf_lds_elems(int logm) { return (1 << logm) + (1 << (logm - 5)); }
 
 template <class V>
 struct MfRead {
@@ -105,6 +112,41 @@ __device__ __forceinline__ void mf_rounds(cplx<V>* lds, const Last& last)
     }
 }
 
+// Rounds over bits [B0, END) of the LDS row in place, then a barrier each.
+template <class V, int LM, int NT, int RMAX, int B0, int END>
+__device__ __forceinline__ void mf_rounds_to(cplx<V>* lds)
+{
+    if constexpr (B0 < END) {
+        constexpr int NB = (END - B0) < RMAX ? (END - B0) : RMAX;
+        wht_round<V, 0, LM, B0, NB, NT, false>(MfRead<V>{lds}, MfWrite<V>{lds});
+        __syncthreads();
+        mf_rounds_to<V, LM, NT, RMAX, B0 + NB, END>(lds);
+    }
+}
+
+// The last round, over bits [B0, LM), kept in registers: thread t holds
+// positions t + NT i + (m << B0) for i < ITER and m < R.
+template <class V, int LM, int NT, int B0>
+struct MfLast {
+    static constexpr int NB = LM - B0, R = 1 << NB, ITER = (1 << B0) / NT;
+    static_assert(ITER >= 1 && ITER * NT == (1 << B0), "whole items per thread");
+    V re[ITER][R], im[ITER][R];
+    __device__ __forceinline__ void run(const cplx<V>* lds)
+    {
+#pragma unroll
+        for (int i = 0; i < ITER; ++i) {
+            const int base = (int)threadIdx.x + NT * i;
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const cplx<V> v = lds[mf_slot(base + (m << B0))];
+                re[i][m] = v.re;
+                im[i][m] = v.im;
+            }
+            wht_reg<V, NB>(re[i], im[i]);
+        }
+    }
+};
+
 template <class V, bool REAL_OUT>
 __device__ __forceinline__ void mf_store(void* __restrict__ out, int logn, uint32_t x, uint32_t z, V re, V im,
                                          V scale)
@@ -144,38 +186,36 @@ __global__ __launch_bounds__(MF_HALF_THREADS) void k_mfree_halves(const cplx<V>*
 {
     constexpr int LH = LOGN - 1;
     constexpr int NT = MF_HALF_THREADS;
-    constexpr int J = (1 << LH) / NT;  // positions per thread in the final butterfly
+    constexpr int RM = mf_rmax<V>();
+    constexpr int LB0 = ((LH - 1) / RM) * RM;  // first bit of the last round
     __shared__ cplx<V> lds[mf_lds_elems(LH)];
     const uint32_t x = blockIdx.x;
     const int t = threadIdx.x;
-    V w0r[J], w0i[J];
 
-    // the transform over bits 0 .. LH-1 of half h, left in LDS
-    auto half = [&](int h) {
+    // the transform over bits 0 .. LH-1 of half h: the rounds below LB0 in
+    // LDS, the last one into registers
+    auto half = [&](int h, MfLast<V, LH, NT, LB0>& r) {
         mf_gather<V, LH, NT, SRC>(src, ld, LOGN, x, h << LH, lds);
         __syncthreads();
-        mf_rounds<V, LH, NT, mf_rmax<V>(), 0>(lds, MfWrite<V>{lds});
-        __syncthreads();
+        mf_rounds_to<V, LH, NT, RM, 0, LB0>(lds);
+        r.run(lds);
+        __syncthreads();  // every thread has its values before LDS is reused
     };
-
-    half(0);
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const cplx<V> v = lds[mf_slot(t + NT * j)];
-        w0r[j] = v.re;
-        w0i[j] = v.im;
-    }
-    __syncthreads();  // every thread has its values before LDS is reused
-    half(1);
+    MfLast<V, LH, NT, LB0> w0, w1;
+    half(0, w0);
+    half(1, w1);
 
     // the top bit: z and z + 2^LH from the two halves' values at z
     const V scale = exp2_neg<V>(LOGN);
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const uint32_t z = (uint32_t)(t + NT * j);
-        const cplx<V> v = lds[mf_slot((int)z)];
-        mf_store<V, REAL_OUT>(out, LOGN, x, z, w0r[j] + v.re, w0i[j] + v.im, scale);
-        mf_store<V, REAL_OUT>(out, LOGN, x, z | (1u << LH), w0r[j] - v.re, w0i[j] - v.im, scale);
+    for (int i = 0; i < w0.ITER; ++i) {
+#pragma unroll
+        for (int m = 0; m < w0.R; ++m) {
+            const uint32_t z = (uint32_t)(t + NT * i + (m << LB0));
+            mf_store<V, REAL_OUT>(out, LOGN, x, z, w0.re[i][m] + w1.re[i][m], w0.im[i][m] + w1.im[i][m], scale);
+            mf_store<V, REAL_OUT>(out, LOGN, x, z | (1u << LH), w0.re[i][m] - w1.re[i][m],
+                                  w0.im[i][m] - w1.im[i][m], scale);
+        }
     }
 }
 
