@@ -1,7 +1,8 @@
 """Plain CPU oracle for the Pauli decomposition -- TEST INFRASTRUCTURE ONLY.
 
-Only the test suite, the smoke check and the CPU-baseline leg of the
-benchmark may import this module.  The product library never does, and this
+Only the test suite, the smoke check and the benchmark (its CPU baseline,
+and the errors it states against the oracle on sampled strings) may import
+this module.  The product library never does, and this
 module imports nothing from the product package: the two share no code.
 
 Two independent evaluations of the definition (paper, Sec. II-A)
