@@ -349,7 +349,8 @@ def main() -> int:
         cpy = torch.empty_like(A)
         ms_copy = _time(lambda: L.ptd_debug_copy(api._ptr(A), api._ptr(cpy), A.numel() * 16, sh), 5, 2, stream)
         legs["copy_ceiling"] = {"GBps": round(2 * A.numel() * 16 / (ms_copy * 1e-3) / 1e9, 1),
-                                "frac_of_peak": round(2 * A.numel() * 16 / (ms_copy * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+                                "frac_of_peak": round(2 * A.numel() * 16 / (ms_copy * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                                "headline_frac_of_copy": round(ms_copy / ms128, 4)}
         del cpy
         torch.cuda.empty_cache()
     g = torch.Generator(device=dev)
@@ -437,7 +438,8 @@ def main() -> int:
             bd = torch.from_numpy(arr).to(dev)
             bout = torch.empty((cnt, N), dtype=torch.complex128, device=dev)
             us = _call_us(skip_call(bd, flags, s_, bout, N), 20, 5, stream)
-            band_legs[name] = {"s": s_, "nonempty_x": cnt, "from_bands_compact_us": round(us, 2)}
+            band_legs[name] = {"s": s_, "nonempty_x": cnt, "from_bands_compact_us": round(us, 2),
+                               "computed_GCoeff_s": round(cnt * N / us / 1e3, 2)}
             if s_ == 8:
                 fl = api.BANDED | api.COMPACT
                 us_dc = _call_us(skip_call(A, fl, 8, bout, N), 20, 5, stream)
@@ -601,14 +603,25 @@ def main() -> int:
 
         msm = _time(per_matrix, 2, 1, stream)
         plan.close()
+        del outs
+        # secondary: the same matrices with complex64 output (the general
+        # path: full read, complex coefficients)
+        bout_c = torch.empty(int(sizes.sum()), dtype=torch.complex64, device=dev)
+        plan_c = api.BatchPlan(bbuf, ns, offs, bout_c, offs, dtype_code=api.C64, hermitian=False)
+        msc = _time(plan_c.launch, 10, 3, stream)
+        plan_c.close()
+        del bout_c
         tot = float(sizes.sum())
         hb = sum(_herm_bytes(int(k), 8) for k in ns)
         legs["batched_4096_herm_c64"] = {"plan_ms": round(msp, 4), "default_plan_ms": round(msd, 4),
                                          "tuned_plans": tuned, "per_matrix_ms": round(msm, 4),
                                          "speedup": round(msm / msp, 2), "GCoeff_s": round(tot / msp / 1e6, 2),
                                          "path_hbm_frac": round(hb / (msp * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                                         "coefficients": int(tot)}
-        del bbuf, bout2, mats, outs
+                                         "coefficients": int(tot),
+                                         "complex_out_plan_ms": round(msc, 4),
+                                         "complex_out_hbm_frac": round(16 * tot / (msc * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                                                                       4)}
+        del bbuf, bout2, mats
         torch.cuda.empty_cache()
 
     # CPU baseline: the oracle on whole X-pattern rows of the same matrix
