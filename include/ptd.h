@@ -151,10 +151,15 @@ ptd_status ptd_nonempty_x(int n, unsigned flags, int s, uint32_t *xs_host);
  *
  *   n        number of qubits, 1..16
  *   dtype    element type of A (and of coeff unless PTD_HERMITIAN)
- *   flags    PTD_HERMITIAN | PTD_DIAGONAL | PTD_BANDED | PTD_BANDS_IN |
- *            PTD_COMPACT | PTD_COMPENSATED
- *   s        half-bandwidth for PTD_BANDED (>= 1), else ignored
- *   A, lda   input matrix (or bands with PTD_BANDS_IN), lda >= 2^n elements
+ *   flags    PTD_HERMITIAN | PTD_DIAGONAL | PTD_BANDED | PTD_ANTIDIAGONAL |
+ *            PTD_BANDS_IN | PTD_COMPACT | PTD_COMPENSATED, or one of the
+ *            matrix-free kinds PTD_TOEPLITZ | PTD_PURE_STATE | PTD_LOW_RANK
+ *            (with PTD_HERMITIAN at most)
+ *   s        half-bandwidth for PTD_BANDED (>= 1), the factor's rank for
+ *            PTD_LOW_RANK (1..32), else ignored
+ *   A, lda   input matrix (or bands with PTD_BANDS_IN), lda >= 2^n elements;
+ *            for a matrix-free kind its defining vector (lda ignored) or
+ *            low-rank factor (lda = its row pitch)
  *   coeff    output, 4^n values (complex, or real with PTD_HERMITIAN; with
  *            PTD_COMPACT ptd_num_nonempty_x * 2^n values); must not overlap A
  *   ws       workspace of ws_bytes >= ptd_workspace_bytes(...) (may be NULL
