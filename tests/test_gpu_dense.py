@@ -635,3 +635,25 @@ def test_rank_one_is_the_pure_state(ptd, dt, n):
     assert bool(torch.equal(c1, c2))
     del a, b, c1, c2, wide
     torch.cuda.empty_cache()
+
+
+def test_mixed_state_n15_complex64(ptd):
+    """n = 15 complex64 (two halves per row) for the state-vector sources: a
+    one-column factor gives the pure-state bits, and a two-column factor the
+    sum of its columns' expectation values within the bar."""
+    import torch
+
+    n, N = 15, 1 << 15
+    U = to_dev(synth.complex_normal((N, 2), seed=830, dtype=np.complex64))
+    p0 = ptd.decompose(U[:, 0].contiguous(), pure_state=True, hermitian=True)
+    a = ptd.decompose(U[:, :1], low_rank=True, hermitian=True)
+    assert bool(torch.equal(a, p0))
+    del a
+    p1 = ptd.decompose(U[:, 1].contiguous(), pure_state=True, hermitian=True)
+    both = ptd.decompose(U, low_rank=True, hermitian=True)
+    xs, zs = synth.sample_strings(n, 4000, seed=19)
+    ix, iz = to_dev(xs.astype(np.int64)), to_dev(zs.astype(np.int64))
+    want = p0[ix, iz].double() + p1[ix, iz].double()
+    assert rel_err(to_host(both[ix, iz].double()), to_host(want)) <= TOL["c64"]
+    del p0, p1, both
+    torch.cuda.empty_cache()
