@@ -53,18 +53,28 @@ constexpr int mf_threads(int logn)
 
 constexpr int MF_HALF_THREADS = 512;
 
-// LDS slot of row position p: one pad element after every 32, so that the
-// first round (each thread owns 16 or 32 consecutive positions) reads with
-// lanes spread over the banks
-__device__ __forceinline__ int mf_slot(int p) { return p + (p >> 5); }
-constexpr int mf_lds_elems(int logm) { return (1 << logm) + (1 << (logm - 5)); }
+// LDS slot of row position p: one pad element after every 2^RMAX, the
+// positions one thread owns in the first round, so that its lanes read
+// conflict-free (32 complex64 lanes or 16 complex128 lanes fill the 64
+// banks once).  A pad after every 32 complex128 values measured two bank
+// conflict cycles per LDS instruction.
+template <class V>
+__device__ __forceinline__ int mf_slot(int p)
+{
+    return p + (p >> mf_rmax<V>());
+}
+template <class V>
+constexpr int mf_lds_elems(int logm)
+{
+    return (1 << logm) + (1 << (logm - mf_rmax<V>()));
+}
 
 template <class V>
 struct MfRead {
     cplx<V>* p;
     __device__ __forceinline__ void operator()(int, int pos, V& re, V& im) const
     {
-        const cplx<V> v = p[mf_slot(pos)];
+        const cplx<V> v = p[mf_slot<V>(pos)];
         re = v.re;
         im = v.im;
     }
@@ -78,7 +88,7 @@ struct MfWrite {
         cplx<V> v;
         v.re = re;
         v.im = im;
-        p[mf_slot(pos)] = v;
+        p[mf_slot<V>(pos)] = v;
     }
 };
 
@@ -92,7 +102,7 @@ __device__ __forceinline__ void mf_gather(const cplx<V>* __restrict__ src, int64
 #pragma unroll 4
     for (int p = threadIdx.x; p < (1 << LM); p += NT) {
         const int k = kb + p;
-        lds[mf_slot(p)] = source_entry<V, SRC>(src, ld, logn, k, k ^ (int)x);
+        lds[mf_slot<V>(p)] = source_entry<V, SRC>(src, ld, logn, k, k ^ (int)x);
     }
 }
 
@@ -138,7 +148,7 @@ struct MfLast {
             const int base = (int)threadIdx.x + NT * i;
 #pragma unroll
             for (int m = 0; m < R; ++m) {
-                const cplx<V> v = lds[mf_slot(base + (m << B0))];
+                const cplx<V> v = lds[mf_slot<V>(base + (m << B0))];
                 re[i][m] = v.re;
                 im[i][m] = v.im;
             }
@@ -171,7 +181,7 @@ __global__ __launch_bounds__(mf_threads(LOGN)) void k_mfree_row(const cplx<V>* _
                                                                 void* __restrict__ out)
 {
     constexpr int NT = mf_threads(LOGN);
-    __shared__ cplx<V> lds[mf_lds_elems(LOGN)];
+    __shared__ cplx<V> lds[mf_lds_elems<V>(LOGN)];
     const uint32_t x = blockIdx.x;
     const V scale = exp2_neg<V>(LOGN);
     mf_gather<V, LOGN, NT, SRC>(src, ld, LOGN, x, 0, lds);
@@ -188,7 +198,7 @@ __global__ __launch_bounds__(MF_HALF_THREADS) void k_mfree_halves(const cplx<V>*
     constexpr int NT = MF_HALF_THREADS;
     constexpr int RM = mf_rmax<V>();
     constexpr int LB0 = ((LH - 1) / RM) * RM;  // first bit of the last round
-    __shared__ cplx<V> lds[mf_lds_elems(LH)];
+    __shared__ cplx<V> lds[mf_lds_elems<V>(LH)];
     const uint32_t x = blockIdx.x;
     const int t = threadIdx.x;
 
