@@ -9,7 +9,7 @@ from .api import (  # noqa: F401
     block_diagonal, decompose, decompose_batched, decompose_sparse, direct_sum, hermitian_augment, lcu_amplitudes,
     linear_combination, nonempty_x, num_nonempty_x, pad_to_power_of_two, parseval, reconstruct,
 )
-from .labels import flat_index, index, label  # noqa: F401
+from .labels import flat_index, index, label, to_dict  # noqa: F401
 from .host_tree import host_tree_decompose  # noqa: F401
 from .autograd import PauliDecompose, PauliReconstruct, pauli_decompose, pauli_reconstruct  # noqa: F401
 from . import tuning  # noqa: F401

@@ -35,3 +35,34 @@ def index(lab: str) -> tuple[int, int]:
 def flat_index(lab: str) -> int:
     x, z = index(lab)
     return (x << len(lab)) | z
+
+
+def to_dict(coeff, tol: float = 0.0, xs=None) -> dict:
+    """The decomposition as {label: coefficient} over the strings whose
+    coefficient exceeds tol in magnitude (the paper keeps its output as such a
+    list of strings and values, Algorithm 2).  coeff is a dense (2^n, 2^n)
+    array (numpy, or a torch tensor on any device, copied to the host), or a
+    compact one of len(xs) rows whose X-patterns are xs.  Host-side
+    formatting of a result, not part of the computation."""
+    import numpy as np
+
+    if hasattr(coeff, "detach"):
+        coeff = coeff.detach().cpu().numpy()
+    c = np.asarray(coeff)
+    if c.ndim != 2:
+        raise ValueError("coeff must be 2-D")
+    N = c.shape[1]
+    if N < 2 or N & (N - 1):
+        raise ValueError("rows must have 2^n entries")
+    n = N.bit_length() - 1
+    rows = np.arange(c.shape[0]) if xs is None else np.asarray(xs, dtype=np.int64)
+    if xs is None and c.shape[0] != N:
+        raise ValueError("a compact array needs its X-patterns xs")
+    if len(rows) != c.shape[0]:
+        raise ValueError("xs must list one X-pattern per row")
+    r, z = np.nonzero(np.abs(c) > tol)
+    out = {}
+    for i, zz in zip(r.tolist(), z.tolist()):
+        v = c[i, zz]
+        out[label(int(rows[i]), int(zz), n)] = complex(v) if np.iscomplexobj(c) else float(v)
+    return out

@@ -309,3 +309,23 @@ def test_toeplitz_argument_errors(lib):
     assert lr(15, api.LOW_RANK, 2, 2) == EUNSUP
     assert lr(16, api.LOW_RANK, 2, 2) == EUNSUP
     assert lib.ptd_workspace_bytes(14, api.C128, api.LOW_RANK, 2) == 0
+
+
+def test_to_dict():
+    """{label: coefficient} view of dense and compact arrays."""
+    import numpy as np
+
+    from paper_2403_11644_amd import labels
+
+    c = np.zeros((4, 4), dtype=np.complex128)
+    c[0, 0] = 0.5           # II
+    c[1, 3] = -0.25j        # Y on qubit 0, Z on qubit 1: 'ZY'
+    c[3, 0] = 1e-20         # below the tolerance
+    d = labels.to_dict(c, tol=1e-12)
+    assert d == {"II": 0.5, labels.label(1, 3, 2): -0.25j}
+    assert labels.label(1, 3, 2) == "ZY"
+    # compact rows with their X-patterns; real (Hermitian) arrays give floats
+    r = np.array([[0.0, 2.0], [0.0, -1.0]])
+    assert labels.to_dict(r, xs=[0, 1]) == {"Z": 2.0, "Y": -1.0}
+    with pytest.raises(ValueError):
+        labels.to_dict(np.zeros((1, 4)))  # compact without xs
