@@ -166,3 +166,14 @@ def test_argument_errors(ht):
         ht.host_tree_decompose(np.zeros((6, 6), dtype=np.complex128))
     with pytest.raises(ValueError):
         ht.host_tree_decompose(np.zeros((8, 8), dtype=np.complex64))
+
+
+def test_default_thread_count_and_many_trees(ht, oracle_mod):
+    # threads=0 takes one per hardware thread; a forest much larger than the
+    # thread count still covers every string once
+    n = 6
+    A = synth.dense(n, seed=360)
+    got, ops = ht.host_tree_decompose(A, split=5, threads=0)
+    assert np.abs(got - oracle_mod.decompose(A)).max() <= 1e-14 * np.abs(got).max()
+    # 4^5 trees, each replaying its path: more operations than the single walk
+    assert 7 * ops > 9 + 5 * 8 ** n
