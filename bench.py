@@ -47,6 +47,31 @@ def _cpu_model() -> str:
     return "unknown"
 
 
+def _environment() -> dict:
+    """Provenance of a bench line: ROCm and torch versions, the device name,
+    the host's usable cores and the commit, where available."""
+    import torch
+
+    env = {"torch": torch.__version__, "hip": getattr(torch.version, "hip", None)}
+    try:
+        env["rocm"] = open("/opt/rocm/.info/version").read().strip()
+    except OSError:
+        env["rocm"] = None
+    try:
+        env["device"] = torch.cuda.get_device_name(0)
+    except Exception:
+        env["device"] = None
+    env["host_cores"] = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    try:
+        import subprocess
+
+        env["commit"] = subprocess.run(["git", "-C", ROOT, "rev-parse", "--short", "HEAD"], capture_output=True,
+                                       text=True, timeout=10).stdout.strip() or None
+    except Exception:
+        env["commit"] = None
+    return env
+
+
 def _kernel_hash() -> str:
     """Hash of the device sources (*.hip, *.hpp); host-only C++ is left out."""
     h = hashlib.sha256()
@@ -711,6 +736,7 @@ def main() -> int:
         "input_gen_s": round(gen_s, 1),
         "transfers": transfers,
         "kernel_hash": _kernel_hash(),
+        "environment": _environment(),
     }
     print(json.dumps(line), flush=True)
     return 0
