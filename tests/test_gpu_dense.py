@@ -657,3 +657,39 @@ def test_mixed_state_n15_complex64(ptd):
     assert rel_err(to_host(both[ix, iz].double()), to_host(want)) <= TOL["c64"]
     del p0, p1, both
     torch.cuda.empty_cache()
+
+
+# --------------------------------------------------------------------------
+# the n = 13 Hermitian workload against the full oracle (every coefficient;
+# about 50 s of host time each on 16 cores)
+
+@pytest.mark.slow
+def test_n13_hermitian_every_coefficient(ptd, oracle_mod):
+    n = 13
+    A = synth.hermitian(n, seed=0)
+    Ad = to_dev(A)
+    real = to_host(ptd.decompose(Ad, hermitian=True))
+    full = to_host(ptd.decompose(Ad))
+    del Ad
+    want = oracle_mod.decompose(A)
+    assert rel_err(real, want.real) <= 1e-12
+    assert rel_err(full, want) <= 1e-12
+    assert np.all(full.imag == 0.0)
+
+
+@pytest.mark.slow
+def test_n13_gaussian_integer_every_coefficient(ptd, oracle_mod):
+    """2^n c_P as exact int64 for all 4^13 strings, through the complex128 and
+    complex64 Hermitian paths."""
+    import torch
+
+    n = 13
+    re, im = synth.gaussian_int_hermitian(n, seed=1)
+    Ad = to_dev(synth.int_to_complex(re, im, np.complex128))
+    g128 = to_host(ptd.decompose(Ad, hermitian=True)) * (1 << n)
+    g64 = to_host(ptd.decompose(Ad.to(torch.complex64), hermitian=True)).astype(np.float64) * (1 << n)
+    del Ad
+    cre, cim = oracle_mod.decompose_int(re, im)
+    assert np.all(cim == 0)
+    np.testing.assert_array_equal(g128, cre.astype(np.float64))
+    np.testing.assert_array_equal(g64, cre.astype(np.float64))
