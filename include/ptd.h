@@ -187,6 +187,23 @@ ptd_status pauli_reconstruct(int n, ptd_dtype dtype, unsigned flags, const void 
                              int64_t lda, void *ws, size_t ws_bytes, ptd_stream stream);
 
 /*
+ * ptd_workspace_status: did the last pauli_decompose / pauli_reconstruct
+ * that used this workspace complete its exchange?  The one-launch schedules
+ * (dense n = 11..15 decomposition, n = 11..14 reconstruction) pass partial
+ * transforms between workgroups and wait for them with bounded polls.  A
+ * wait that gives up (about 0.2 s, which needs another process or a device
+ * fault to starve the launch) sets an error word in the workspace, and the
+ * affected coefficients (or entries of A) are written as NaN, never as
+ * finite wrong values.  This call copies that word to the host on `stream`
+ * and synchronises the stream: PTD_OK if clear, PTD_EHIP (with
+ * ptd_last_hip_error() = hipErrorLaunchTimeOut) if a wait gave up.  The
+ * word is cleared by the next call that uses the workspace.  ws may be NULL
+ * when ws_bytes is 0 (such calls never wait): PTD_OK.  PTD_EINVAL when
+ * ws_bytes is nonzero but smaller than one workspace header (128 bytes).
+ */
+ptd_status ptd_workspace_status(const void *ws, size_t ws_bytes, ptd_stream stream);
+
+/*
  * Batched decomposition: `count` matrices of uneven size in one persistent
  * launch whose workgroups take (matrix, X-pattern group) items from an
  * atomic queue, largest matrices first.  Every n_i must lie in 1..10 (one

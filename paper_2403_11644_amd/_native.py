@@ -31,6 +31,7 @@ SIGNATURES = {
     "ptd_nonempty_x": (I, [I, U, I, P]),
     "pauli_decompose": (I, [I, I, U, I, P, I64, P, P, SZ, P]),
     "pauli_reconstruct": (I, [I, I, U, P, P, I64, P, SZ, P]),
+    "ptd_workspace_status": (I, [P, SZ, P]),
     "ptd_reduce_workspace_bytes": (SZ, []),
     "ptd_parseval_residual": (I, [I, I, U, P, I64, P, P, P, SZ, P]),
     "ptd_batched_workspace_bytes": (SZ, [I, I, P]),
@@ -61,6 +62,8 @@ SIGNATURES = {
     "ptd_debug_decompose_stage": (I, [I, I, U, P, I64, P, I, P]),
     "ptd_debug_decompose_fused": (I, [I, I, U, P, I64, P, P, SZ, I, I, P]),
     "ptd_debug_copy": (I, [P, P, SZ, P]),
+    "ptd_debug_wait_test_mode": (None, [I]),
+    "ptd_debug_xcc_ids": (I, [P, P]),
 }
 
 

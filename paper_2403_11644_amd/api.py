@@ -7,6 +7,7 @@ the computation runs in the library's HIP kernels.
 from __future__ import annotations
 
 import ctypes
+import functools
 
 import torch
 
@@ -54,6 +55,25 @@ def _stream_handle(device: torch.device, stream) -> ctypes.c_void_p:
     if stream is None:
         stream = torch.cuda.current_stream(device)
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _on_stream(fn):
+    """Run a wrapper with ``stream=`` as torch's current stream.
+
+    The workspace and the outputs a wrapper allocates then belong to the
+    stream the kernels run on: when the workspace is freed on return, the
+    caching allocator hands its block only to later work on that same stream,
+    which runs after these kernels.
+    """
+
+    @functools.wraps(fn)
+    def wrapper(*args, stream=None, **kwargs):
+        if stream is None:
+            return fn(*args, stream=None, **kwargs)
+        with torch.cuda.stream(stream):
+            return fn(*args, stream=stream, **kwargs)
+
+    return wrapper
 
 
 def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
@@ -109,10 +129,11 @@ def nonempty_x(n: int, structure: str | None = None, s: int = 0) -> list[int]:
     return buf.tolist()
 
 
+@_on_stream
 def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None = None, s: int | None = None,
               bands: bool = False, compact: bool = False, compensated: bool = False, pad: bool = False,
               toeplitz: bool = False, pure_state: bool = False, low_rank: bool = False,
-              out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+              out: torch.Tensor | None = None, check: bool = False, stream=None) -> torch.Tensor:
     """Pauli coefficients of A, as a (2^n, 2^n) tensor c[x, z].
 
     hermitian   A == A^*: return the (real) coefficients as float64/float32.
@@ -131,6 +152,10 @@ def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None
     low_rank    A is a 2^n x r factor U (r <= 32, rows contiguous) and the
                 matrix is the mixed state U U^* (matrix-free): the
                 coefficients are sum_j <u_j|P|u_j> / 2^n over its columns.
+    check       wait for the call and raise if the one-launch schedule's
+                exchange did not complete (its coefficients are then NaN;
+                see ptd_workspace_status).  Off by default: the call stays
+                asynchronous.
     """
     _require_device(A, "A")
     code = _dtype_code(A.dtype)
@@ -215,17 +240,23 @@ def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None
     L = _native.lib()
     wsb = L.ptd_workspace_bytes(n, code, flags, sv)
     ws = torch.empty(wsb, dtype=torch.uint8, device=A.device) if wsb else None
+    sh = _stream_handle(A.device, stream)
     st = L.pauli_decompose(n, code, flags, sv, _ptr(A), lda, _ptr(out), _ptr(ws) if ws is not None else None,
-                           wsb, _stream_handle(A.device, stream))
+                           wsb, sh)
     _native.check(st, "pauli_decompose")
+    if check:
+        _native.check(L.ptd_workspace_status(_ptr(ws) if ws is not None else None, wsb, sh), "pauli_decompose")
     return out
 
 
+@_on_stream
 def reconstruct(c: torch.Tensor, *, hermitian: bool = False, adjoint: bool = False, dtype: torch.dtype | None = None,
-                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+                out: torch.Tensor | None = None, check: bool = False, stream=None) -> torch.Tensor:
     """A = sum_P c_P P from dense coefficients c[x, z] (adjoint: times 2^-n).
 
     With hermitian=True, c is real (float64/float32) and A is Hermitian.
+    check: wait and raise if the one-launch schedule's exchange did not
+    complete (as for decompose).
     """
     _require_device(c, "c")
     if hermitian:
@@ -250,12 +281,16 @@ def reconstruct(c: torch.Tensor, *, hermitian: bool = False, adjoint: bool = Fal
     L = _native.lib()
     wsb = L.ptd_reconstruct_workspace_bytes(n, code, flags)
     ws = torch.empty(wsb, dtype=torch.uint8, device=c.device) if wsb else None
+    sh = _stream_handle(c.device, stream)
     st = L.pauli_reconstruct(n, code, flags, _ptr(c), _ptr(out), out.stride(0),
-                             _ptr(ws) if ws is not None else None, wsb, _stream_handle(c.device, stream))
+                             _ptr(ws) if ws is not None else None, wsb, sh)
     _native.check(st, "pauli_reconstruct")
+    if check:
+        _native.check(L.ptd_workspace_status(_ptr(ws) if ws is not None else None, wsb, sh), "pauli_reconstruct")
     return out
 
 
+@_on_stream
 def parseval(A: torch.Tensor, c: torch.Tensor, *, hermitian: bool = False, stream=None):
     """(||A||_F^2, 2^n sum|c|^2, relative residual), reduced in float64 on the GPU."""
     import numpy as np
@@ -291,6 +326,7 @@ def _check_out(out, shape, dtype, device):
     return out
 
 
+@_on_stream
 def block_diagonal(blocks, *, compact: bool = False, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Coefficients of diag(A_0, ..., A_{2^m - 1}) from those of its blocks.
 
@@ -314,6 +350,7 @@ def block_diagonal(blocks, *, compact: bool = False, out: torch.Tensor | None = 
     return out
 
 
+@_on_stream
 def direct_sum(ca: torch.Tensor, cb: torch.Tensor, *, compact: bool = False, out: torch.Tensor | None = None,
                stream=None) -> torch.Tensor:
     """Coefficients of A (+) B = [[A, 0], [0, B]] from those of A and B."""
@@ -329,6 +366,7 @@ def direct_sum(ca: torch.Tensor, cb: torch.Tensor, *, compact: bool = False, out
     return out
 
 
+@_on_stream
 def hermitian_augment(c: torch.Tensor, *, compact: bool = False, out: torch.Tensor | None = None,
                       stream=None) -> torch.Tensor:
     """Real coefficients of [[0, A^H], [A, 0]] on n + 1 qubits from those of A:
@@ -344,6 +382,7 @@ def hermitian_augment(c: torch.Tensor, *, compact: bool = False, out: torch.Tens
     return out
 
 
+@_on_stream
 def linear_combination(mu, ca: torch.Tensor, cb: torch.Tensor, *, out: torch.Tensor | None = None,
                        stream=None) -> torch.Tensor:
     """Coefficients of mu A + B: mu * ca + cb elementwise (out may be ca or cb)."""
@@ -359,6 +398,7 @@ def linear_combination(mu, ca: torch.Tensor, cb: torch.Tensor, *, out: torch.Ten
     return out
 
 
+@_on_stream
 def decompose_sparse(rows: torch.Tensor, cols: torch.Tensor, vals: torch.Tensor, n: int, *, compact: bool = False,
                      out: torch.Tensor | None = None, stream=None):
     """Coefficients of a sparse 2^n x 2^n matrix given by coordinate entries
@@ -400,6 +440,7 @@ def decompose_sparse(rows: torch.Tensor, cols: torch.Tensor, vals: torch.Tensor,
     return out, xs[:count].to(torch.int64)
 
 
+@_on_stream
 def lcu_amplitudes(c: torch.Tensor, *, hermitian: bool = False, out: torch.Tensor | None = None, stream=None):
     """Amplitudes sqrt(|c_P| / lambda) of the ancilla state that prepares a
     block-encoding by a linear combination of the strings, and lambda =
@@ -488,6 +529,7 @@ def _out_layout(ns, odt, device):
     return buf, offs, views
 
 
+@_on_stream
 def decompose_batched(mats, *, hermitian: bool = False, stream=None):
     """Decompose a list of square GPU matrices (n <= 10 each) in one launch.
 

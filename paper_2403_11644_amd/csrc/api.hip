@@ -29,6 +29,36 @@ ptd_status hip_status(hipError_t e)
 
 bool valid_dtype(ptd_dtype dt) { return dt == PTD_C128 || dt == PTD_C64; }
 
+// Do the byte ranges [a, a + na) and [b, b + nb) meet?
+bool overlap(const void* a, size_t na, const void* b, size_t nb)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+size_t elem_bytes(ptd_dtype dt) { return dt == PTD_C128 ? 16 : 8; }
+
+// Bytes of a row-major array of `rows` rows of `cols` elements at pitch ld.
+size_t span_bytes(int64_t rows, int64_t cols, int64_t ld, size_t eb)
+{
+    return rows < 1 ? 0 : (size_t)((rows - 1) * ld + cols) * eb;
+}
+
+// Bytes pauli_decompose reads from A for these arguments (flags checked).
+size_t decompose_in_bytes(int n, ptd_dtype dt, unsigned flags, int s, int64_t lda)
+{
+    const int64_t N = (int64_t)1 << n;
+    const size_t eb = elem_bytes(dt);
+    if (flags & PTD_TOEPLITZ) return (size_t)(2 * N - 1) * eb;
+    if (flags & PTD_PURE_STATE) return (size_t)N * eb;
+    if (flags & PTD_LOW_RANK) return span_bytes(N, s, lda, eb);
+    if (flags & PTD_BANDS_IN) {
+        const int64_t rows = (flags & PTD_BANDED) ? 2 * (int64_t)s + 1 : 1;
+        return span_bytes(rows, N, lda, eb);
+    }
+    return span_bytes(N, N, lda, eb);
+}
+
 // Structured-flag checks shared by the decompose entry points.
 ptd_status check_structure(int n, unsigned flags, int s)
 {
@@ -124,8 +154,14 @@ ptd_status ptd_nonempty_x(int n, unsigned flags, int s, uint32_t* xs_host)
     return PTD_OK;
 }
 
-ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const void* A, int64_t lda, void* coeff,
-                           void* ws, size_t ws_bytes, ptd_stream stream)
+}  // extern "C"
+
+namespace ptd {
+
+// Every argument check of pauli_decompose except those of the workspace:
+// PTD_OK, PTD_EINVAL or PTD_EUNSUP, with no HIP call.
+ptd_status decompose_check(int n, ptd_dtype dtype, unsigned flags, int s, const void* A, int64_t lda,
+                           const void* coeff)
 {
     if (n < 1 || n > 16 || !valid_dtype(dtype) || !A || !coeff) return PTD_EINVAL;
     if (flags & ~kAllFlags) return PTD_EINVAL;
@@ -140,27 +176,63 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
     if ((flags & PTD_LOW_RANK) && (s < 1 || s > ptd::LOWRANK_MAX || lda < s || lda > ((int64_t)1 << 40)))
         return PTD_EINVAL;
     if ((flags & PTD_COMPENSATED) && dtype != PTD_C64) return PTD_EUNSUP;
-    if (ws_bytes < ptd_workspace_bytes(n, dtype, flags, s)) return PTD_ENOSPC;
-    (void)ws;
-    if (A == coeff) return PTD_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
-    const bool herm = flags & PTD_HERMITIAN;
+    // A and coeff must be disjoint (the one-launch schedule keeps partial
+    // results in coeff while it still reads A)
+    const int rows = (flags & PTD_COMPACT) ? ptd_num_nonempty_x(n, flags, s) : (1 << n);
+    if (rows < 1) return PTD_EINVAL;
+    const size_t out_eb = (flags & PTD_HERMITIAN) ? elem_bytes(dtype) / 2 : elem_bytes(dtype);
+    if (overlap(A, decompose_in_bytes(n, dtype, flags, s, lda), coeff, ((size_t)rows << n) * out_eb))
+        return PTD_EINVAL;
     if (mfree) {
         if (flags & (kStructure | PTD_COMPENSATED)) return PTD_EUNSUP;
+        if (n > 15 || (n == 15 && dtype == PTD_C128)) return PTD_EUNSUP;
+    }
+    if ((flags & kStructure) && (flags & PTD_COMPENSATED)) return PTD_EUNSUP;
+    return PTD_OK;
+}
+
+ptd_status status_from_hip(hipError_t e) { return hip_status(e); }
+
+}  // namespace ptd
+
+namespace {
+
+// Bytes pauli_decompose writes to coeff (arguments already checked).
+size_t decompose_out_bytes(int n, ptd_dtype dtype, unsigned flags, int s)
+{
+    const int rows = (flags & PTD_COMPACT) ? ptd_num_nonempty_x(n, flags, s) : (1 << n);
+    const size_t out_eb = (flags & PTD_HERMITIAN) ? elem_bytes(dtype) / 2 : elem_bytes(dtype);
+    return ((size_t)rows << n) * out_eb;
+}
+
+}  // namespace
+
+extern "C" {
+
+ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const void* A, int64_t lda, void* coeff,
+                           void* ws, size_t ws_bytes, ptd_stream stream)
+{
+    const ptd_status chk = ptd::decompose_check(n, dtype, flags, s, A, lda, coeff);
+    if (chk != PTD_OK) return chk;
+    if (ws_bytes < ptd_workspace_bytes(n, dtype, flags, s)) return PTD_ENOSPC;
+    if (ws && ws_bytes &&
+        (overlap(ws, ws_bytes, A, decompose_in_bytes(n, dtype, flags, s, lda)) ||
+         overlap(ws, ws_bytes, coeff, decompose_out_bytes(n, dtype, flags, s))))
+        return PTD_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const bool herm = flags & PTD_HERMITIAN;
+    if (flags & kMatrixFree) {
         const int src = (flags & PTD_TOEPLITZ) ? ptd::SRC_TOEPLITZ
                         : (flags & PTD_PURE_STATE) ? ptd::SRC_PURE
                                                    : ptd::SRC_LOWRANK;
         const int64_t ld = src == ptd::SRC_LOWRANK ? ptd::lowrank_ld(lda, s) : 0;
         if (n <= 10) return hip_status(ptd::launch_group_src(n, dtype, herm, src, A, ld, coeff, st));
-        if (n > 15 || (n == 15 && dtype == PTD_C128)) return PTD_EUNSUP;
         return hip_status(ptd::launch_mfree(n, dtype, herm, src, A, ld, coeff, st));
     }
     if (flags & kStructure) {
-        if (flags & PTD_COMPENSATED) return PTD_EUNSUP;
         // s < 0 codes the anti-diagonal for the structured kernels
         const int se = (flags & PTD_ANTIDIAGONAL) ? -1 : (flags & PTD_DIAGONAL) ? 0 : s;
         const int count = ptd_num_nonempty_x(n, flags, s);
-        if (count < 1) return PTD_EINVAL;
         return hip_status(ptd::launch_structured(n, dtype, herm, flags & PTD_BANDS_IN, flags & PTD_COMPACT, se, count,
                                                  A, lda, coeff, st));
     }
@@ -186,7 +258,14 @@ ptd_status pauli_reconstruct(int n, ptd_dtype dtype, unsigned flags, const void*
     if (n < 1 || n > 16 || !valid_dtype(dtype) || !A || !coeff) return PTD_EINVAL;
     if (flags & ~(PTD_HERMITIAN | PTD_ADJOINT)) return PTD_EINVAL;
     if (lda < ((int64_t)1 << n)) return PTD_EINVAL;
-    if (A == coeff) return PTD_EINVAL;
+    {
+        const int64_t N = (int64_t)1 << n;
+        const size_t a_bytes = span_bytes(N, N, lda, elem_bytes(dtype));
+        const size_t c_bytes = ((size_t)N << n) * ((flags & PTD_HERMITIAN) ? elem_bytes(dtype) / 2 : elem_bytes(dtype));
+        if (overlap(A, a_bytes, coeff, c_bytes)) return PTD_EINVAL;
+        if (ws && ws_bytes && (overlap(ws, ws_bytes, A, a_bytes) || overlap(ws, ws_bytes, coeff, c_bytes)))
+            return PTD_EINVAL;
+    }
     const bool herm = flags & PTD_HERMITIAN, adj = flags & PTD_ADJOINT;
     if (use_fused_rec(n)) {
         if (!ws || ws_bytes < ptd_reconstruct_workspace_bytes(n, dtype, flags)) return PTD_ENOSPC;
@@ -195,6 +274,19 @@ ptd_status pauli_reconstruct(int n, ptd_dtype dtype, unsigned flags, const void*
         return hip_status(ptd::launch_fused_rec(n, dtype, herm, adj, coeff, A, lda, ws, la, (hipStream_t)stream));
     }
     return hip_status(ptd::launch_dense_rec(n, dtype, herm, adj, coeff, A, lda, 0, (hipStream_t)stream));
+}
+
+ptd_status ptd_workspace_status(const void* ws, size_t ws_bytes, ptd_stream stream)
+{
+    if (ws_bytes == 0) return PTD_OK;
+    if (!ws || ws_bytes < 32 * sizeof(uint32_t)) return PTD_EINVAL;
+    uint32_t word = 0;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(&word, (const uint32_t*)ws + ptd::FUSED_WS_ERR_WORD, sizeof(word),
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_status(e);
+    return word ? hip_status(hipErrorLaunchTimeOut) : PTD_OK;
 }
 
 size_t ptd_reduce_workspace_bytes(void) { return ptd::reduce_workspace_bytes(); }
@@ -214,14 +306,6 @@ ptd_status ptd_parseval_residual(int n, ptd_dtype dtype, unsigned flags, const v
 
 namespace {
 
-// Do the byte ranges [a, a + na) and [b, b + nb) meet?
-bool overlap(const void* a, size_t na, const void* b, size_t nb)
-{
-    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
-    return x < y + nb && y < x + na;
-}
-
-size_t elem_bytes(ptd_dtype dt) { return dt == PTD_C128 ? 16 : 8; }
 
 // Outputs whose zero rows are written with 16-byte stores.
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
@@ -497,6 +581,9 @@ ptd_status ptd_set_tuning(int n, ptd_dtype dtype, unsigned flags, int cfg, int l
     }
     if (!use_fused(n, dtype, flags)) return PTD_EINVAL;
     if (cfg < 0 || cfg > 31 || lookahead < 1 || lookahead > 64) return PTD_EINVAL;
+    // cfg 0 is the default; otherwise a shape (bits 0-1) must be named, and
+    // n = 15 is built with shape 1 only
+    if (cfg != 0 && ((cfg & 3) == 0 || (n == 15 && (cfg & 3) != 1))) return PTD_EINVAL;
     ptd::set_fused_tuning(n, dtype, flags & PTD_HERMITIAN, ptd::FusedTuning{cfg, lookahead});
     return PTD_OK;
 }
@@ -559,6 +646,18 @@ ptd_status ptd_debug_decompose_fused(int n, ptd_dtype dtype, unsigned flags, con
     return hip_status(ptd::launch_fused_fwd(n, dtype, flags & PTD_HERMITIAN, A, lda, coeff, ws, lookahead, cfg,
                                             (hipStream_t)stream));
 }
+
+// Test hook: the dies workgroups run on (bit i: HW_REG_XCC_ID == i was seen)
+// and the XCD count the one-launch schedules use.  Synchronises the device.
+ptd_status ptd_debug_xcc_ids(unsigned* mask_host, int* count_host)
+{
+    if (!mask_host || !count_host) return PTD_EINVAL;
+    return hip_status(ptd::probe_xcc_ids(mask_host, count_host));
+}
+
+// Test hook: while on, every bounded wait of the one-launch schedules gives
+// up after a few polls (the failure path of ptd_workspace_status).
+void ptd_debug_wait_test_mode(int on) { ptd::set_wait_test_mode(on != 0); }
 
 // Bandwidth reference: a plain 16-byte-per-lane device copy of `bytes` bytes.
 ptd_status ptd_debug_copy(const void* src, void* dst, size_t bytes, ptd_stream stream)

@@ -1,8 +1,25 @@
 // fused.hip -- host side of the single-launch dense schedule (fused.hpp):
 // device queries, workspace size, default setting and dtype dispatch.
+#include <atomic>
+
+#include "fused.hpp"
 #include "internal.hpp"
 
 namespace ptd {
+
+namespace {
+std::atomic<bool> g_wait_test{false};
+}  // namespace
+
+WaitLimits wait_limits()
+{
+    // about 0.2 s of polling; the test hook gives up after 16 polls with a
+    // target no producer count reaches
+    if (g_wait_test.load(std::memory_order_relaxed)) return WaitLimits{16u, 1u};
+    return WaitLimits{1u << 22, 0u};
+}
+
+void set_wait_test_mode(bool on) { g_wait_test.store(on, std::memory_order_relaxed); }
 
 namespace {
 
@@ -22,9 +39,13 @@ DevInfo device_info()
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
         cached.cus = cus;
-        // 32 compute units per XCD on MI355X; partitioned modes expose fewer
-        int x = cus / 32;
-        cached.xcds = x < 1 ? 1 : (x > 8 ? 8 : x);
+        // XCDs (accelerator complex dies) the runtime reports for this device
+        // (8 on MI355X; partitioned modes expose fewer).  Workgroups read
+        // their die from HW_REG_XCC_ID, which runs over 0 .. xcds-1 (checked
+        // by a probe kernel in the test suite).
+        int x = 0;
+        if (hipDeviceGetAttribute(&x, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || x < 1) x = 1;
+        cached.xcds = x > 16 ? 16 : x;
         cached_dev = dev;
     }
     return cached;
@@ -33,6 +54,14 @@ DevInfo device_info()
 __global__ void k_zero_words(uint32_t* __restrict__ p, int count)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+__device__ unsigned g_xcc_seen;
+
+// Every workgroup records the die it runs on.
+__global__ void k_xcc_probe()
+{
+    if (threadIdx.x == 0) atomicOr(&g_xcc_seen, 1u << fused::xcc_id());
 }
 
 __global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t count)
@@ -44,6 +73,19 @@ __global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst,
 }  // namespace
 
 int device_cu_count() { return device_info().cus; }
+
+hipError_t probe_xcc_ids(unsigned* mask, int* count)
+{
+    const unsigned zero = 0;
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_xcc_seen), &zero, sizeof(zero));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_xcc_probe, dim3(device_cu_count() * 8), dim3(64), 0, 0);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpyFromSymbol(mask, HIP_SYMBOL(g_xcc_seen), sizeof(unsigned));
+    *count = device_xcd_count();
+    return e;
+}
 int device_xcd_count() { return device_info().xcds; }
 
 hipError_t launch_zero_words(uint32_t* p, int count, hipStream_t st)

@@ -36,25 +36,27 @@
 // meets the workgroup barrier, and then bumps the group's counter with an
 // atomic; a consumer polls that counter with an atomic and then reads lines
 // that no CU of this launch has read before.  So no L2 write-back or
-// invalidation is needed.  Partial results that spill from L2 go to the
-// memory-side cache and are usually overwritten by the final values there.
+// invalidation is needed.
 //
 // Latency hiding comes from two resident workgroups per CU (512 threads,
 // 64 KiB of LDS each).  Cache policies are options (POL bits): non-temporal
 // gathers of A, non-temporal final stores, non-temporal phase-2 loads of the
 // partial results (each is read once, then overwritten).
 //
-// Measured on MI355X: the L2 (4 MiB per XCD) does keep written lines for a
-// later read, but a group's partial band (one 128-byte segment per row, 2 MiB
-// at n = 14) is evicted by the next group's gathers and partial stores
-// before phase 2 reads it.  So every partial line is written back and read
-// again through the memory side, and the launch moves about four times the
-// matrix size across the L2 boundary instead of the two of a pure copy.
+// Measured on MI355X: every store crosses the L2 boundary (a region
+// written, read back and overwritten by one workgroup moves twice its size
+// out of L2 and its size back in), and reads from the memory-side cache
+// come no faster than from HBM.  So the partial band costs one extra write
+// and one extra read of the output size at the L2 boundary whatever the
+// schedule, and the launch runs near that boundary's throughput.
 //
 // Progress: a phase-2 item only waits for phase-1 items that precede it in
 // the same queue; those were taken by running workgroups, which never wait
 // before publishing their own completions, so every wait ends.  The poll is
-// bounded anyway (error flag in the workspace).  If the hardware put no
+// bounded anyway: a wait that gives up sets the workspace error word
+// (reported by ptd_workspace_status) and its item stores NaN in place of
+// every value it would have written, so an incomplete exchange can never
+// yield finite coefficients.  If the hardware put no
 // workgroup on some XCD, the last workgroup to finish runs that XCD's
 // untouched queue by itself.
 #pragma once
@@ -68,8 +70,28 @@ namespace fused {
 // workspace layout (uint32 words)
 constexpr int WS_HEAD = 0;    // [16] queue heads
 constexpr int WS_DONE = 16;   // finished workgroups
-constexpr int WS_ERR = 17;    // nonzero: a bounded wait ran out
+constexpr int WS_ERR = FUSED_WS_ERR_WORD;  // nonzero: a bounded wait ran out
 constexpr int WS_GROUP = 32;  // [num groups] phase-1 completions per group
+
+// Bounded poll of a group counter by one thread: true once ws[word] >= need.
+// Gives up (false) after wl.spins polls, or at once when another wait of the
+// launch has already given up; a give-up sets the error word WS_ERR, which
+// ptd_workspace_status reports.  wl.extra raises the target above what the
+// producers can reach: a test hook that makes every wait give up.
+__device__ __forceinline__ bool bounded_wait(uint32_t* __restrict__ ws, int word, uint32_t need, WaitLimits wl)
+{
+    const uint32_t target = need + wl.extra;
+    uint32_t spins = 0;
+    while (__hip_atomic_fetch_add(ws + word, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > wl.spins ||
+            ((spins & 255) == 0 && __hip_atomic_load(ws + WS_ERR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
+            __hip_atomic_store(ws + WS_ERR, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+    return true;
+}
 
 // cache-policy bits
 constexpr int POL_NT_GATHER = 1;
@@ -319,7 +341,7 @@ __device__ __forceinline__ V swap_halves(V v)
 }
 
 template <class V, class S, bool HERM, int POL>
-__device__ __forceinline__ void phase2(void* __restrict__ out, int g, int sub, cplx<V>* lds)
+__device__ __forceinline__ void phase2(void* __restrict__ out, int g, int sub, cplx<V>* lds, bool poison)
 {
     constexpr int KAP = S::KAP, NB2 = S::NB2;
     constexpr int N = 1 << S::LOGN;
@@ -327,7 +349,9 @@ __device__ __forceinline__ void phase2(void* __restrict__ out, int g, int sub, c
     const int r = sub / S::IPR;
     const int zl0 = (sub % S::IPR) * S::ZB;
     const uint32_t x = ((uint32_t)g << S::LOGT) | (uint32_t)r;
-    const V scale = exp2_neg<V>(S::LOGN);
+    // a group whose partial results never all arrived: every value of the
+    // item becomes NaN (the scale is multiplied into every stored value)
+    const V scale = poison ? __builtin_nan("") : exp2_neg<V>(S::LOGN);
     const int64_t rowo = (int64_t)x * N;
     if constexpr (S::STASH) {
         // 32 values per position: the first 16 take a 16-point transform and
@@ -426,7 +450,7 @@ template <class V, class S, bool HERM, int POL>
 // at least 4 waves per SIMD: two 512-thread workgroups fit on one CU
 __global__ __launch_bounds__(S::NT, 4) void k_fused_fwd(const cplx<V>* __restrict__ A, int64_t lda,
                                                      void* __restrict__ out, uint32_t* __restrict__ ws, int Q,
-                                                     int LA, uint32_t spin_limit)
+                                                     int LA, WaitLimits wl)
 {
     constexpr int NP1 = S::NP1, NP2 = S::NP2, NG = S::NG;
     __shared__ cplx<V> lds[(1 << S::LOGT) * ((1 << S::KAP) + 1)];
@@ -441,23 +465,11 @@ __global__ __launch_bounds__(S::NT, 4) void k_fused_fwd(const cplx<V>* __restric
         if (threadIdx.x == 0)
             __hip_atomic_fetch_add(ws + WS_GROUP + grp, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
-    auto wait_group = [&](int grp) {
-        if (threadIdx.x == 0) {
-            // bounded: after spin_limit polls (or once any wait has run out)
-            // the flag is set and every later wait returns at once
-            uint32_t spins = 0;
-            while (__hip_atomic_fetch_add(ws + WS_GROUP + grp, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                   (uint32_t)NP1) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > spin_limit ||
-                    ((spins & 255) == 0 &&
-                     __hip_atomic_load(ws + WS_ERR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
-                    __hip_atomic_store(ws + WS_ERR, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-            }
-        }
+    __shared__ int s_fail;
+    auto wait_group = [&](int grp) -> bool {
+        if (threadIdx.x == 0) s_fail = bounded_wait(ws, WS_GROUP + grp, (uint32_t)NP1, wl) ? 0 : 1;
         __syncthreads();
+        return s_fail != 0;
     };
     auto groups_of = [&](int q) { return (NG - q + Q - 1) / Q; };
     auto drain = [&](int q) {
@@ -473,8 +485,8 @@ __global__ __launch_bounds__(S::NT, 4) void k_fused_fwd(const cplx<V>* __restric
                 phase1<V, S, HERM, POL>(A, lda, out, it.group, it.sub, lds);
                 publish(it.group);
             } else {
-                wait_group(it.group);
-                phase2<V, S, HERM, POL>(out, it.group, it.sub, lds);
+                const bool failed = wait_group(it.group);
+                phase2<V, S, HERM, POL>(out, it.group, it.sub, lds, failed);
             }
             __syncthreads();  // LDS reuse, s_next reuse
             if (threadIdx.x == 0)
@@ -597,8 +609,9 @@ __device__ __forceinline__ void rec_phase1(const void* __restrict__ coeff, cplx<
 
 template <class V, class S>
 __device__ __forceinline__ void rec_phase2(cplx<V>* __restrict__ A, int64_t lda, int g, int b, cplx<V>* lds,
-                                           V scale)
+                                           V scale, bool poison)
 {
+    if (poison) scale = __builtin_nan("");  // the group's intermediate is incomplete
     constexpr int KAP = S::KAP, LOGT = S::LOGT, T = 1 << LOGT;
     const uint32_t xg = (uint32_t)g << LOGT;
     const int k0 = b << KAP;
@@ -618,7 +631,7 @@ __device__ __forceinline__ void rec_phase2(cplx<V>* __restrict__ A, int64_t lda,
 template <class V, class S, bool REAL_IN>
 __global__ __launch_bounds__(S::NT, 4) void k_fused_rec(const void* __restrict__ coeff, cplx<V>* __restrict__ A,
                                                      int64_t lda, uint32_t* __restrict__ ws, int Q, int LA,
-                                                     uint32_t spin_limit, V scale)
+                                                     WaitLimits wl, V scale)
 {
     typedef RecShape<V, S> R;
     constexpr int NP1 = R::NR1, NP2 = R::NR2, NG = S::NG;
@@ -632,21 +645,11 @@ __global__ __launch_bounds__(S::NT, 4) void k_fused_rec(const void* __restrict__
         if (threadIdx.x == 0)
             __hip_atomic_fetch_add(ws + WS_GROUP + grp, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
-    auto wait_group = [&](int grp) {
-        if (threadIdx.x == 0) {
-            uint32_t spins = 0;
-            while (__hip_atomic_fetch_add(ws + WS_GROUP + grp, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                   (uint32_t)NP1) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > spin_limit ||
-                    ((spins & 255) == 0 &&
-                     __hip_atomic_load(ws + WS_ERR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
-                    __hip_atomic_store(ws + WS_ERR, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-            }
-        }
+    __shared__ int s_fail;
+    auto wait_group = [&](int grp) -> bool {
+        if (threadIdx.x == 0) s_fail = bounded_wait(ws, WS_GROUP + grp, (uint32_t)NP1, wl) ? 0 : 1;
         __syncthreads();
+        return s_fail != 0;
     };
     auto groups_of = [&](int q) { return (NG - q + Q - 1) / Q; };
     auto drain = [&](int q) {
@@ -662,8 +665,8 @@ __global__ __launch_bounds__(S::NT, 4) void k_fused_rec(const void* __restrict__
                 rec_phase1<V, S, REAL_IN>(coeff, A, lda, it.group, it.sub, lds);
                 publish(it.group);
             } else {
-                wait_group(it.group);
-                rec_phase2<V, S>(A, lda, it.group, it.sub, lds, scale);
+                const bool failed = wait_group(it.group);
+                rec_phase2<V, S>(A, lda, it.group, it.sub, lds, scale, failed);
             }
             __syncthreads();  // LDS reuse, s_next reuse
             if (threadIdx.x == 0)
@@ -695,7 +698,7 @@ hipError_t launch_rec_n(const void* coeff, void* A, int64_t lda, void* ws, int l
     if (e != hipSuccess) return e;
     const V scale = adjoint ? (V)1 / (V)(1u << LOGN) : (V)1;  // exact power of two
     hipLaunchKernelGGL((k_fused_rec<V, S, REAL_IN>), dim3(device_cu_count() * 2), dim3(512), 0, st, coeff,
-                       (cplx<V>*)A, lda, (uint32_t*)ws, device_xcd_count(), la, 1u << 22, scale);
+                       (cplx<V>*)A, lda, (uint32_t*)ws, device_xcd_count(), la, wait_limits(), scale);
     return hipGetLastError();
 }
 
@@ -721,9 +724,8 @@ hipError_t launch_cfg(const void* A, int64_t lda, void* out, void* ws, int la, h
     if (e != hipSuccess) return e;
     // persistent grid: as many workgroups as fit at once (LDS-limited)
     const int per_cu = NT == 512 ? 2 : 1;
-    const uint32_t spin_limit = 1u << 22;  // about 0.2 s of polling
     hipLaunchKernelGGL((k_fused_fwd<V, S, HERM, POL>), dim3(device_cu_count() * per_cu), dim3(NT), 0, st,
-                       (const cplx<V>*)A, lda, out, (uint32_t*)ws, device_xcd_count(), la, spin_limit);
+                       (const cplx<V>*)A, lda, out, (uint32_t*)ws, device_xcd_count(), la, wait_limits());
     return hipGetLastError();
 }
 

@@ -59,6 +59,33 @@ hipError_t launch_sparse(int n, ptd_dtype dt, bool compact, int64_t nnz, const i
                          const void* vals, const uint32_t* xs, int count, void* out, void* ws, bool* bad_xs,
                          hipStream_t st);
 
+// Test hook: the set of HW_REG_XCC_ID values that workgroups of a wide
+// launch observe (bit i for die i), and the XCD count the library uses.
+hipError_t probe_xcc_ids(unsigned* mask, int* count);
+
+// Every argument check of pauli_decompose except those of the workspace
+// (api.hip): PTD_OK, PTD_EINVAL or PTD_EUNSUP, before any HIP call.
+ptd_status decompose_check(int n, ptd_dtype dtype, unsigned flags, int s, const void* A, int64_t lda,
+                           const void* coeff);
+// PTD_OK, or PTD_EHIP with e recorded for ptd_last_hip_error (api.hip).
+ptd_status status_from_hip(hipError_t e);
+
+// Limits of the bounded waits in the single-launch kernels (fused.hpp): a
+// phase-2 item polls its group's counter at most `spins` times; `extra` is
+// added to the counter target (0, except in the test hook below, where no
+// target can be reached and every wait gives up).
+struct WaitLimits {
+    uint32_t spins;
+    uint32_t extra;
+};
+WaitLimits wait_limits();
+// Test hook: while on, every bounded wait gives up after a few polls, so a
+// test can observe the failure path (NaN outputs, the workspace error word)
+// with every kernel still ending normally.
+void set_wait_test_mode(bool on);
+// Workspace word that a bounded wait sets when it gives up.
+constexpr int FUSED_WS_ERR_WORD = 17;
+
 // Single-launch dense decompose for n = 11..15 (fused.hpp); ws holds
 // fused_workspace_bytes() bytes of queue and group counters; la = lookahead.
 size_t fused_workspace_bytes(int n, ptd_dtype dt);

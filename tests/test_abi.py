@@ -77,7 +77,11 @@ def test_nonempty_counts_match_bruteforce(lib, oracle_mod):
     assert api.num_nonempty_x(5) == 32
 
 
-def _dec(lib, n=4, dt=0, flags=0, s=0, A=1, lda=16, C=2, ws=None, wsb=0):
+# fake, far-apart "device" addresses: validation must reject before touching them
+FAKE_A, FAKE_C, FAKE_W = 1 << 40, 1 << 42, 1 << 44
+
+
+def _dec(lib, n=4, dt=0, flags=0, s=0, A=FAKE_A, lda=16, C=FAKE_C, ws=None, wsb=0):
     return lib.pauli_decompose(n, dt, flags, s, ctypes.c_void_p(A), lda, ctypes.c_void_p(C),
                                ctypes.c_void_p(ws) if ws else None, wsb, None)
 
@@ -106,10 +110,57 @@ def test_decompose_argument_errors(lib):
     assert _dec(lib, n=12, lda=4096, ws=0, wsb=0) == ENOSPC  # single-launch schedule needs counters
 
 
+def test_decompose_overlap_errors(lib):
+    """A, coeff and the workspace must be disjoint byte ranges, not just
+    different pointers: the one-launch schedule keeps partial results in
+    coeff while it still reads A."""
+    EINVAL = -1
+    a = FAKE_A
+    n = 12
+    N = 1 << n
+    wsb = lib.ptd_workspace_bytes(n, 0, 0, 0)
+    assert wsb > 0
+    # coeff starts inside the last row of A (16-byte complex128 elements)
+    assert _dec(lib, n=n, lda=N, A=a, C=a + (N * N - 1) * 16, ws=FAKE_W, wsb=wsb) == EINVAL
+    # A starts inside coeff
+    assert _dec(lib, n=n, lda=N, A=a + 16, C=a, ws=FAKE_W, wsb=wsb) == EINVAL
+    # a padded pitch widens the span of A
+    assert _dec(lib, n=n, lda=2 * N, A=a, C=a + N * N * 16, ws=FAKE_W, wsb=wsb) == EINVAL
+    # the workspace inside A, or inside coeff
+    assert _dec(lib, n=n, lda=N, A=a, C=FAKE_C, ws=a + 4096, wsb=wsb) == EINVAL
+    assert _dec(lib, n=n, lda=N, A=a, C=FAKE_C, ws=FAKE_C + 64, wsb=wsb) == EINVAL
+    # real (Hermitian) output: coeff starting 8 bytes before the end of A
+    assert _dec(lib, n=3, lda=8, flags=1, A=a, C=a + 64 * 16 - 8) == EINVAL
+    # compact band output: only the nonempty rows count
+    rows = lib.ptd_num_nonempty_x(6, 1 << 2, 1)
+    assert _dec(lib, n=6, lda=64, flags=(1 << 2) | (1 << 4), s=1, A=a, C=a - rows * 64 * 16 + 16) == EINVAL
+
+
+def test_reconstruct_overlap_errors(lib):
+    EINVAL = -1
+    n, N = 12, 1 << 12
+    wsb = lib.ptd_reconstruct_workspace_bytes(n, 0, 0)
+
+    def rec(C, A, ws):
+        return lib.pauli_reconstruct(n, 0, 0, ctypes.c_void_p(C), ctypes.c_void_p(A), N, ctypes.c_void_p(ws), wsb,
+                                     None)
+
+    assert rec(FAKE_C, FAKE_C + 16, FAKE_W) == EINVAL
+    assert rec(FAKE_C, FAKE_A, FAKE_A + 1024) == EINVAL
+
+
+def test_workspace_status_arguments(lib):
+    """A call that needs no workspace never waits: status is OK without a
+    GPU call; a non-empty but too small workspace is an argument error."""
+    assert lib.ptd_workspace_status(None, 0, None) == 0
+    assert lib.ptd_workspace_status(None, 256, None) == -1
+    assert lib.ptd_workspace_status(ctypes.c_void_p(FAKE_W), 64, None) == -1
+
+
 def test_reconstruct_argument_errors(lib):
     EINVAL = -1
 
-    def rec(n=4, dt=0, flags=0, C=1, A=2, lda=16):
+    def rec(n=4, dt=0, flags=0, C=FAKE_C, A=FAKE_A, lda=16):
         return lib.pauli_reconstruct(n, dt, flags, ctypes.c_void_p(C), ctypes.c_void_p(A), lda, None, 0, None)
 
     assert rec(n=0) == EINVAL
@@ -163,6 +214,12 @@ def test_tuning_registry(lib):
     assert lib.ptd_set_tuning(14, 0, 0, 99, 4) == -1
     assert lib.ptd_set_tuning(14, 0, 0, 22, 0) == -1
     assert lib.ptd_set_tuning(15, 0, 0, 1, 2) == -1  # complex128 n=15 runs the two-pass schedule
+    # a setting must name a shape (bits 0-1); cache-policy bits alone are rejected
+    for bad in (4, 8, 12, 16, 28):
+        assert lib.ptd_set_tuning(14, 0, 0, bad, 4) == -1
+    assert lib.ptd_set_tuning(15, 1, 0, 2, 4) == -1  # n = 15 is built with shape 1 only
+    assert lib.ptd_set_tuning(15, 1, 0, 3, 4) == -1
+    assert lib.ptd_set_tuning(15, 1, 0, 29, 4) == 0
     lib.ptd_clear_tuning()
     assert lib.ptd_get_tuning(14, 0, 0, ctypes.byref(cfg), ctypes.byref(la)) == 0
 
