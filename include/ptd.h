@@ -204,6 +204,25 @@ ptd_status pauli_reconstruct(int n, ptd_dtype dtype, unsigned flags, const void 
 ptd_status ptd_workspace_status(const void *ws, size_t ws_bytes, ptd_stream stream);
 
 /*
+ * pauli_decompose_noalloc: pauli_decompose for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and results as
+ * pauli_decompose, bit for bit, without the workspace: the one-launch
+ * schedule's counters live in a fixed device array of the library
+ * (PTD_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends).  The
+ * call allocates nothing and needs no set-up; its first call on a device
+ * looks up that device's array.  Each call clears the counters it uses, but
+ * all calls on one GPU share the array: calls that overlap in time on the
+ * same GPU (other streams, other host threads) race and are not supported.
+ * PTD_ENOSPC if the request needs more than PTD_NOALLOC_SCRATCH_BYTES
+ * (no current request does).  A bounded wait that gives up leaves NaN in
+ * the affected coefficients, as in pauli_decompose.
+ */
+#define PTD_NOALLOC_SCRATCH_BYTES 65536
+ptd_status pauli_decompose_noalloc(int n, ptd_dtype dtype, unsigned flags, int s, const void *A, int64_t lda,
+                                   void *coeff, ptd_stream stream);
+
+/*
  * Batched decomposition: `count` matrices of uneven size in one persistent
  * launch whose workgroups take (matrix, X-pattern group) items from an
  * atomic queue, largest matrices first.  Every n_i must lie in 1..10 (one

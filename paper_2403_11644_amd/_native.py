@@ -32,6 +32,7 @@ SIGNATURES = {
     "pauli_decompose": (I, [I, I, U, I, P, I64, P, P, SZ, P]),
     "pauli_reconstruct": (I, [I, I, U, P, P, I64, P, SZ, P]),
     "ptd_workspace_status": (I, [P, SZ, P]),
+    "pauli_decompose_noalloc": (I, [I, I, U, I, P, I64, P, P]),
     "ptd_reduce_workspace_bytes": (SZ, []),
     "ptd_parseval_residual": (I, [I, I, U, P, I64, P, P, P, SZ, P]),
     "ptd_batched_workspace_bytes": (SZ, [I, I, P]),
