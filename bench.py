@@ -35,6 +35,13 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+# bandwidth sweep (probe.hip): (log2 accesses per thread, nt loads, nt stores,
+# blocked, log2 threads/256, log2 workgroups per CU); the first entry of each
+# list is the fastest shape measured on MI355X
+CEILING_COPY = [(0, 1, 1, 0, 1, 1), (0, 1, 1, 0, 2, 0), (3, 1, 1, 1, 2, 0), (2, 1, 1, 1, 2, 0), (2, 1, 1, 0, 0, 0),
+                (1, 1, 1, 0, 1, 0), (2, 0, 0, 1, 2, 0), (0, 0, 0, 0, 0, 2)]
+CEILING_READ = [(2, 1, 0, 1, 1, 0), (3, 1, 0, 1, 0, 0), (2, 1, 0, 1, 0, 1), (3, 1, 0, 0, 0, 0), (2, 0, 0, 1, 1, 0)]
+CEILING_WRITE = [(0, 0, 0, 0, 0, 0), (2, 0, 0, 1, 2, 0), (2, 0, 1, 1, 2, 0), (0, 0, 0, 0, 1, 0)]
 
 
 def _cpu_model() -> str:
@@ -82,18 +89,71 @@ def _kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel: str, key: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources; else None."""
+def _traffic_records() -> dict:
+    """profiles/traffic.json, or {} if it is missing or was taken on other
+    kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         data = json.load(open(path))
     except (OSError, ValueError):
+        return {}
+    if data.get("kernel_hash") != _kernel_hash():
+        return {}
+    return data.get("kernels", {})
+
+
+def _traffic(*parts: str):
+    """(fetch, write) bytes per launch at the L2 boundary of the one kernel
+    whose name holds every string in parts, from the committed rocprofv3
+    counter summary of the current kernel sources; else None."""
+    recs = [r for name, r in _traffic_records().items() if all(p in name for p in parts)]
+    if len(recs) != 1:
         return None
-    rec = data.get("%s/%s" % (kernel, key))
-    if not rec or rec.get("kernel_hash") != _kernel_hash():
+    return recs[0]["fetch_bytes"], recs[0]["write_bytes"]
+
+
+def _traffic_total(*parts: str):
+    t = _traffic(*parts)
+    return None if t is None else t[0] + t[1]
+
+
+def _traffic_sum(*parts: str):
+    """Summed fetch + write bytes of every kernel whose name holds all parts
+    (a launch sequence, e.g. the per-size kernels of a batch plan)."""
+    recs = [r for name, r in _traffic_records().items() if all(p in name for p in parts)]
+    if not recs:
         return None
-    return rec.get("bytes_per_launch")
+    return sum(r["fetch_bytes"] + r["write_bytes"] for r in recs)
+
+
+def _batched_traffic():
+    """Bytes per launch of the Hermitian complex64 batch plan: its per-size
+    kernels k_batched<float, n, true, false, ...> plus the shared launch of
+    the small sizes k_batched_small<float, true, false>.  None unless each
+    size ran with one plan shape only (a tuned plan of another shape would
+    be counted twice)."""
+    recs, sizes = [], []
+    for name, r in _traffic_records().items():
+        if "k_batched" not in name:
+            continue
+        targs = [a.strip() for a in name.split("<", 1)[1].split(">", 1)[0].split(",")]
+        small = "k_batched_small<" in name
+        herm, rec = (targs[1], targs[2]) if small else (targs[2], targs[3])
+        if targs[0] == "float" and herm == "true" and rec == "false":
+            recs.append(r)
+            if not small:
+                sizes.append(targs[1])
+    if not recs or len(sizes) != len(set(sizes)):
+        return None
+    return sum(r["fetch_bytes"] + r["write_bytes"] for r in recs)
+
+
+def _with_traffic(leg: dict, total, algorithmic: float) -> dict:
+    """Adds the counter traffic (bytes per launch at the L2 boundary) and its
+    ratio to the algorithmic bytes, when a record of these sources exists."""
+    leg["traffic_bytes"] = total
+    leg["traffic_ratio"] = None if total is None else round(total / algorithmic, 3)
+    return leg
 
 
 def _herm_bytes(n: int, elem: int) -> float:
@@ -105,7 +165,7 @@ def _herm_bytes(n: int, elem: int) -> float:
 
 
 def _counter_means(folder: str, counter: str) -> dict:
-    """Mean value per kernel of one counter in a rocprofv3 --pmc CSV folder."""
+    """Mean value of one counter per kernel name in a rocprofv3 --pmc CSV folder."""
     import csv
     import glob
 
@@ -114,37 +174,41 @@ def _counter_means(folder: str, counter: str) -> dict:
         for r in csv.DictReader(open(f)):
             if r.get("Counter_Name") != counter:
                 continue
-            nm = r["Kernel_Name"]
-            key = "k_fused_fwd" if "k_fused_fwd" in nm else ("k_copy16" if "k_copy16" in nm else None)
-            if key:
-                vals.setdefault(key, []).append(float(r["Counter_Value"]))
+            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
     return {k: sum(v) / len(v) for k, v in vals.items()}
 
 
 def write_traffic(fetch_dir: str, write_dir: str, n: int) -> dict:
-    """profiles/traffic.json from two rocprofv3 counter runs of
-    `bench.py --legs copy` (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).
-    Each counter is scaled by what it reads for the reference copy, which
-    reads and writes the 2^n x 2^n complex128 matrix once each."""
+    """profiles/traffic.json from two rocprofv3 counter runs of this bench
+    with the copy leg among its legs (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch).  Each counter is scaled by what it reads for the reference
+    copy, which reads and writes the 2^n x 2^n complex128 matrix once each;
+    every kernel of the runs is recorded."""
     fetch = _counter_means(fetch_dir, "FETCH_SIZE")
     write = _counter_means(write_dir, "WRITE_SIZE")
+    copy_name = [k for k in fetch if "k_copy16" in k]
+    if len(copy_name) != 1:
+        raise SystemExit("the counter runs must include the copy leg (k_copy16)")
     mat_bytes = 16.0 * 4.0 ** n
-    fs = mat_bytes / (fetch["k_copy16"] * 1024.0)
-    ws = mat_bytes / (write["k_copy16"] * 1024.0)
-    fb = fetch["k_fused_fwd"] * 1024.0 * fs
-    wb = write["k_fused_fwd"] * 1024.0 * ws
-    rec = {"kernel_hash": _kernel_hash(), "bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
-           "fetch_scale": round(fs, 4), "write_scale": round(ws, 4), "algorithmic_bytes": 2 * mat_bytes,
-           "ratio_to_algorithmic": round((fb + wb) / (2 * mat_bytes), 3)}
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    try:
-        data = json.load(open(path))
-    except (OSError, ValueError):
-        data = {}
-    data["k_fused_fwd/n%d/c128" % n] = rec
-    with open(path, "w") as f:
+    fs = mat_bytes / (fetch[copy_name[0]] * 1024.0)
+    ws = mat_bytes / (write[copy_name[0]] * 1024.0)
+    kernels = {}
+    for name in sorted(set(fetch) & set(write)):
+        if "ptd::" not in name:  # the library's kernels only
+            continue
+        fb = fetch[name] * 1024.0 * fs
+        wb = write[name] * 1024.0 * ws
+        kernels[name] = {"fetch_bytes": round(fb), "write_bytes": round(wb)}
+    data = {"kernel_hash": _kernel_hash(), "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+            "scale_reference": "k_copy16 over 2 x %d bytes" % int(mat_bytes), "kernels": kernels}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
         json.dump(data, f, indent=1)
-    return rec
+    return data
+
+
+def _progress(msg: str) -> None:
+    """One line per finished step on stderr (stdout carries only the JSON line)."""
+    print("[bench] %s" % msg, file=sys.stderr, flush=True)
 
 
 def _settle(fn, seconds: float = 0.15) -> None:
@@ -235,7 +299,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=14)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="all",
-                    help="comma list of reported legs to run: complex64, two_pass, copy, reconstruct, parseval, "
+                    help="comma list of reported legs to run: complex64, two_pass, copy, ceiling, reconstruct, parseval, "
+                         "batched_direct (counter runs), "
                          "small, hermitian, band, toeplitz, algebra, n15, batched; 'all' or 'none'")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -285,6 +350,7 @@ def main() -> int:
         _native.check(L.pauli_decompose(n, api.C128, 0, 0, api._ptr(A), N, api._ptr(out128), api._ptr(ws), wsb, sh),
                       "pauli_decompose")
 
+    _progress("input ready, headline")
     # the headline: exactly `warmup` untimed calls, then `steps` timed ones
     ms128 = _time(run128, args.steps, args.warmup, stream, settle=False)
     run128()
@@ -309,11 +375,12 @@ def main() -> int:
     legs = {}
     want_legs = set()
     if args.legs == "all":
-        want_legs = {"complex64", "two_pass", "copy", "reconstruct", "parseval", "small", "hermitian", "band",
+        want_legs = {"complex64", "two_pass", "copy", "ceiling", "reconstruct", "parseval", "small", "hermitian", "band",
                      "toeplitz", "algebra", "n15", "batched"}
     elif args.legs != "none":
         want_legs = set(args.legs.split(","))
     if "reconstruct" in want_legs:
+        _progress("leg reconstruct")
         # A = sum_P c_P P from the coefficients just computed (the adjoint
         # path of autograd); checked against the input on sampled entries
         rec = torch.empty_like(A)
@@ -324,14 +391,18 @@ def main() -> int:
         legs["reconstruct_f64"] = {"ms": round(msr, 4), "GCoeff_s": round(ncoef / msr / 1e6, 2),
                                    "path_hbm_frac": round(32 * ncoef / (msr * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
                                    "err_rel_sampled_entries": rerr}
+        _with_traffic(legs["reconstruct_f64"], _traffic_total("k_fused_rec<double", "Shape<double, %d," % n),
+                      32 * ncoef)
         del rec
     if "parseval" in want_legs:
+        _progress("leg parseval")
         # float64 residual reductions: ||A||_F^2 and 2^n sum |c|^2 (reads A
         # and c once each, then one 48-byte copy to the host)
         msp_ = _time(lambda: ptd.parseval(A, out128), 10, 3, stream)
         legs["parseval_f64"] = {"ms": round(msp_, 4),
                                 "path_hbm_frac": round(32 * ncoef / (msp_ * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
     if "complex64" in want_legs:
+        _progress("leg complex64")
         # complex64 cast of the same matrix (cast excluded from the time, reported apart)
         torch.cuda.synchronize()
         t0 = time.time()
@@ -360,8 +431,11 @@ def main() -> int:
                              "err_rel_sampled_vs_oracle_on_cast_input": _rel(got64, want_cast),
                              "parseval_residual": pars64, "speedup_vs_f64": round(ms128 / ms64, 3),
                              "cast_ms": round(cast_ms, 3)}
+        _with_traffic(legs["complex64"], _traffic_total("k_fused_fwd<float", "Shape<float, %d," % n, ", false,"),
+                      16 * ncoef)
         del out64, A64
     if "two_pass" in want_legs:
+        _progress("leg two_pass")
         # the two-pass schedule on the same input (same bytes moved twice)
         def run_two():
             _native.check(L.ptd_debug_decompose_stage(n, api.C128, 0, api._ptr(A), N, api._ptr(out128), 3, sh),
@@ -369,17 +443,69 @@ def main() -> int:
 
         ms_two = _time(run_two, 5, 2, stream)
         legs["two_pass_f64"] = {"ms": round(ms_two, 4), "single_launch_speedup": round(ms_two / ms128, 3)}
-    if "copy" in want_legs:
-        # plain device copy of the same bytes (practical bandwidth ceiling)
+    if "copy" in want_legs or "ceiling" in want_legs:
+        _progress("leg copy/ceiling")
+        # bandwidth references over the same bytes: a plain 16-byte copy, then
+        # a sweep of copy / read-only / write-only shapes (probe.hip); the best
+        # copy is the practical ceiling of a kernel that reads and writes
+        # every byte once.  A read and a write of a 128 MiB window repeated
+        # 20 times run from the memory-side cache.
         cpy = torch.empty_like(A)
-        ms_copy = _time(lambda: L.ptd_debug_copy(api._ptr(A), api._ptr(cpy), A.numel() * 16, sh), 5, 2, stream)
-        legs["copy_ceiling"] = {"GBps": round(2 * A.numel() * 16 / (ms_copy * 1e-3) / 1e9, 1),
-                                "frac_of_peak": round(2 * A.numel() * 16 / (ms_copy * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                                "headline_frac_of_copy": round(ms_copy / ms128, 4)}
+        nbytes = A.numel() * 16
+        ms_copy = _time(lambda: L.ptd_debug_copy(api._ptr(A), api._ptr(cpy), nbytes, sh), 5, 2, stream)
+        ceiling = {"plain_copy_GBps": round(2 * nbytes / (ms_copy * 1e-3) / 1e9, 1)}
+        if "ceiling" in want_legs:
+            sweep = []
+            for mode, cfgs in ((0, CEILING_COPY), (1, CEILING_READ), (2, CEILING_WRITE)):
+                for (lu, ntl, nts, blk, lt, lw) in cfgs:
+                    var = mode | (lu << 2) | (ntl << 4) | (nts << 5) | (blk << 6) | (lt << 8) | (lw << 10)
+
+                    def runbw(var=var):
+                        _native.check(L.ptd_debug_bandwidth(var, api._ptr(A), api._ptr(cpy), nbytes, sh),
+                                      "ptd_debug_bandwidth")
+
+                    msb = _time(runbw, 5, 2, stream, settle=False)
+                    moved = (2 if mode == 0 else 1) * nbytes
+                    sweep.append({"mode": ("copy", "read", "write")[mode], "variant": var,
+                                  "GBps": round(moved / (msb * 1e-3) / 1e9, 1)})
+            for mname in ("copy", "read", "write"):
+                best = max((r for r in sweep if r["mode"] == mname), key=lambda r: r["GBps"])
+                ceiling["best_%s_GBps" % mname] = best["GBps"]
+                ceiling["best_%s_variant" % mname] = best["variant"]
+                ceiling["best_%s_frac_of_peak" % mname] = round(best["GBps"] / HBM_PEAK_GBPS, 4)
+            win = 128 << 20
+            rd = CEILING_READ[0]
+            wr = CEILING_WRITE[0]
+            var_r = 1 | (rd[0] << 2) | (rd[1] << 4) | (rd[2] << 5) | (rd[3] << 6) | (rd[4] << 8) | (rd[5] << 10)
+            var_w = 2 | (wr[0] << 2) | (wr[1] << 4) | (wr[2] << 5) | (wr[3] << 6) | (wr[4] << 8) | (wr[5] << 10)
+
+            def rep(var, reps=20):
+                for _ in range(reps):
+                    L.ptd_debug_bandwidth(var, api._ptr(A), api._ptr(cpy), win, sh)
+
+            ms_r = _time(lambda: rep(var_r), 3, 1, stream, settle=False)
+            ms_w = _time(lambda: rep(var_w), 3, 1, stream, settle=False)
+            # write-back probe over 16 MiB (its counters: does the L2 keep
+            # written lines?); timed only so that it runs
+            _native.check(L.ptd_debug_bandwidth(3, None, api._ptr(cpy), 16 << 20, sh), "ptd_debug_bandwidth")
+            ceiling["memory_side_cache_read_GBps"] = round(20 * win / (ms_r * 1e-3) / 1e9, 1)
+            ceiling["memory_side_cache_write_GBps"] = round(20 * win / (ms_w * 1e-3) / 1e9, 1)
+            ceiling["sweep"] = sweep
+            best_copy = max(ceiling["best_copy_GBps"], ceiling["plain_copy_GBps"])
+        else:
+            best_copy = ceiling["plain_copy_GBps"]
+        ceiling["ceiling_copy_GBps"] = best_copy
+        ceiling["ceiling_frac_of_peak"] = round(best_copy / HBM_PEAK_GBPS, 4)
+        # the headline moves 2 x 4^n x 16 B at the L2 boundary (its exchange
+        # adds one write and one read of the output): its rate there
+        ceiling["headline_frac_of_ceiling"] = round(32 * ncoef / (ms128 * 1e-3) / 1e9 / best_copy, 4)
+        ceiling["headline_l2_boundary_GBps"] = round(2 * 32 * ncoef / (ms128 * 1e-3) / 1e9, 1)
+        legs["copy_ceiling"] = ceiling
         del cpy
         torch.cuda.empty_cache()
     g = torch.Generator(device=dev)
     if "small" in want_legs:
+        _progress("leg small")
         # n = 8 dense complex128 (65,536 coefficients): latency of one call,
         # warm and after a 1 GiB write that evicts A from the L2 and the
         # memory-side cache; every coefficient against the oracle
@@ -402,6 +528,7 @@ def main() -> int:
                            "err_rel_all_vs_oracle": _rel(o8.cpu().numpy(), O.decompose(A8_host))}
         del A8, o8, flush
     if "hermitian" in want_legs:
+        _progress("leg hermitian")
         # n = 13 Hermitian A = (B + B^H)/2 (device-generated B): the Hermitian
         # path (real output, reads one element of each mirrored pair) and the
         # dense path on the same matrix, in complex128 and in a complex64 cast
@@ -426,7 +553,9 @@ def main() -> int:
                                      "path_hbm_frac": round(_herm_bytes(13, 16) / (msh * 1e-3) / 1e9 / HBM_PEAK_GBPS,
                                                             4),
                                      "err_rel_sampled": errh, "dense_path_ms": round(msd, 4),
-                                     "dense_path_max_abs_im": im_max}
+                                     "dense_path_max_abs_im": im_max, "speedup_vs_dense_path": round(msd / msh, 3)}
+        _with_traffic(legs["hermitian_n13_f64"], _traffic_total("k_fused_fwd<double", "Shape<double, 13,", ", true,"),
+                      _herm_bytes(13, 16))
         H32 = H.to(torch.complex64)
         del H
         hout32 = torch.empty((1 << 13, 1 << 13), dtype=torch.float32, device=dev)
@@ -438,10 +567,14 @@ def main() -> int:
                                      "path_hbm_frac": round(_herm_bytes(13, 8) / (msh32 * 1e-3) / 1e9 / HBM_PEAK_GBPS,
                                                             4),
                                      "speedup_vs_f64": round(msh / msh32, 2),
-                                     "err_rel_sampled_vs_f64_oracle": errh32, "dense_path_ms": round(msd32, 4)}
+                                     "err_rel_sampled_vs_f64_oracle": errh32, "dense_path_ms": round(msd32, 4),
+                                     "speedup_vs_dense_path": round(msd32 / msh32, 3)}
+        _with_traffic(legs["hermitian_n13_f32"], _traffic_total("k_fused_fwd<float", "Shape<float, 13,", ", true,"),
+                      _herm_bytes(13, 8))
         del H32, hout32, dout32
         torch.cuda.empty_cache()
     if "band" in want_legs:
+        _progress("leg band")
         # n = 14 structured inputs: the skip path over the nonempty X-patterns
         # only (1 / 15 / 96 / 1 of 16384), from compressed bands with compact
         # output, and for s = 8 also from the dense matrix (reading only the
@@ -497,6 +630,7 @@ def main() -> int:
         del rd, cd, vd, sp_out, sp_xs
         legs["structured_n14"] = band_legs
     if "toeplitz" in want_legs:
+        _progress("leg toeplitz")
         # matrix-free Toeplitz input at the headline size: the kernels read the
         # 2^15 - 1 defining entries (0.5 MiB, cache-resident) instead of A;
         # same output, same arithmetic as the dense call
@@ -528,6 +662,7 @@ def main() -> int:
         del tv, tv64, o64
         torch.cuda.empty_cache()
     if "algebra" in want_legs:
+        _progress("leg algebra")
         # Sec. IV-B combinations on coefficient arrays: one HBM pass each
         # (bytes = inputs read once + output written once)
         n13 = 13
@@ -572,6 +707,7 @@ def main() -> int:
         del ca, cb, lco
         torch.cuda.empty_cache()
     if "n15" in want_legs:
+        _progress("leg n15")
         # n = 15 complex64, plain and compensated butterflies
         g.manual_seed(15)
         A15 = torch.randn((1 << 15, 1 << 15), dtype=torch.complex64, device=dev, generator=g)
@@ -595,20 +731,39 @@ def main() -> int:
                            "compensated_roofline": _comp_roofline(15, ms15c),
                            "err_rel_1e6_sampled_vs_f64_oracle": {"plain": _rel(got_plain, want15),
                                                                  "compensated": _rel(got_comp, want15)}}
+        _with_traffic(legs["n15_c64"], _traffic_total("k_fused_fwd<float", "Shape<float, 15,"), 16 * 4.0 ** 15)
+        torch.cuda.empty_cache()
+    if "batched_direct" in want_legs:
+        _progress("leg batched_direct")
+        # the same 4096-matrix Hermitian complex64 batch through the direct
+        # batched call (descriptors uploaded per call, no graph): the launch
+        # sequence whose counters stand for the plan's kernels
+        ns = synth.batched_ns(4096, seed=0).astype(np.int32)
+        hbuf, offs = synth.batched_hermitian(ns, seed=1, dtype=np.complex64)
+        sizes = np.array([1 << (2 * int(k)) for k in ns], dtype=np.int64)
+        bbuf = torch.from_numpy(hbuf).to(dev)
+        del hbuf
+        mats = [bbuf[o:o + s].view(1 << int(k), 1 << int(k)) for o, s, k in zip(offs, sizes, ns)]
+        L.ptd_clear_tuning()
+        msb = _time(lambda: ptd.decompose_batched(mats, hermitian=True), 5, 2, stream)
+        hb = sum(_herm_bytes(int(k), 8) for k in ns)
+        legs["batched_direct_4096_herm_c64"] = _with_traffic(
+            {"ms": round(msb, 4), "path_hbm_frac": round(hb / (msb * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
+            _batched_traffic(), hb)
+        del mats, bbuf
         torch.cuda.empty_cache()
     if "batched" in want_legs:
+        _progress("leg batched")
         # 4096 Hermitian complex64 matrices, n uniform on {2..10}: one captured
         # plan launch vs one pauli_decompose call per matrix
+        # A_i = (B_i + B_i^H) / 2 with B_i complex N(0, 1) in float32 (synth)
         ns = synth.batched_ns(4096, seed=0).astype(np.int32)
+        hbuf, offs = synth.batched_hermitian(ns, seed=1, dtype=np.complex64)
         sizes = np.array([1 << (2 * int(k)) for k in ns], dtype=np.int64)
-        offs = np.zeros(len(ns), dtype=np.int64)
-        offs[1:] = np.cumsum(sizes)[:-1]
-        g.manual_seed(1)
-        bbuf = torch.randn(int(sizes.sum()), dtype=torch.complex64, device=dev, generator=g)
+        bbuf = torch.from_numpy(hbuf).to(dev)
+        del hbuf
         bout2 = torch.empty(int(sizes.sum()), dtype=torch.float32, device=dev)
         mats = [bbuf[o:o + s].view(1 << int(k), 1 << int(k)) for o, s, k in zip(offs, sizes, ns)]
-        for m in mats:  # Hermitian: (B + B^H) / 2 in place per matrix
-            m.copy_((m + m.conj().T) / 2)
         # plans as shipped (the defaults encode an earlier tuning on MI355X),
         # then re-tuned here by the autotuner for every size present
         L.ptd_clear_tuning()
@@ -646,6 +801,10 @@ def main() -> int:
                                          "complex_out_plan_ms": round(msc, 4),
                                          "complex_out_hbm_frac": round(16 * tot / (msc * 1e-3) / 1e9 / HBM_PEAK_GBPS,
                                                                        4)}
+        # the Hermitian plans' kernels (per-size persistent launches and the
+        # shared launch of sizes <= 7); counters of every plan run are summed
+        # per launch kind, so this is per plan launch only if one plan ran
+        _with_traffic(legs["batched_4096_herm_c64"], _batched_traffic(), hb)
         del bbuf, bout2, mats
         torch.cuda.empty_cache()
 
@@ -726,7 +885,7 @@ def main() -> int:
                                "coefficients per step" % (n, N, N, n), "n": n, "parallelism": "none"},
         "roofline": {"bound": "hbm", "kernel": "k_fused_fwd", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": _traffic("k_fused_fwd", "n%d/c128" % n),
+                     "traffic": _traffic_total("k_fused_fwd<double", "Shape<double, %d," % n, ", false,"),
                      "algorithmic_bytes_per_launch": bytes128, "avg_launch_ms": round(ms128, 4)},
         "err_rel_sampled": err128,
         "parseval_residual": pars128,

@@ -63,6 +63,7 @@ SIGNATURES = {
     "ptd_debug_decompose_stage": (I, [I, I, U, P, I64, P, I, P]),
     "ptd_debug_decompose_fused": (I, [I, I, U, P, I64, P, P, SZ, I, I, P]),
     "ptd_debug_copy": (I, [P, P, SZ, P]),
+    "ptd_debug_bandwidth": (I, [I, P, P, SZ, P]),
     "ptd_debug_wait_test_mode": (None, [I]),
     "ptd_debug_xcc_ids": (I, [P, P]),
 }

@@ -666,6 +666,24 @@ ptd_status ptd_debug_copy(const void* src, void* dst, size_t bytes, ptd_stream s
     return hip_status(ptd::launch_copy(src, dst, bytes, (hipStream_t)stream));
 }
 
+// Bandwidth reference of one shape (probe.hip: mode, accesses per thread,
+// cache hints, partition, workgroup size and count); the read-only mode
+// ignores dst, the write-only mode src.
+ptd_status ptd_debug_bandwidth(int variant, const void* src, void* dst, size_t bytes, ptd_stream stream)
+{
+    const int mode = variant & 3;
+    if ((bytes & 15) || bytes == 0) return PTD_EINVAL;
+    if (mode == 3) {
+        // write-back probe over dst: 64 KiB per workgroup, at most 1 GiB
+        if (variant != 3 || !dst || (bytes & 65535) || bytes > ((size_t)1 << 30)) return PTD_EINVAL;
+        return hip_status(ptd::launch_bandwidth(variant, src, dst, bytes, (hipStream_t)stream));
+    }
+    if ((mode != 2 && !src) || (mode != 1 && !dst)) return PTD_EINVAL;
+    if ((variant & ~0xF7F) || ((variant >> 8) & 3) == 3 || (256 << ((variant >> 8) & 3)) * (1 << ((variant >> 10) & 3)) > 2048)
+        return PTD_EINVAL;
+    return hip_status(ptd::launch_bandwidth(variant, src, dst, bytes, (hipStream_t)stream));
+}
+
 // Timing hook: launch one pass of the two-pass dense schedule (n >= 7).
 ptd_status ptd_debug_decompose_stage(int n, ptd_dtype dtype, unsigned flags, const void* A, int64_t lda,
                                      void* coeff, int stage, ptd_stream stream)

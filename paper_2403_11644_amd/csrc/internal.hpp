@@ -59,6 +59,10 @@ hipError_t launch_sparse(int n, ptd_dtype dt, bool compact, int64_t nnz, const i
                          const void* vals, const uint32_t* xs, int count, void* out, void* ws, bool* bad_xs,
                          hipStream_t st);
 
+// Bandwidth reference kernels (probe.hip): copy / read / write of `bytes`
+// (a multiple of 16) in the shape `variant` encodes.
+hipError_t launch_bandwidth(int variant, const void* src, void* dst, size_t bytes, hipStream_t st);
+
 // Test hook: the set of HW_REG_XCC_ID values that workgroups of a wide
 // launch observe (bit i for die i), and the XCD count the library uses.
 hipError_t probe_xcc_ids(unsigned* mask, int* count);

@@ -386,3 +386,18 @@ def test_to_dict():
     assert labels.to_dict(r, xs=[0, 1]) == {"Z": 2.0, "Y": -1.0}
     with pytest.raises(ValueError):
         labels.to_dict(np.zeros((1, 4)))  # compact without xs
+
+
+def test_bandwidth_probe_arguments(lib):
+    """The bandwidth reference hook validates its shape bits before any HIP call."""
+    bw = lib.ptd_debug_bandwidth
+    a, c = ctypes.c_void_p(FAKE_A), ctypes.c_void_p(FAKE_C)
+    assert bw(0, a, c, 4096 + 8, None) == -1  # not a multiple of 16 bytes
+    assert bw(0, None, c, 4096, None) == -1  # copy needs a source
+    assert bw(2 | (3 << 8), None, c, 4096, None) == -1  # 2048-thread workgroups
+    assert bw(2 | (2 << 8) | (2 << 10), None, c, 4096, None) == -1  # 1024 threads x 4 per CU
+    assert bw(1 << 7, a, c, 4096, None) == -1  # unused bit
+    assert bw(3, None, c, 4096, None) == -1  # write-back probe: 64 KiB granules
+    assert bw(3 | (1 << 4), None, c, 65536, None) == -1  # write-back probe takes no other bits
+    assert bw(3, None, None, 65536, None) == -1
+    assert bw(3, None, c, 2 << 30, None) == -1  # at most 1 GiB

@@ -34,7 +34,7 @@ def test_counter_means(bench, tmp_path):
         ("ptd::fused::k_fused_fwd<double, Shape<...>>(...)", "FETCH_SIZE", 300.0),
         ("ptd::(anonymous namespace)::k_copy16(...)", "FETCH_SIZE", 50.0),
         ("ptd::(anonymous namespace)::k_copy16(...)", "WRITE_SIZE", 999.0),  # other counter: ignored
-        ("at::native::elementwise_kernel<...>", "FETCH_SIZE", 7.0),  # other kernel: ignored
+        ("at::native::elementwise_kernel<...>", "FETCH_SIZE", 7.0),  # every kernel is kept, by full name
     ]
     with open(tmp_path / "x_counter_collection.csv", "w", newline="") as f:
         w = csv.writer(f)
@@ -42,7 +42,8 @@ def test_counter_means(bench, tmp_path):
         for i, (k, c, v) in enumerate(rows):
             w.writerow([i, k, c, v])
     got = bench._counter_means(str(tmp_path), "FETCH_SIZE")
-    assert got == {"k_fused_fwd": 200.0, "k_copy16": 50.0}
+    assert got == {"ptd::fused::k_fused_fwd<double, Shape<...>>(...)": 200.0,
+                   "ptd::(anonymous namespace)::k_copy16(...)": 50.0, "at::native::elementwise_kernel<...>": 7.0}
 
 
 def test_hermitian_bytes(bench):
@@ -74,9 +75,41 @@ def test_traffic_record_is_dropped_once_the_sources_change(bench, tmp_path, monk
     (csrc / "k.hip").write_text("v1")
     (tmp_path / "profiles").mkdir()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    rec = {"k_fused_fwd/n14/c128": {"kernel_hash": bench._kernel_hash(), "bytes_per_launch": 123.0}}
+    k14 = "void ptd::fused::k_fused_fwd<double, ptd::fused::Shape<double, 14, 9, 512, 3>, false, 3>(x)"
+    k13 = "void ptd::fused::k_fused_fwd<double, ptd::fused::Shape<double, 13, 9, 512, 3>, true, 3>(x)"
+    rec = {"kernel_hash": bench._kernel_hash(),
+           "kernels": {k14: {"fetch_bytes": 100, "write_bytes": 23}, k13: {"fetch_bytes": 1, "write_bytes": 2}}}
     (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
-    assert bench._traffic("k_fused_fwd", "n14/c128") == 123.0
-    assert bench._traffic("k_fused_fwd", "n13/c128") is None
+    assert bench._traffic_total("k_fused_fwd<double", "Shape<double, 14,", ", false,") == 123
+    assert bench._traffic_total("k_fused_fwd<double", "Shape<double, 13,", ", true,") == 3
+    assert bench._traffic_total("k_fused_fwd<double") is None  # two kernels match: ambiguous
+    assert bench._traffic_total("k_fused_fwd<double", "Shape<double, 12,") is None
     (csrc / "k.hip").write_text("v2")
-    assert bench._traffic("k_fused_fwd", "n14/c128") is None
+    assert bench._traffic_total("k_fused_fwd<double", "Shape<double, 14,", ", false,") is None
+
+
+def test_write_traffic_scales_every_kernel_by_the_copy(bench, tmp_path, monkeypatch):
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of every kernel, scaled so
+    that the reference copy reads and writes the matrix once each."""
+    import json
+
+    csrc = tmp_path / "paper_2403_11644_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (csrc / "k.hip").write_text("v1")
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    n = 4
+    mat_kib = 16 * 4 ** n / 1024.0
+    rows = {"f": [("ptd::k_copy16(a)", mat_kib / 2), ("ptd::k_x<float>(b)", mat_kib), ("at::other(c)", 1.0)],
+            "w": [("ptd::k_copy16(a)", mat_kib), ("ptd::k_x<float>(b)", 3 * mat_kib), ("at::other(c)", 1.0)]}
+    for d, counter in (("f", "FETCH_SIZE"), ("w", "WRITE_SIZE")):
+        (tmp_path / d).mkdir()
+        lines = ["Kernel_Name,Counter_Name,Counter_Value"]
+        lines += ['"%s",%s,%r' % (k, counter, v) for k, v in rows[d]]
+        (tmp_path / d / "p_counter_collection.csv").write_text("\n".join(lines) + "\n")
+    data = bench.write_traffic(str(tmp_path / "f"), str(tmp_path / "w"), n)
+    assert data["fetch_scale"] == 2.0 and data["write_scale"] == 1.0
+    assert "at::other(c)" not in data["kernels"]  # the library's kernels only
+    assert data["kernels"]["ptd::k_x<float>(b)"] == {"fetch_bytes": 2 * 16 * 4 ** n, "write_bytes": 3 * 16 * 4 ** n}
+    assert json.loads((tmp_path / "profiles" / "traffic.json").read_text()) == data
+    assert bench._traffic("k_x<float>") == (2 * 16 * 4 ** n, 3 * 16 * 4 ** n)
