@@ -185,3 +185,23 @@ def sample_strings(n: int, count: int, seed: int):
     idx = np.random.default_rng(seed).choice(total, count, replace=False)
     idx = np.sort(idx.astype(np.int64))
     return (idx >> n).astype(np.uint32), (idx & ((1 << n) - 1)).astype(np.uint32)
+
+
+def sample_every_row(n: int, per_x: int, seed: int, low_bits: int = 9):
+    """per_x strings for EVERY X-pattern x: the j-th one has a Z-pattern whose
+    low `low_bits` bits fall in the j-th of per_x equal blocks of
+    [0, 2^low_bits) (the rest of z uniform), so that every row, and every
+    run of low Z-positions a kernel may give to one work item, is sampled.
+    Returns (xs, zs) as uint32 arrays of length per_x * 2^n."""
+    N = 1 << n
+    low_bits = min(low_bits, n)
+    L = 1 << low_bits
+    if per_x < 1 or L % per_x:
+        raise ValueError("per_x must divide 2^low_bits")
+    blk = L // per_x
+    rng = np.random.default_rng(seed)
+    xs = np.repeat(np.arange(N, dtype=np.int64), per_x)
+    j = np.tile(np.arange(per_x, dtype=np.int64), N)
+    high = rng.integers(0, N, size=N * per_x, dtype=np.int64) & ~np.int64(L - 1)
+    low = j * blk + rng.integers(0, blk, size=N * per_x, dtype=np.int64)
+    return xs.astype(np.uint32), (high | low).astype(np.uint32)
