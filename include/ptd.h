@@ -125,7 +125,9 @@ typedef void *ptd_stream;
 
 /* Workspace (device bytes) a pauli_decompose call with these arguments
  * needs: a few KiB of queue counters for dense decompositions with
- * n = 11..15 (one persistent launch), 0 otherwise.  Host-only, pure. */
+ * n = 11..15 (one persistent launch); for PTD_LOW_RANK with n >= 11 the
+ * factor's transpose, s * 2^n elements of dtype (the kernels read its
+ * columns contiguously); 0 otherwise.  Host-only, pure. */
 size_t ptd_workspace_bytes(int n, ptd_dtype dtype, unsigned flags, int s);
 
 /* Workspace (device bytes) a pauli_reconstruct call with these arguments
@@ -214,9 +216,10 @@ ptd_status ptd_workspace_status(const void *ws, size_t ws_bytes, ptd_stream stre
  * looks up that device's array.  Each call clears the counters it uses, but
  * all calls on one GPU share the array: calls that overlap in time on the
  * same GPU (other streams, other host threads) race and are not supported.
- * PTD_ENOSPC if the request needs more than PTD_NOALLOC_SCRATCH_BYTES
- * (no current request does).  A bounded wait that gives up leaves NaN in
- * the affected coefficients, as in pauli_decompose.
+ * PTD_ENOSPC if the request needs more than PTD_NOALLOC_SCRATCH_BYTES:
+ * the dense and structured paths never do; a PTD_LOW_RANK factor with
+ * n >= 11 does when rank * 2^n elements exceed it.  A bounded wait that
+ * gives up leaves NaN in the affected coefficients, as in pauli_decompose.
  */
 #define PTD_NOALLOC_SCRATCH_BYTES 65536
 ptd_status pauli_decompose_noalloc(int n, ptd_dtype dtype, unsigned flags, int s, const void *A, int64_t lda,

@@ -172,8 +172,12 @@ def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None
             flags = LOW_RANK | (HERMITIAN if hermitian else 0)
             odt = _real_dtype(code) if hermitian else _complex_dtype(code)
             out = _check_out(out, (N, N), odt, A.device)
-            st = _native.lib().pauli_decompose(n, code, flags, int(A.shape[1]), _ptr(A), _rows(A, "U"), _ptr(out),
-                                               None, 0, _stream_handle(A.device, stream))
+            L = _native.lib()
+            rank = int(A.shape[1])
+            wsb = L.ptd_workspace_bytes(n, code, flags, rank)
+            ws = torch.empty(wsb, dtype=torch.uint8, device=A.device) if wsb else None
+            st = L.pauli_decompose(n, code, flags, rank, _ptr(A), _rows(A, "U"), _ptr(out),
+                                   _ptr(ws) if ws is not None else None, wsb, _stream_handle(A.device, stream))
             _native.check(st, "pauli_decompose")
             return out
         if A.dim() != 1 or not A.is_contiguous():

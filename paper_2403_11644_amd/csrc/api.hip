@@ -110,6 +110,10 @@ size_t ptd_workspace_bytes(int n, ptd_dtype dtype, unsigned flags, int s)
 {
     (void)s;
     if (n < 1 || n > 16 || !valid_dtype(dtype)) return 0;
+    // a low-rank factor is staged transposed for the one-row-per-workgroup
+    // kernels (n >= 11): rank columns of 2^n values
+    if ((flags & PTD_LOW_RANK) && n >= 11 && s >= 1 && s <= ptd::LOWRANK_MAX)
+        return (size_t)s * ((size_t)1 << n) * elem_bytes(dtype);
     if (flags & (kStructure | PTD_ADJOINT | kMatrixFree)) return 0;
     if (use_fused(n, dtype, flags)) return ptd::fused_workspace_bytes(n, dtype);
     return 0;
@@ -214,7 +218,8 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
 {
     const ptd_status chk = ptd::decompose_check(n, dtype, flags, s, A, lda, coeff);
     if (chk != PTD_OK) return chk;
-    if (ws_bytes < ptd_workspace_bytes(n, dtype, flags, s)) return PTD_ENOSPC;
+    const size_t need = ptd_workspace_bytes(n, dtype, flags, s);
+    if (ws_bytes < need || (need && !ws)) return PTD_ENOSPC;
     if (ws && ws_bytes &&
         (overlap(ws, ws_bytes, A, decompose_in_bytes(n, dtype, flags, s, lda)) ||
          overlap(ws, ws_bytes, coeff, decompose_out_bytes(n, dtype, flags, s))))
@@ -227,6 +232,13 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
                                                    : ptd::SRC_LOWRANK;
         const int64_t ld = src == ptd::SRC_LOWRANK ? ptd::lowrank_ld(lda, s) : 0;
         if (n <= 10) return hip_status(ptd::launch_group_src(n, dtype, herm, src, A, ld, coeff, st));
+        if (src == ptd::SRC_LOWRANK) {
+            // factor columns contiguous in the workspace, then the rows
+            hipError_t e = ptd::launch_lowrank_transpose(n, dtype, A, lda, s, ws, st);
+            if (e != hipSuccess) return hip_status(e);
+            return hip_status(ptd::launch_mfree(n, dtype, herm, ptd::SRC_LOWRANK_T, ws, ptd::lowrank_ld(0, s), coeff,
+                                                st));
+        }
         return hip_status(ptd::launch_mfree(n, dtype, herm, src, A, ld, coeff, st));
     }
     if (flags & kStructure) {

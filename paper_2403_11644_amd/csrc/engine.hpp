@@ -163,6 +163,21 @@ __device__ __forceinline__ cplx<V> source_entry(const cplx<V>* __restrict__ A, i
             v.im += u.im * w.re - u.re * w.im;
         }
         return v;
+    } else if constexpr (SRC == SRC_LOWRANK_T) {
+        // the same products in the same order as SRC_LOWRANK, from the
+        // transposed factor: lanes over k read consecutive values
+        const int rank = (int)(lda & 63);
+        const int64_t N = (int64_t)1 << logn;
+        cplx<V> v;
+        v.re = (V)0;
+        v.im = (V)0;
+#pragma unroll 4
+        for (int j = 0; j < rank; ++j) {
+            const cplx<V> u = A[j * N + k], w = A[j * N + col];
+            v.re += u.re * w.re + u.im * w.im;
+            v.im += u.im * w.re - u.re * w.im;
+        }
+        return v;
     } else {
         return A[(int64_t)k * lda + col];
     }

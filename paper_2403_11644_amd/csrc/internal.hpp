@@ -21,6 +21,11 @@ constexpr int SRC_MATRIX = 0;
 constexpr int SRC_TOEPLITZ = 1;
 constexpr int SRC_PURE = 2;
 constexpr int SRC_LOWRANK = 3;
+// SRC_LOWRANK_T: the same mixed state from the factor's transpose
+// UT[j][r] = U[r][j] (column j of U contiguous, 2^n values), staged in the
+// workspace so that consecutive lanes (consecutive r) read consecutive
+// values; lowrank_ld carries the rank (pitch 2^n).
+constexpr int SRC_LOWRANK_T = 4;
 constexpr int LOWRANK_MAX = 32;
 inline int64_t lowrank_ld(int64_t pitch, int rank) { return (pitch << 6) | (int64_t)rank; }
 
@@ -126,6 +131,9 @@ hipError_t launch_group_src(int n, ptd_dtype dt, bool herm, int src, const void*
 // X-pattern, the row's transform in LDS (mfree.hip).
 hipError_t launch_mfree(int n, ptd_dtype dt, bool herm, int src, const void* t, int64_t ld, void* out,
                         hipStream_t st);
+// UT[j][r] = U[r][j] for r < 2^n, j < rank (U row-major with pitch ld).
+hipError_t launch_lowrank_transpose(int n, ptd_dtype dt, const void* U, int64_t ld, int rank, void* UT,
+                                    hipStream_t st);
 // Zero `count` uint32 words with a small kernel (capturable, unlike a memset node).
 hipError_t launch_zero_words(uint32_t* p, int count, hipStream_t st);
 // Plain 16-byte-per-lane device copy (bandwidth reference).

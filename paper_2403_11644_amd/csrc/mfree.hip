@@ -268,10 +268,37 @@ hipError_t mfree_src(int n, int src, const void* t, int64_t ld, void* out, hipSt
     if (src == SRC_TOEPLITZ) return mfree_t<V, REAL_OUT, SRC_TOEPLITZ>(n, t, ld, out, st);
     if (src == SRC_PURE) return mfree_t<V, REAL_OUT, SRC_PURE>(n, t, ld, out, st);
     if (src == SRC_LOWRANK) return mfree_t<V, REAL_OUT, SRC_LOWRANK>(n, t, ld, out, st);
+    if (src == SRC_LOWRANK_T) return mfree_t<V, REAL_OUT, SRC_LOWRANK_T>(n, t, ld, out, st);
     return hipErrorInvalidValue;
 }
 
+template <class V>
+__global__ void k_lowrank_transpose(const cplx<V>* __restrict__ U, int64_t ld, int rank, int logn,
+                                    cplx<V>* __restrict__ UT)
+{
+    const int64_t N = (int64_t)1 << logn;
+    const int64_t total = N * rank;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = i >> logn, r = i & (N - 1);  // consecutive threads write consecutive r
+        UT[i] = U[r * ld + j];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_lowrank_transpose(int n, ptd_dtype dt, const void* U, int64_t ld, int rank, void* UT,
+                                    hipStream_t st)
+{
+    const int64_t total = ((int64_t)1 << n) * rank;
+    const int blocks = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+    if (dt == PTD_C128)
+        hipLaunchKernelGGL(k_lowrank_transpose<double>, dim3(blocks), dim3(256), 0, st, (const cplx<double>*)U, ld,
+                           rank, n, (cplx<double>*)UT);
+    else
+        hipLaunchKernelGGL(k_lowrank_transpose<float>, dim3(blocks), dim3(256), 0, st, (const cplx<float>*)U, ld,
+                           rank, n, (cplx<float>*)UT);
+    return hipGetLastError();
+}
 
 hipError_t launch_mfree(int n, ptd_dtype dt, bool herm, int src, const void* t, int64_t ld, void* out,
                         hipStream_t st)

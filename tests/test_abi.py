@@ -365,7 +365,11 @@ def test_toeplitz_argument_errors(lib):
     assert lr(8, api.LOW_RANK | api.DIAGONAL, 2, 2) == EUNSUP
     assert lr(15, api.LOW_RANK, 2, 2) == EUNSUP
     assert lr(16, api.LOW_RANK, 2, 2) == EUNSUP
-    assert lib.ptd_workspace_bytes(14, api.C128, api.LOW_RANK, 2) == 0
+    # n >= 11: the factor's transpose is staged in the workspace
+    assert lib.ptd_workspace_bytes(14, api.C128, api.LOW_RANK, 2) == 2 * (1 << 14) * 16
+    assert lib.ptd_workspace_bytes(15, api.C64, api.LOW_RANK | api.HERMITIAN, 32) == 32 * (1 << 15) * 8
+    assert lib.ptd_workspace_bytes(10, api.C128, api.LOW_RANK, 2) == 0
+    assert lr(12, api.LOW_RANK, 2, 2) == -2  # no workspace given
 
 
 def test_to_dict():
