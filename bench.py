@@ -588,6 +588,10 @@ def main() -> int:
                                                            api._ptr(wsd), wsb_, sh), "pauli_decompose")
 
         band_legs = {}
+        # cold calls: a 1 GiB write before each one evicts the inputs from the
+        # L2 and the memory-side cache (inputs here are far below 256 MB)
+        flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        cold = lambda: flush.fill_(1)
         for name, s_, arr in (("diag", 0, synth.bands_from_diag(synth.diagonal_real(n, seed=0))),
                               ("tridiag", 1, synth.bands_from_tridiag(*synth.tridiag_real_sym(n, seed=1))),
                               ("band8", 8, synth.banded_complex(n, 8, seed=2))):
@@ -596,11 +600,15 @@ def main() -> int:
             bd = torch.from_numpy(arr).to(dev)
             bout = torch.empty((cnt, N), dtype=torch.complex128, device=dev)
             us = _call_us(skip_call(bd, flags, s_, bout, N), 20, 5, stream)
+            us_cold = _call_us(skip_call(bd, flags, s_, bout, N), 10, 2, stream, before=cold)
             band_legs[name] = {"s": s_, "nonempty_x": cnt, "from_bands_compact_us": round(us, 2),
+                               "from_bands_compact_cold_us": round(us_cold, 2),
                                "computed_GCoeff_s": round(cnt * N / us / 1e3, 2)}
             if s_ == 8:
                 fl = api.BANDED | api.COMPACT
                 us_dc = _call_us(skip_call(A, fl, 8, bout, N), 20, 5, stream)
+                band_legs[name]["from_dense_compact_cold_us"] = round(
+                    _call_us(skip_call(A, fl, 8, bout, N), 10, 2, stream, before=cold), 2)
                 us_dd = _call_us(skip_call(A, api.BANDED, 8, out128, N), 10, 3, stream)
                 band_legs[name].update({"from_dense_compact_us": round(us_dc, 2),
                                         "from_dense_zero_filled_us": round(us_dd, 2),
@@ -609,8 +617,10 @@ def main() -> int:
         # anti-diagonal: the one X-pattern 2^n - 1, from the vector A[k][N-1-k]
         adv = torch.from_numpy(synth.antidiagonal_complex(n, seed=3).reshape(1, N).copy()).to(dev)
         aout = torch.empty((1, N), dtype=torch.complex128, device=dev)
-        us = _call_us(skip_call(adv, api.ANTIDIAGONAL | api.BANDS_IN | api.COMPACT, 0, aout, N), 20, 5, stream)
-        band_legs["antidiag"] = {"nonempty_x": 1, "from_vector_compact_us": round(us, 2)}
+        anti = skip_call(adv, api.ANTIDIAGONAL | api.BANDS_IN | api.COMPACT, 0, aout, N)
+        us = _call_us(anti, 20, 5, stream)
+        band_legs["antidiag"] = {"nonempty_x": 1, "from_vector_compact_us": round(us, 2),
+                                 "from_vector_compact_cold_us": round(_call_us(anti, 10, 2, stream, before=cold), 2)}
         del adv, aout
         # sparse coordinate input: 7 entries per row within distance 3 of the
         # diagonal plus 64 scattered ones; the call lists its X-patterns and
@@ -624,10 +634,12 @@ def main() -> int:
         cd = torch.from_numpy(c.astype(np.int32)).to(dev)
         vd = torch.randn(r.shape[0], dtype=torch.complex128, device=dev, generator=g)
         sp_out, sp_xs = ptd.decompose_sparse(rd, cd, vd, n, compact=True)
-        us = _call_us(lambda: ptd.decompose_sparse(rd, cd, vd, n, compact=True, out=sp_out), 10, 3, stream)
+        sp_call = lambda: ptd.decompose_sparse(rd, cd, vd, n, compact=True, out=sp_out)
+        us = _call_us(sp_call, 10, 3, stream)
         band_legs["sparse"] = {"nnz": int(r.shape[0]), "nonempty_x": int(sp_xs.numel()),
-                               "call_compact_us": round(us, 2)}
-        del rd, cd, vd, sp_out, sp_xs
+                               "call_compact_us": round(us, 2),
+                               "call_compact_cold_us": round(_call_us(sp_call, 5, 1, stream, before=cold), 2)}
+        del rd, cd, vd, sp_out, sp_xs, flush
         legs["structured_n14"] = band_legs
     if "toeplitz" in want_legs:
         _progress("leg toeplitz")

@@ -82,8 +82,12 @@ typedef void *ptd_stream;
  * twice the bytes of the default path).  PTD_EUNSUP with structure flags;
  * PTD_EUNSUP for PTD_C128. */
 #define PTD_COMPENSATED (1u << 5)
-/* pauli_reconstruct only: multiply the result by 2^-n, which makes the call
- * the adjoint (vector-Jacobian product) of pauli_decompose. */
+/* Adjoint pairs.  pauli_reconstruct: multiply the result by 2^-n, which
+ * makes the call the adjoint (vector-Jacobian product) of pauli_decompose.
+ * pauli_decompose (dense input only; not with a structure, a matrix-free
+ * kind or PTD_COMPENSATED): leave out the 2^-n, i.e. coeff = Tr(P A), the
+ * adjoint of pauli_reconstruct.  The scale is an exact power of two either
+ * way. */
 #define PTD_ADJOINT (1u << 6)
 /* ptd_batch_plan_create only: the plan reconstructs (coefficients -> matrices). */
 #define PTD_PLAN_RECONSTRUCT (1u << 7)
@@ -154,7 +158,8 @@ ptd_status ptd_nonempty_x(int n, unsigned flags, int s, uint32_t *xs_host);
  *   n        number of qubits, 1..16
  *   dtype    element type of A (and of coeff unless PTD_HERMITIAN)
  *   flags    PTD_HERMITIAN | PTD_DIAGONAL | PTD_BANDED | PTD_ANTIDIAGONAL |
- *            PTD_BANDS_IN | PTD_COMPACT | PTD_COMPENSATED, or one of the
+ *            PTD_BANDS_IN | PTD_COMPACT | PTD_COMPENSATED | PTD_ADJOINT
+ *            (unscaled Tr(P A), dense input only), or one of the
  *            matrix-free kinds PTD_TOEPLITZ | PTD_PURE_STATE | PTD_LOW_RANK
  *            (with PTD_HERMITIAN at most)
  *   s        half-bandwidth for PTD_BANDED (>= 1), the factor's rank for
@@ -437,6 +442,18 @@ void ptd_clear_tuning(void);
  */
 ptd_status ptd_host_tree_decompose(int n, unsigned flags, const void *A, int64_t lda, void *coeff_out, int split,
                                    int64_t tree_begin, int64_t tree_end, int threads, uint64_t *ops_out);
+
+/*
+ * ptd_zero_pad: the zero padding of a matrix whose size is not a power of
+ * two (the decomposition formula of Sec. II-A needs 2^n x 2^n; the paper
+ * pads with zeros without fixing where the matrix goes).  dst (2^n x 2^n,
+ * contiguous, dtype elements) receives src (rows x cols, row pitch ld >=
+ * cols) in its top-left corner and zeros elsewhere; 1 <= rows, cols <= 2^n.
+ * Both device memory, disjoint (PTD_EINVAL otherwise).  Asynchronous on
+ * `stream`.
+ */
+ptd_status ptd_zero_pad(ptd_dtype dtype, const void *src, int64_t ld, int64_t rows, int64_t cols, void *dst, int n,
+                        ptd_stream stream);
 
 /* Human-readable name of a status code (static string). */
 const char *ptd_status_str(ptd_status st);

@@ -93,20 +93,29 @@ def _rows(t: torch.Tensor, name: str) -> int:
     return t.stride(0) if t.shape[0] > 1 else t.shape[1]
 
 
-def pad_to_power_of_two(A: torch.Tensor) -> torch.Tensor:
+def pad_to_power_of_two(A: torch.Tensor, stream=None) -> torch.Tensor:
     """Embed A top-left in the smallest 2^n x 2^n zero matrix (n >= 1).
 
     The paper allows zero padding to reach a power-of-two size (Sec. II-A)
     without fixing where A goes; this library puts it in the top-left block.
-    """
+    The padded copy is written by the library's ptd_zero_pad kernel."""
     r, c = A.shape
     N = 2
     while N < max(r, c):
         N *= 2
     if (r, c) == (N, N):
         return A
-    out = torch.zeros((N, N), dtype=A.dtype, device=A.device)
-    out[:r, :c] = A
+    _require_device(A, "A")
+    code = _dtype_code(A.dtype)
+    n = N.bit_length() - 1
+    if stream is not None:
+        with torch.cuda.stream(stream):
+            out = torch.empty((N, N), dtype=A.dtype, device=A.device)
+    else:
+        out = torch.empty((N, N), dtype=A.dtype, device=A.device)
+    st = _native.lib().ptd_zero_pad(code, _ptr(A), _rows(A, "A"), r, c, _ptr(out), n,
+                                    _stream_handle(A.device, stream))
+    _native.check(st, "ptd_zero_pad")
     return out
 
 
@@ -133,7 +142,8 @@ def nonempty_x(n: int, structure: str | None = None, s: int = 0) -> list[int]:
 def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None = None, s: int | None = None,
               bands: bool = False, compact: bool = False, compensated: bool = False, pad: bool = False,
               toeplitz: bool = False, pure_state: bool = False, low_rank: bool = False,
-              out: torch.Tensor | None = None, check: bool = False, stream=None) -> torch.Tensor:
+              adjoint: bool = False, out: torch.Tensor | None = None, check: bool = False,
+              stream=None) -> torch.Tensor:
     """Pauli coefficients of A, as a (2^n, 2^n) tensor c[x, z].
 
     hermitian   A == A^*: return the (real) coefficients as float64/float32.
@@ -152,6 +162,8 @@ def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None
     low_rank    A is a 2^n x r factor U (r <= 32, rows contiguous) and the
                 matrix is the mixed state U U^* (matrix-free): the
                 coefficients are sum_j <u_j|P|u_j> / 2^n over its columns.
+    adjoint     dense input only: Tr(P A) without the 2^-n, the adjoint of
+                reconstruct (used by autograd).
     check       wait for the call and raise if the one-launch schedule's
                 exchange did not complete (its coefficients are then NaN;
                 see ptd_workspace_status).  Off by default: the call stays
@@ -162,7 +174,7 @@ def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None
     if toeplitz or pure_state or low_rank:
         if int(toeplitz) + int(pure_state) + int(low_rank) > 1:
             raise ValueError("toeplitz, pure_state and low_rank exclude each other")
-        if structure is not None or bands or pad or compact or compensated:
+        if structure is not None or bands or pad or compact or compensated or adjoint:
             raise ValueError("matrix-free input takes a dense decomposition only")
         if low_rank:
             if A.dim() != 2 or not 1 <= A.shape[1] <= 32:
@@ -221,7 +233,7 @@ def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None
             raise ValueError("band array must have 2s+1 rows")
     else:
         if pad:
-            A = pad_to_power_of_two(A)
+            A = pad_to_power_of_two(A, stream=stream)
         if A.dim() != 2 or A.shape[0] != A.shape[1]:
             raise ValueError("A must be square")
         N = A.shape[0]
@@ -234,6 +246,8 @@ def decompose(A: torch.Tensor, *, hermitian: bool = False, structure: str | None
         flags |= COMPACT
     if compensated:
         flags |= COMPENSATED
+    if adjoint:
+        flags |= ADJOINT
     lda = _rows(A, "A")
     rows = num_nonempty_x(n, structure, sv) if compact else N
     odt = _real_dtype(code) if hermitian else _complex_dtype(code)

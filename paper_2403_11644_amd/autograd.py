@@ -4,7 +4,8 @@ decompose is linear: c = M vec(A) with M[P, (r, c)] = 2^-n P[c][r], so its
 vector-Jacobian product (PyTorch's convention for complex tensors: the
 gradient with respect to conj(A)) is M^H g = 2^-n sum_P g_P P -- the
 reconstruction kernel with the PTD_ADJOINT scale.  Reconstruction
-A = sum_P c_P P has adjoint 2^n M, i.e. 2^n times the decomposition.
+A = sum_P c_P P has adjoint 2^n M, i.e. the decomposition without its
+2^-n scale (PTD_ADJOINT of pauli_decompose).
 """
 from __future__ import annotations
 
@@ -28,7 +29,7 @@ class PauliDecompose(torch.autograd.Function):
 
 class PauliReconstruct(torch.autograd.Function):
     """A = reconstruct(c) for dense complex coefficients; backward runs the
-    decomposition kernel scaled by 2^n."""
+    decomposition kernel without its 2^-n scale."""
 
     @staticmethod
     def forward(ctx, c: torch.Tensor) -> torch.Tensor:
@@ -36,7 +37,7 @@ class PauliReconstruct(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g: torch.Tensor) -> torch.Tensor:
-        return api.decompose(g.contiguous()) * float(g.shape[0])
+        return api.decompose(g.contiguous(), adjoint=True)
 
 
 def pauli_decompose(A: torch.Tensor) -> torch.Tensor:

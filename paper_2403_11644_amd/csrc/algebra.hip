@@ -95,6 +95,24 @@ __global__ __launch_bounds__(ALG_THREADS) void k_zero16(uint4* __restrict__ p, i
         p[i] = zero;
 }
 
+// dst (2^n x 2^n, contiguous) = src (rows x cols at pitch ld) in the
+// top-left corner, zero elsewhere.
+template <class V>
+__global__ __launch_bounds__(ALG_THREADS) void k_zero_pad(const cplx<V>* __restrict__ src, int64_t ld, int64_t rows,
+                                                         int64_t cols, int n, cplx<V>* __restrict__ dst)
+{
+    const int64_t N = (int64_t)1 << n;
+    const int64_t total = N * N;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i >> n, c = i & (N - 1);
+        cplx<V> v;
+        v.re = (V)0;
+        v.im = (V)0;
+        if (r < rows && c < cols) v = src[r * ld + c];
+        dst[i] = v;
+    }
+}
+
 // Zero `bytes` (a multiple of 16) at p.
 hipError_t zero_bytes(void* p, int64_t bytes, hipStream_t st)
 {
@@ -151,6 +169,18 @@ hipError_t launch_hermitian_augment(int n, ptd_dtype dt, bool compact, const voi
 {
     return dt == PTD_C128 ? herm_augment_t<double>(n, compact, in, out, st)
                           : herm_augment_t<float>(n, compact, in, out, st);
+}
+
+hipError_t launch_zero_pad(ptd_dtype dt, const void* src, int64_t ld, int64_t rows, int64_t cols, int n, void* dst,
+                           hipStream_t st)
+{
+    if (dt == PTD_C128)
+        hipLaunchKernelGGL(k_zero_pad<double>, dim3(alg_grid()), dim3(ALG_THREADS), 0, st, (const cplx<double>*)src, ld,
+                           rows, cols, n, (cplx<double>*)dst);
+    else
+        hipLaunchKernelGGL(k_zero_pad<float>, dim3(alg_grid()), dim3(ALG_THREADS), 0, st, (const cplx<float>*)src, ld,
+                           rows, cols, n, (cplx<float>*)dst);
+    return hipGetLastError();
 }
 
 hipError_t launch_linear_combination(int n, ptd_dtype dt, double mu_re, double mu_im, const void* a, const void* b,

@@ -114,7 +114,7 @@ size_t ptd_workspace_bytes(int n, ptd_dtype dtype, unsigned flags, int s)
     // kernels (n >= 11): rank columns of 2^n values
     if ((flags & PTD_LOW_RANK) && n >= 11 && s >= 1 && s <= ptd::LOWRANK_MAX)
         return (size_t)s * ((size_t)1 << n) * elem_bytes(dtype);
-    if (flags & (kStructure | PTD_ADJOINT | kMatrixFree)) return 0;
+    if (flags & (kStructure | kMatrixFree)) return 0;
     if (use_fused(n, dtype, flags)) return ptd::fused_workspace_bytes(n, dtype);
     return 0;
 }
@@ -169,7 +169,8 @@ ptd_status decompose_check(int n, ptd_dtype dtype, unsigned flags, int s, const 
 {
     if (n < 1 || n > 16 || !valid_dtype(dtype) || !A || !coeff) return PTD_EINVAL;
     if (flags & ~kAllFlags) return PTD_EINVAL;
-    if (flags & PTD_ADJOINT) return PTD_EINVAL;
+    // unscaled traces (the adjoint of reconstruction): dense input only
+    if ((flags & PTD_ADJOINT) && (flags & (kStructure | kMatrixFree | PTD_COMPENSATED))) return PTD_EINVAL;
     const ptd_status sst = check_structure(n, flags, s);
     if (sst != PTD_OK) return sst;
     // matrix-free input: a defining vector or factor instead of the matrix
@@ -253,9 +254,10 @@ ptd_status pauli_decompose(int n, ptd_dtype dtype, unsigned flags, int s, const 
         if (!ws) return PTD_ENOSPC;
         ptd::FusedTuning t = ptd::fused_default(n, dtype, herm);
         (void)ptd::get_fused_tuning(n, dtype, herm, &t);
-        return hip_status(ptd::launch_fused_fwd(n, dtype, herm, A, lda, coeff, ws, t.la, t.cfg, st));
+        return hip_status(ptd::launch_fused_fwd(n, dtype, herm, A, lda, coeff, ws, t.la, t.cfg, st,
+                                                (flags & PTD_ADJOINT) != 0));
     }
-    return hip_status(ptd::launch_dense_fwd(n, dtype, herm, A, lda, coeff, 0, st));
+    return hip_status(ptd::launch_dense_fwd(n, dtype, herm, A, lda, coeff, 0, st, (flags & PTD_ADJOINT) != 0));
 }
 
 size_t ptd_reconstruct_workspace_bytes(int n, ptd_dtype dtype, unsigned flags)
@@ -380,6 +382,16 @@ ptd_status ptd_linear_combination(int n, ptd_dtype dtype, double mu_re, double m
     if ((c_out != ca && overlap(ca, bytes, c_out, bytes)) || (c_out != cb && overlap(cb, bytes, c_out, bytes)))
         return PTD_EINVAL;
     return hip_status(ptd::launch_linear_combination(n, dtype, mu_re, mu_im, ca, cb, c_out, (hipStream_t)stream));
+}
+
+ptd_status ptd_zero_pad(ptd_dtype dtype, const void* src, int64_t ld, int64_t rows, int64_t cols, void* dst,
+                        int n, ptd_stream stream)
+{
+    if (!valid_dtype(dtype) || !src || !dst || n < 1 || n > 16) return PTD_EINVAL;
+    if (rows < 1 || cols < 1 || rows > ((int64_t)1 << n) || cols > ((int64_t)1 << n) || ld < cols) return PTD_EINVAL;
+    const size_t eb = elem_bytes(dtype);
+    if (overlap(src, span_bytes(rows, cols, ld, eb), dst, ((size_t)1 << (2 * n)) * eb)) return PTD_EINVAL;
+    return hip_status(ptd::launch_zero_pad(dtype, src, ld, rows, cols, n, dst, (hipStream_t)stream));
 }
 
 size_t ptd_sparse_workspace_bytes(int n)

@@ -77,7 +77,7 @@ __device__ __forceinline__ void batched_item(const void* __restrict__ in_base, v
     if constexpr (!REC) {
         const cplx<V>* A = (const cplx<V>*)in_base + m.in_off;
         void* out = HERM ? (void*)((V*)out_base + m.out_off) : (void*)((cplx<V>*)out_base + m.out_off);
-        group_fwd<V, NN, LOGT, HERM, SMALL_NT, 4>(A, N, out, N, g, lds);
+        group_fwd<V, NN, LOGT, HERM, SMALL_NT, 4>(A, N, out, N, g, lds, exp2_neg<V>(NN));
     } else {
         const void* C = HERM ? (const void*)((const V*)in_base + m.in_off)
                              : (const void*)((const cplx<V>*)in_base + m.in_off);
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(NT, (NT / 256) * (NT == 512 ? wgs_per_cu<V, NN>() :
             if constexpr (!REC) {
                 const cplx<V>* A = (const cplx<V>*)in_base + m.in_off;
                 void* out = HERM ? (void*)((V*)out_base + m.out_off) : (void*)((cplx<V>*)out_base + m.out_off);
-                group_fwd<V, NN, LOGT, HERM, NT, RMAX>(A, N, out, N, g, lds);
+                group_fwd<V, NN, LOGT, HERM, NT, RMAX>(A, N, out, N, g, lds, exp2_neg<V>(NN));
             } else {
                 const void* C = HERM ? (const void*)((const V*)in_base + m.in_off)
                                      : (const void*)((const cplx<V>*)in_base + m.in_off);

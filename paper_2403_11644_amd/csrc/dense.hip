@@ -71,11 +71,11 @@ constexpr int row_threads()
 
 template <class V, int LOGN, bool REAL_OUT, int NT, int RMAX, int SRC = SRC_MATRIX>
 __global__ __launch_bounds__(NT) void k_group_fwd(const cplx<V>* __restrict__ A, int64_t lda,
-                                                  void* __restrict__ out, int64_t ldo)
+                                                  void* __restrict__ out, int64_t ldo, V scale)
 {
     constexpr int LOGT = group_logt<V>(LOGN);
     __shared__ cplx<V> lds[(1 << LOGT) * ((1 << LOGN) + 1)];
-    group_fwd<V, LOGN, LOGT, REAL_OUT, NT, RMAX, SRC>(A, lda, out, ldo, blockIdx.x, lds);
+    group_fwd<V, LOGN, LOGT, REAL_OUT, NT, RMAX, SRC>(A, lda, out, ldo, blockIdx.x, lds, scale);
 }
 
 template <class V, int LOGN, bool REAL_IN>
@@ -152,7 +152,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_tile_fwd(const cplx<V>* __rest
 // pass 2: WHT over the block index (stride 64) of each output row chunk,
 // then the phase and the scale.
 template <class V, int LOGM, bool HERM, bool COMP>
-__global__ __launch_bounds__((row_threads<LOGM, COMP>())) void k_high_fwd(void* __restrict__ out, int64_t ldo, int x0)
+__global__ __launch_bounds__((row_threads<LOGM, COMP>())) void k_high_fwd(void* __restrict__ out, int64_t ldo, int x0,
+                                                                                               V scale)
 {
     constexpr int LOGW = row_logw<V, LOGM, COMP>();
     constexpr int CH = 6 - LOGW;
@@ -164,7 +165,6 @@ __global__ __launch_bounds__((row_threads<LOGM, COMP>())) void k_high_fwd(void* 
     const int xh = x >> 6, xl = x & 63;
     V* rowr = (V*)out + (int64_t)x * ldo;
     cplx<V>* rowc = (cplx<V>*)out + (int64_t)x * ldo;
-    const V scale = exp2_neg<V>(LOGM + 6);
     auto load = [&](int vec, int pos, V& re, V& im) {
         const int zl = z0 + vec;
         if constexpr (HERM) {
@@ -367,13 +367,13 @@ __global__ __launch_bounds__(TILE_THREADS) void k_small_comp(const cplx<V>* __re
 // dispatch over n (compile-time sizes)
 
 template <class V, bool HERM, int NT, int RMAX>
-hipError_t fwd_group_plan(int n, const cplx<V>* a, int64_t lda, void* out, int64_t ldo, hipStream_t st)
+hipError_t fwd_group_plan(int n, const cplx<V>* a, int64_t lda, void* out, int64_t ldo, V scale, hipStream_t st)
 {
     const int logt = group_logt<V>(n);
     const dim3 grid(1u << (n - logt)), block(NT);
     switch (n) {
 #define PTD_CASE(NN) \
-    case NN: hipLaunchKernelGGL((k_group_fwd<V, NN, HERM, NT, RMAX>), grid, block, 0, st, a, lda, out, ldo); break;
+    case NN: hipLaunchKernelGGL((k_group_fwd<V, NN, HERM, NT, RMAX>), grid, block, 0, st, a, lda, out, ldo, scale); break;
         PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5)
         PTD_CASE(6) PTD_CASE(7) PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
 #undef PTD_CASE
@@ -384,24 +384,27 @@ hipError_t fwd_group_plan(int n, const cplx<V>* a, int64_t lda, void* out, int64
 
 // plan: see group.hpp (workgroup size, widest round); radix 32 is complex64 only
 template <class V, bool HERM>
-hipError_t fwd_group(int n, const void* A, int64_t lda, void* out, int plan, hipStream_t st)
+hipError_t fwd_group(int n, const void* A, int64_t lda, void* out, int plan, hipStream_t st, bool unscaled = false)
 {
     const cplx<V>* a = (const cplx<V>*)A;
     const int64_t ldo = (int64_t)1 << n;
     const bool big = group_plan_nt(plan) == 1024;
+    const V scale = unscaled ? (V)1 : (V)1 / (V)(1u << n);
     if constexpr (sizeof(V) == 4) {
         if (group_effective_rmax(n, PTD_C64, plan) == 5)
-            return big ? fwd_group_plan<V, HERM, 1024, 5>(n, a, lda, out, ldo, st)
-                       : fwd_group_plan<V, HERM, 512, 5>(n, a, lda, out, ldo, st);
+            return big ? fwd_group_plan<V, HERM, 1024, 5>(n, a, lda, out, ldo, scale, st)
+                       : fwd_group_plan<V, HERM, 512, 5>(n, a, lda, out, ldo, scale, st);
     }
-    return big ? fwd_group_plan<V, HERM, 1024, 4>(n, a, lda, out, ldo, st)
-               : fwd_group_plan<V, HERM, 512, 4>(n, a, lda, out, ldo, st);
+    return big ? fwd_group_plan<V, HERM, 1024, 4>(n, a, lda, out, ldo, scale, st)
+               : fwd_group_plan<V, HERM, 512, 4>(n, a, lda, out, ldo, scale, st);
 }
 
 // stage: 3 = both passes, 1 = tile pass only, 2 = row pass only (timing)
 template <class V, bool HERM, bool COMP = false>
-hipError_t fwd_two_pass(int n, const void* A, int64_t lda, void* out, hipStream_t st, int stage = 3)
+hipError_t fwd_two_pass(int n, const void* A, int64_t lda, void* out, hipStream_t st, int stage = 3,
+                        bool unscaled = false)
 {
+    const V scale = unscaled ? (V)1 : (V)1 / (V)(1u << n);
     const cplx<V>* a = (const cplx<V>*)A;
     const int64_t ldo = (int64_t)1 << n;
     const int nb = 1 << (n - 6);
@@ -428,7 +431,7 @@ hipError_t fwd_two_pass(int n, const void* A, int64_t lda, void* out, hipStream_
     case MM:                                                                                                      \
         hipLaunchKernelGGL((k_high_fwd<V, MM, HERM, COMP>),                                                       \
                            dim3((unsigned)(((int64_t)cnt * 64) << (6 - row_logw<V, MM, COMP>()))),                \
-                           dim3(row_threads<MM, COMP>()), 0, st, out, ldo, x0);                                   \
+                           dim3(row_threads<MM, COMP>()), 0, st, out, ldo, x0, scale);                            \
         break;
             PTD_CASE(1) PTD_CASE(2) PTD_CASE(3) PTD_CASE(4) PTD_CASE(5)
             PTD_CASE(6) PTD_CASE(7) PTD_CASE(8) PTD_CASE(9) PTD_CASE(10)
@@ -482,18 +485,24 @@ hipError_t rec_two_pass(int n, const void* coeff, void* A, int64_t lda, V scale,
 }  // namespace
 
 hipError_t launch_dense_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out, int path,
-                            hipStream_t st)
+                            hipStream_t st, bool unscaled)
 {
     const bool two = path == 2 ? true : path == 1 ? false : n > 10;
     if (two && n < 7) return hipErrorInvalidValue;
     if (!two && n > 10) return hipErrorInvalidValue;
     const int plan = two ? 0 : group_plan(n, dt, herm);
+    const bool u = unscaled;
     if (dt == PTD_C128) {
-        if (two) return herm ? fwd_two_pass<double, true>(n, A, lda, out, st) : fwd_two_pass<double, false>(n, A, lda, out, st);
-        return herm ? fwd_group<double, true>(n, A, lda, out, plan, st) : fwd_group<double, false>(n, A, lda, out, plan, st);
+        if (two)
+            return herm ? fwd_two_pass<double, true>(n, A, lda, out, st, 3, u)
+                        : fwd_two_pass<double, false>(n, A, lda, out, st, 3, u);
+        return herm ? fwd_group<double, true>(n, A, lda, out, plan, st, u)
+                    : fwd_group<double, false>(n, A, lda, out, plan, st, u);
     }
-    if (two) return herm ? fwd_two_pass<float, true>(n, A, lda, out, st) : fwd_two_pass<float, false>(n, A, lda, out, st);
-    return herm ? fwd_group<float, true>(n, A, lda, out, plan, st) : fwd_group<float, false>(n, A, lda, out, plan, st);
+    if (two)
+        return herm ? fwd_two_pass<float, true>(n, A, lda, out, st, 3, u)
+                    : fwd_two_pass<float, false>(n, A, lda, out, st, 3, u);
+    return herm ? fwd_group<float, true>(n, A, lda, out, plan, st, u) : fwd_group<float, false>(n, A, lda, out, plan, st, u);
 }
 
 hipError_t launch_dense_fwd_stage(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out, int stage,
@@ -555,10 +564,10 @@ hipError_t group_src_t(int n, bool herm, const void* src, int64_t ld, void* out,
     case NN:                                                                                                  \
         if (herm)                                                                                             \
             hipLaunchKernelGGL((k_group_fwd<V, NN, true, 512, 4, SRC>), grid, dim3(512), 0, st,               \
-                               (const cplx<V>*)src, ld, out, (int64_t)N);                                     \
+                               (const cplx<V>*)src, ld, out, (int64_t)N, (V)1 / (V)(1u << NN));                    \
         else                                                                                                  \
             hipLaunchKernelGGL((k_group_fwd<V, NN, false, 512, 4, SRC>), grid, dim3(512), 0, st,              \
-                               (const cplx<V>*)src, ld, out, (int64_t)N);                                     \
+                               (const cplx<V>*)src, ld, out, (int64_t)N, (V)1 / (V)(1u << NN));                    \
         break;
         PTD_T(1) PTD_T(2) PTD_T(3) PTD_T(4) PTD_T(5) PTD_T(6) PTD_T(7) PTD_T(8) PTD_T(9) PTD_T(10)
 #undef PTD_T

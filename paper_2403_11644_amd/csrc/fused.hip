@@ -130,14 +130,14 @@ size_t fused_workspace_bytes(int n, ptd_dtype dt)
 }
 
 hipError_t launch_fused_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out, void* ws, int la,
-                            int cfg, hipStream_t st)
+                            int cfg, hipStream_t st, bool unscaled)
 {
     if (n < 11 || n > 15 || la < 1) return hipErrorInvalidValue;
     if (dt == PTD_C128)
-        return herm ? fused_launch_c128_herm(n, A, lda, out, ws, la, cfg, st)
-                    : fused_launch_c128(n, A, lda, out, ws, la, cfg, st);
-    return herm ? fused_launch_c64_herm(n, A, lda, out, ws, la, cfg, st)
-                : fused_launch_c64(n, A, lda, out, ws, la, cfg, st);
+        return herm ? fused_launch_c128_herm(n, A, lda, out, ws, la, cfg, unscaled, st)
+                    : fused_launch_c128(n, A, lda, out, ws, la, cfg, unscaled, st);
+    return herm ? fused_launch_c64_herm(n, A, lda, out, ws, la, cfg, unscaled, st)
+                : fused_launch_c64(n, A, lda, out, ws, la, cfg, unscaled, st);
 }
 
 hipError_t launch_fused_rec(int n, ptd_dtype dt, bool herm, bool adjoint, const void* coeff, void* A, int64_t lda,

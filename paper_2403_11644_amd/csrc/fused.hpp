@@ -93,6 +93,13 @@ __device__ __forceinline__ bool bounded_wait(uint32_t* __restrict__ ws, int word
     return true;
 }
 
+// 2^-n on the host (exact power of two).
+template <class V>
+inline V exp2_neg_host(int n)
+{
+    return (V)1 / (V)(1u << n);
+}
+
 // cache-policy bits
 constexpr int POL_NT_GATHER = 1;
 constexpr int POL_NT_STORE = 2;
@@ -341,7 +348,7 @@ __device__ __forceinline__ V swap_halves(V v)
 }
 
 template <class V, class S, bool HERM, int POL>
-__device__ __forceinline__ void phase2(void* __restrict__ out, int g, int sub, cplx<V>* lds, bool poison)
+__device__ __forceinline__ void phase2(void* __restrict__ out, int g, int sub, cplx<V>* lds, bool poison, V unit)
 {
     constexpr int KAP = S::KAP, NB2 = S::NB2;
     constexpr int N = 1 << S::LOGN;
@@ -351,7 +358,7 @@ __device__ __forceinline__ void phase2(void* __restrict__ out, int g, int sub, c
     const uint32_t x = ((uint32_t)g << S::LOGT) | (uint32_t)r;
     // a group whose partial results never all arrived: every value of the
     // item becomes NaN (the scale is multiplied into every stored value)
-    const V scale = poison ? __builtin_nan("") : exp2_neg<V>(S::LOGN);
+    const V scale = poison ? __builtin_nan("") : unit;
     const int64_t rowo = (int64_t)x * N;
     if constexpr (S::STASH) {
         // 32 values per position: the first 16 take a 16-point transform and
@@ -450,7 +457,7 @@ template <class V, class S, bool HERM, int POL>
 // at least 4 waves per SIMD: two 512-thread workgroups fit on one CU
 __global__ __launch_bounds__(S::NT, 4) void k_fused_fwd(const cplx<V>* __restrict__ A, int64_t lda,
                                                      void* __restrict__ out, uint32_t* __restrict__ ws, int Q,
-                                                     int LA, WaitLimits wl)
+                                                     int LA, WaitLimits wl, V unit)
 {
     constexpr int NP1 = S::NP1, NP2 = S::NP2, NG = S::NG;
     __shared__ cplx<V> lds[(1 << S::LOGT) * ((1 << S::KAP) + 1)];
@@ -486,7 +493,7 @@ __global__ __launch_bounds__(S::NT, 4) void k_fused_fwd(const cplx<V>* __restric
                 publish(it.group);
             } else {
                 const bool failed = wait_group(it.group);
-                phase2<V, S, HERM, POL>(out, it.group, it.sub, lds, failed);
+                phase2<V, S, HERM, POL>(out, it.group, it.sub, lds, failed, unit);
             }
             __syncthreads();  // LDS reuse, s_next reuse
             if (threadIdx.x == 0)
@@ -716,7 +723,7 @@ hipError_t fused_rec_dispatch(int n, const void* coeff, void* A, int64_t lda, vo
 }
 
 template <class V, int LOGN, int KAP, int NT, int LOGT, bool HERM, int POL>
-hipError_t launch_cfg(const void* A, int64_t lda, void* out, void* ws, int la, hipStream_t st)
+hipError_t launch_cfg(const void* A, int64_t lda, void* out, void* ws, int la, bool unscaled, hipStream_t st)
 {
     typedef Shape<V, LOGN, KAP, NT, LOGT> S;
     const int words = WS_GROUP + S::NG;
@@ -725,16 +732,17 @@ hipError_t launch_cfg(const void* A, int64_t lda, void* out, void* ws, int la, h
     // persistent grid: as many workgroups as fit at once (LDS-limited)
     const int per_cu = NT == 512 ? 2 : 1;
     hipLaunchKernelGGL((k_fused_fwd<V, S, HERM, POL>), dim3(device_cu_count() * per_cu), dim3(NT), 0, st,
-                       (const cplx<V>*)A, lda, out, (uint32_t*)ws, device_xcd_count(), la, wait_limits());
+                       (const cplx<V>*)A, lda, out, (uint32_t*)ws, device_xcd_count(), la, wait_limits(),
+                       unscaled ? (V)1 : exp2_neg_host<V>(LOGN));
     return hipGetLastError();
 }
 
 template <class V, int LOGN, int KAP, int NT, int LOGT, bool HERM>
-hipError_t launch_pol(int pol, const void* A, int64_t lda, void* out, void* ws, int la, hipStream_t st)
+hipError_t launch_pol(int pol, const void* A, int64_t lda, void* out, void* ws, int la, bool unscaled, hipStream_t st)
 {
     switch (pol & 7) {
 #define PTD_POL(P) \
-    case P: return launch_cfg<V, LOGN, KAP, NT, LOGT, HERM, P>(A, lda, out, ws, la, st);
+    case P: return launch_cfg<V, LOGN, KAP, NT, LOGT, HERM, P>(A, lda, out, ws, la, unscaled, st);
         PTD_POL(0) PTD_POL(1) PTD_POL(2) PTD_POL(3) PTD_POL(4) PTD_POL(5) PTD_POL(6) PTD_POL(7)
 #undef PTD_POL
     }
@@ -748,7 +756,8 @@ hipError_t launch_pol(int pol, const void* A, int64_t lda, void* out, void* ws, 
 // the partial band in flight); 0 = default.  +4: non-temporal gather loads;
 // +8: non-temporal final stores; +16: non-temporal phase-2 loads.
 template <class V, bool HERM>
-hipError_t fused_dispatch(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg, hipStream_t st)
+hipError_t fused_dispatch(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg, bool unscaled,
+                          hipStream_t st)
 {
     constexpr int LT = fused_logt<V>();
     if (cfg == 0) cfg = fused_default(n, sizeof(V) == 8 ? PTD_C128 : PTD_C64, HERM).cfg;
@@ -756,7 +765,7 @@ hipError_t fused_dispatch(int n, const void* A, int64_t lda, void* out, void* ws
     const int pol = (cfg >> 2) & 7;
     if (shape == 0) return hipErrorInvalidValue;
     if (shape >= 2 && n > 14) return hipErrorInvalidValue;
-#define PTD_CFG(NN, KK, TT, LL) return launch_pol<V, NN, KK, TT, LL, HERM>(pol, A, lda, out, ws, la, st);
+#define PTD_CFG(NN, KK, TT, LL) return launch_pol<V, NN, KK, TT, LL, HERM>(pol, A, lda, out, ws, la, unscaled, st);
     if (shape == 2) {
         switch (n) {
             case 11: PTD_CFG(11, 9, 512, LT)

@@ -5,9 +5,10 @@
 
 namespace ptd {
 
-hipError_t fused_launch_c64_herm(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg, hipStream_t st)
+hipError_t fused_launch_c64_herm(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg, bool unscaled,
+                           hipStream_t st)
 {
-    return fused::fused_dispatch<float, true>(n, A, lda, out, ws, la, cfg, st);
+    return fused::fused_dispatch<float, true>(n, A, lda, out, ws, la, cfg, unscaled, st);
 }
 
 hipError_t fused_rec_c64_herm(int n, const void* coeff, void* A, int64_t lda, void* ws, int la, bool adjoint, hipStream_t st)

@@ -109,11 +109,11 @@ __device__ __forceinline__ void group_rounds(const G& gather, const St& store, c
 // matrix-free kinds A holds their defining vector and lda is unused.
 template <class V, int LOGN, int LOGT, bool REAL_OUT, int NT = GROUP_THREADS, int RMAX = 4, int SRC = SRC_MATRIX>
 __device__ __forceinline__ void group_fwd(const cplx<V>* __restrict__ A, int64_t lda, void* __restrict__ out,
-                                          int64_t ldo, int g, cplx<V>* lds)
+                                          int64_t ldo, int g, cplx<V>* lds, V scale)
 {
+    // scale: 2^-n, or 1 for the unscaled traces Tr(P A) (an exact power of two)
     static_assert(RMAX == 4 || (RMAX == 5 && sizeof(V) == 4), "radix 32 for complex64 only");
     const uint32_t xg = (uint32_t)g << LOGT;
-    const V scale = exp2_neg<V>(LOGN);
     auto gather = [&](int vec, int pos, V& re, V& im) {
         const cplx<V> v = source_entry<V, SRC>(A, lda, LOGN, pos, pos ^ (int)(xg | vec));
         re = v.re;

@@ -32,8 +32,9 @@ inline int64_t lowrank_ld(int64_t pitch, int rank) { return (pitch << 6) | (int6
 // Dense decompose: coeff[x][z] (complex, or real when herm) for n in 1..16.
 // path: 0 = automatic, 1 = force the single-pass group kernel (n <= 10),
 // 2 = force the two-pass tile + high kernels (n >= 7).
+// unscaled: Tr(P A) instead of 2^-n Tr(P A) (the adjoint of reconstruction).
 hipError_t launch_dense_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out,
-                            int path, hipStream_t st);
+                            int path, hipStream_t st, bool unscaled = false);
 
 // One pass of the two-pass dense schedule (1 = tile, 2 = row, 3 = both); timing hook.
 hipError_t launch_dense_fwd_stage(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out, int stage,
@@ -100,16 +101,16 @@ constexpr int FUSED_WS_ERR_WORD = 17;
 size_t fused_workspace_bytes(int n, ptd_dtype dt);
 // cfg 0 = default shape; see fused.hpp for the others.
 hipError_t launch_fused_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out, void* ws, int la,
-                            int cfg, hipStream_t st);
+                            int cfg, hipStream_t st, bool unscaled = false);
 // Per-dtype instantiations of the single-launch schedule (fused_*.hip).
-hipError_t fused_launch_c64(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg,
+hipError_t fused_launch_c64(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg, bool unscaled,
                             hipStream_t st);
-hipError_t fused_launch_c128(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg,
-                             hipStream_t st);
-hipError_t fused_launch_c64_herm(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg,
-                                 hipStream_t st);
-hipError_t fused_launch_c128_herm(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg,
-                                  hipStream_t st);
+hipError_t fused_launch_c128(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg, bool unscaled,
+                            hipStream_t st);
+hipError_t fused_launch_c64_herm(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg, bool unscaled,
+                            hipStream_t st);
+hipError_t fused_launch_c128_herm(int n, const void* A, int64_t lda, void* out, void* ws, int la, int cfg, bool unscaled,
+                            hipStream_t st);
 // Single-launch dense reconstruction for n = 11..14 (fused.hpp); ws holds
 // fused_workspace_bytes() bytes; real coefficients for the Hermitian forms.
 hipError_t fused_rec_c64(int n, const void* coeff, void* A, int64_t lda, void* ws, int la, bool adjoint,
@@ -199,6 +200,9 @@ struct BlockPtrs {
 hipError_t launch_block_diagonal(int k, int m, ptd_dtype dt, bool compact, const BlockPtrs& blocks, void* out,
                                  hipStream_t st);
 hipError_t launch_hermitian_augment(int n, ptd_dtype dt, bool compact, const void* in, void* out, hipStream_t st);
+// dst (2^n x 2^n) = src (rows x cols, pitch ld) top-left, zeros elsewhere.
+hipError_t launch_zero_pad(ptd_dtype dt, const void* src, int64_t ld, int64_t rows, int64_t cols, int n, void* dst,
+                           hipStream_t st);
 hipError_t launch_linear_combination(int n, ptd_dtype dt, double mu_re, double mu_im, const void* a, const void* b,
                                      void* out, hipStream_t st);
 

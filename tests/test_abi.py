@@ -101,7 +101,9 @@ def test_decompose_argument_errors(lib):
     assert _dec(lib, flags=(1 << 2), s=16) == EINVAL  # s < 2^n
     assert _dec(lib, flags=(1 << 3)) == EINVAL  # bands-in without structure
     assert _dec(lib, flags=(1 << 4)) == EINVAL  # compact without structure
-    assert _dec(lib, flags=(1 << 6)) == EINVAL  # adjoint is a reconstruct flag
+    assert _dec(lib, flags=(1 << 6) | (1 << 1)) == EINVAL  # unscaled traces: dense input only
+    assert _dec(lib, flags=(1 << 6) | (1 << 5), dt=1) == EINVAL
+    assert _dec(lib, flags=(1 << 6) | (1 << 9)) == EINVAL
     assert _dec(lib, flags=(1 << 8) | (1 << 2), s=1) == EINVAL  # anti-diagonal + banded
     assert _dec(lib, flags=(1 << 8) | (1 << 5), dt=1) == -3  # compensated structured: unsupported
     assert _dec(lib, flags=(1 << 5), dt=0) == EUNSUP  # compensated is complex64 only
@@ -241,19 +243,27 @@ def test_batched_argument_errors(lib):
     lib.ptd_batch_plan_destroy(None)
 
 
-def test_pad_to_power_of_two():
-    """Zero padding (Sec. II-A) embeds A top-left in the next 2^n square; the
-    host logic runs on CPU tensors too."""
+def test_pad_to_power_of_two_arguments(lib):
+    """Zero padding (Sec. II-A) runs in the library (ptd_zero_pad): a CPU
+    tensor is refused, a power-of-two square passes through untouched, and
+    the entry point validates sizes and overlap before any HIP call."""
     import torch
 
     from paper_2403_11644_amd import api
 
-    for shape, N in (((1, 1), 2), ((3, 3), 4), ((5, 7), 8), ((8, 8), 8), ((100, 64), 128)):
-        A = torch.arange(shape[0] * shape[1], dtype=torch.float64).reshape(shape).to(torch.complex128) + 1
-        P = api.pad_to_power_of_two(A)
-        assert P.shape == (N, N)
-        assert torch.equal(P[: shape[0], : shape[1]], A)
-        assert float(P.abs().sum()) == float(A.abs().sum())
+    A8 = torch.zeros((8, 8), dtype=torch.complex128)
+    assert api.pad_to_power_of_two(A8) is A8
+    with pytest.raises(ValueError):
+        api.pad_to_power_of_two(torch.zeros((3, 5), dtype=torch.complex128))
+    zp = lib.ptd_zero_pad
+    src, dst = ctypes.c_void_p(FAKE_A), ctypes.c_void_p(FAKE_C)
+    assert zp(2, src, 5, 3, 5, dst, 3, None) == -1  # dtype
+    assert zp(0, None, 5, 3, 5, dst, 3, None) == -1
+    assert zp(0, src, 4, 3, 5, dst, 3, None) == -1  # pitch < cols
+    assert zp(0, src, 5, 9, 5, dst, 3, None) == -1  # rows > 2^n
+    assert zp(0, src, 5, 3, 0, dst, 3, None) == -1
+    assert zp(0, src, 5, 3, 5, dst, 0, None) == -1
+    assert zp(0, src, 5, 3, 5, ctypes.c_void_p(FAKE_A + 16), 3, None) == -1  # overlap
 
 
 def test_empty_batch():

@@ -69,3 +69,22 @@ def test_real_loss_gradient(ptd):
     L.backward()
     np.testing.assert_allclose(to_host(A.grad), to_host(A.detach()) * 2.0 / (1 << n), rtol=1e-12, atol=1e-14)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n,dt,herm", [(3, "c128", False), (8, "c64", False), (10, "c128", True), (11, "c128", False),
+                                       (13, "c64", True), (14, "c128", False), (15, "c128", False)])
+def test_decompose_adjoint_is_unscaled(ptd, n, dt, herm):
+    """PTD_ADJOINT of pauli_decompose: Tr(P A) without the 2^-n, i.e. the
+    scaled coefficients times 2^n bit for bit (the scale is an exact power
+    of two), on every dense schedule (group n <= 10, one launch n = 11..14,
+    two-pass complex128 n = 15)."""
+    import torch
+
+    npdt = np.complex128 if dt == "c128" else np.complex64
+    A = synth.hermitian(n, seed=70 + n, dtype=npdt) if herm else synth.dense(n, seed=70 + n, dtype=npdt)
+    Ad = to_dev(A)
+    c = ptd.decompose(Ad, hermitian=herm)
+    u = ptd.decompose(Ad, hermitian=herm, adjoint=True, check=True)
+    assert torch.equal(u, c * float(1 << n))
+    del c, u, Ad
+    torch.cuda.empty_cache()

@@ -382,6 +382,28 @@ def test_fused_n15_c64(ptd, oracle_mod):
     assert rel_err(g, want) <= 1e-5
 
 
+@pytest.mark.parametrize("shape,pitch", [((1, 1), 1), ((3, 3), 3), ((5, 7), 9), ((100, 64), 64), ((70, 130), 200)])
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_zero_pad_kernel(ptd, shape, pitch, dt):
+    """ptd_zero_pad: A top-left in the next 2^n zero square, any row pitch."""
+    import torch
+
+    from paper_2403_11644_amd import api
+
+    tdt = torch.complex128 if dt == "c128" else torch.complex64
+    r, c = shape
+    base = torch.arange(r * pitch, dtype=torch.float64).reshape(r, pitch).to(tdt) * (1 + 1j) + 1
+    A = base.cuda()[:, :c]
+    P = api.pad_to_power_of_two(A)
+    N = 2
+    while N < max(r, c):
+        N *= 2
+    assert P.shape == (N, N)
+    want = torch.zeros((N, N), dtype=tdt)
+    want[:r, :c] = base[:, :c]
+    assert torch.equal(P.cpu(), want)
+
+
 @pytest.mark.parametrize("size", [3, 100, 1500])
 def test_pad_non_power_of_two(ptd, oracle_mod, size):
     """pad=True: the coefficients are those of A embedded top-left in the
