@@ -783,8 +783,14 @@ def main() -> int:
         msd = _time(plan.launch, 10, 3, stream)
         plan.close()
         from paper_2403_11644_amd import tuning as T
-        tuned = {int(k): T.autotune(int(k), api.C64, hermitian=True, reps=5, save=False)["cfg"]
-                 for k in sorted(set(ns.tolist()))}
+        # per size: the plan kept, and the default's and the fastest plan's
+        # median times with the run-to-run spread that decided
+        tuned = {}
+        for k in sorted(set(ns.tolist())):
+            r = T.autotune(int(k), api.C64, hermitian=True, reps=5, save=False)
+            tuned[int(k)] = {"plan": r["cfg"], "kept_non_default": r.get("kept"),
+                             "default_ms": round(r.get("default_ms", float("nan")), 4),
+                             "chosen_ms": round(r["ms"], 4), "spread_ms": round(r.get("spread_ms", float("nan")), 4)}
         plan = api.BatchPlan(bbuf, ns, offs, bout2, offs, dtype_code=api.C64, hermitian=True)
         msp = _time(plan.launch, 10, 3, stream)
         outs = [bout2[o:o + s].view(1 << int(k), 1 << int(k)) for o, s, k in zip(offs, sizes, ns)]

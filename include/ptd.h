@@ -411,6 +411,16 @@ ptd_status ptd_parseval_residual(int n, ptd_dtype dtype, unsigned flags, const v
  */
 ptd_status ptd_autotune(int n, ptd_dtype dtype, unsigned flags, int reps, ptd_stream stream, int *cfg,
                         int *lookahead, float *ms, int *tried, int *admitted);
+
+/* The last ptd_autotune of (n, dtype, flags & PTD_HERMITIAN) on this
+ * process: the default setting's median time per call, the chosen
+ * setting's, and the run-to-run spread that decided (every candidate and the
+ * default are timed in 5 rounds; a setting other than the default is kept
+ * only if its median beats the default's by more than the larger spread of
+ * the two; *kept = 1 then).  Returns 1 if such a tuning exists, 0 if not,
+ * PTD_EINVAL on a bad argument.  Host-only. */
+int ptd_autotune_report(int n, ptd_dtype dtype, unsigned flags, float *default_ms, float *best_ms, float *spread_ms,
+                        int *kept);
 ptd_status ptd_set_tuning(int n, ptd_dtype dtype, unsigned flags, int cfg, int lookahead);
 int ptd_get_tuning(int n, ptd_dtype dtype, unsigned flags, int *cfg, int *lookahead);
 void ptd_clear_tuning(void);

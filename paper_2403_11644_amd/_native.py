@@ -54,6 +54,7 @@ SIGNATURES = {
     "ptd_set_tuning": (I, [I, I, U, I, I]),
     "ptd_get_tuning": (I, [I, I, U, P, P]),
     "ptd_clear_tuning": (None, []),
+    "ptd_autotune_report": (I, [I, I, U, P, P, P, P]),
     "ptd_zero_pad": (I, [I, P, I64, I64, I64, P, I, P]),
     "ptd_status_str": (ctypes.c_char_p, [I]),
     "ptd_last_hip_error": (I, []),

@@ -632,6 +632,14 @@ int ptd_get_tuning(int n, ptd_dtype dtype, unsigned flags, int* cfg, int* lookah
 
 void ptd_clear_tuning(void) { ptd::clear_fused_tuning(); }
 
+int ptd_autotune_report(int n, ptd_dtype dtype, unsigned flags, float* default_ms, float* best_ms, float* spread_ms,
+                        int* kept)
+{
+    if (!valid_dtype(dtype) || (flags & ~PTD_HERMITIAN) || !default_ms || !best_ms || !spread_ms || !kept)
+        return PTD_EINVAL;
+    return ptd::get_tune_report(n, dtype, flags & PTD_HERMITIAN, default_ms, best_ms, spread_ms, kept) ? 1 : 0;
+}
+
 ptd_status ptd_autotune(int n, ptd_dtype dtype, unsigned flags, int reps, ptd_stream stream, int* cfg, int* lookahead,
                         float* ms, int* tried, int* admitted)
 {

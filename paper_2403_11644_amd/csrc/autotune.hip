@@ -14,6 +14,12 @@
 // pauli_decompose reads.  A candidate is admitted only if its output on a
 // Gaussian-integer matrix (every partial sum exact in both precisions)
 // equals the default setting's output bit for bit.
+//
+// Noise: every admitted candidate, and the default setting, is timed in
+// TRIALS separate rounds; the fastest candidate by median replaces the
+// default only if it beats the default's median by more than the larger of
+// the two run-to-run spreads (max - min over the rounds).  The medians and
+// spreads of the last tuning of each point are kept for ptd_autotune_report.
 #include <map>
 #include <mutex>
 #include <vector>
@@ -28,6 +34,14 @@ namespace {
 std::mutex g_mu;
 std::map<int, FusedTuning> g_table;
 std::map<int, int> g_group;  // single-pass group plans, n <= 10
+
+struct TuneReport {
+    float default_ms, best_ms, spread_ms;
+    int kept;  // 1 if the fastest candidate replaced the default
+};
+std::map<int, TuneReport> g_report;
+
+constexpr int TRIALS = 5;
 
 int key_of(int n, ptd_dtype dt, bool herm) { return (n << 2) | ((int)dt << 1) | (herm ? 1 : 0); }
 
@@ -117,6 +131,19 @@ void clear_fused_tuning()
     std::lock_guard<std::mutex> lk(g_mu);
     g_table.clear();
     g_group.clear();
+    g_report.clear();
+}
+
+bool get_tune_report(int n, ptd_dtype dt, bool herm, float* default_ms, float* best_ms, float* spread_ms, int* kept)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_report.find(key_of(n, dt, herm));
+    if (it == g_report.end()) return false;
+    *default_ms = it->second.default_ms;
+    *best_ms = it->second.best_ms;
+    *spread_ms = it->second.spread_ms;
+    *kept = it->second.kept;
+    return true;
 }
 
 int group_default_plan(int n, ptd_dtype dt, bool herm)
@@ -173,6 +200,41 @@ hipError_t settle(const F& launch, float ms, hipStream_t st, hipEvent_t e0, hipE
 
 constexpr float SETTLE_MS = 60.f;
 
+// TRIALS rounds of `reps` back-to-back launches: the median and the spread
+// (max - min) of the per-launch time over the rounds.
+template <class F>
+hipError_t time_trials(const F& launch, int reps, hipStream_t st, hipEvent_t e0, hipEvent_t e1, float* med,
+                       float* spread)
+{
+    float t[TRIALS];
+    for (int k = 0; k < TRIALS; ++k) {
+        hipError_t e = hipEventRecord(e0, st);
+        if (e != hipSuccess) return e;
+        for (int r = 0; r < reps; ++r)
+            if ((e = launch()) != hipSuccess) return e;
+        if ((e = hipEventRecord(e1, st)) != hipSuccess) return e;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return e;
+        t[k] = ms / (float)reps;
+    }
+    for (int i = 1; i < TRIALS; ++i)
+        for (int j = i; j > 0 && t[j] < t[j - 1]; --j) {
+            const float x = t[j];
+            t[j] = t[j - 1];
+            t[j - 1] = x;
+        }
+    *med = t[TRIALS / 2];
+    *spread = t[TRIALS - 1] - t[0];
+    return hipSuccess;
+}
+
+void record_report(int key, float def_ms, float best_ms, float spread, bool kept)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_report[key] = TuneReport{def_ms, best_ms, spread, kept ? 1 : 0};
+}
+
 hipError_t autotune_fused(int n, ptd_dtype dt, bool herm, int reps, hipStream_t st, FusedTuning* best, float* best_ms,
                           int* tried, int* admitted)
 {
@@ -214,7 +276,11 @@ hipError_t autotune_fused(int n, ptd_dtype dt, bool herm, int reps, hipStream_t 
     }
     e = settle([&] { return launch_fused_fwd(n, dt, herm, b.A, N, b.out, b.ws, def.la, 0, st); }, SETTLE_MS, st, e0,
                e1);
-    float bestt = 1e30f;
+    float def_ms = 0.f, def_spread = 0.f;
+    if (e == hipSuccess)
+        e = time_trials([&] { return launch_fused_fwd(n, dt, herm, b.A, N, b.out, b.ws, def.la, 0, st); }, reps, st, e0,
+                        e1, &def_ms, &def_spread);
+    float bestt = 1e30f, best_spread = 0.f;
     FusedTuning bt = def;
     int ntried = 0, nadmit = 0;
     for (const FusedTuning& c : cands) {
@@ -236,15 +302,13 @@ hipError_t autotune_fused(int n, ptd_dtype dt, bool herm, int reps, hipStream_t 
         if (diff != 0) continue;
         ++nadmit;
         (void)launch_fused_fwd(n, dt, herm, b.A, N, b.out, b.ws, c.la, c.cfg, st);  // warm-up
-        if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
-        for (int r = 0; r < reps; ++r) (void)launch_fused_fwd(n, dt, herm, b.A, N, b.out, b.ws, c.la, c.cfg, st);
-        if ((e = hipEventRecord(e1, st)) != hipSuccess) break;
-        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
-        float ms = 0.f;
-        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-        ms /= (float)reps;
+        float ms = 0.f, spread = 0.f;
+        e = time_trials([&] { return launch_fused_fwd(n, dt, herm, b.A, N, b.out, b.ws, c.la, c.cfg, st); }, reps, st,
+                        e0, e1, &ms, &spread);
+        if (e != hipSuccess) break;
         if (ms < bestt) {
             bestt = ms;
+            best_spread = spread;
             bt = c;
         }
     }
@@ -252,11 +316,19 @@ hipError_t autotune_fused(int n, ptd_dtype dt, bool herm, int reps, hipStream_t 
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return e;
     if (nadmit == 0) return hipErrorUnknown;
+    // keep the fastest only if it beats the default beyond the run-to-run spread
+    const float noise = def_spread > best_spread ? def_spread : best_spread;
+    const bool keep = def_ms - bestt > noise;
+    if (!keep) {
+        bt = def;
+        bestt = def_ms;
+    }
     *best = bt;
     *best_ms = bestt;
     *tried = ntried;
     *admitted = nadmit;
     set_fused_tuning(n, dt, herm, bt);
+    record_report(key_of(n, dt, herm), def_ms, bestt, noise, keep);
     return hipSuccess;
 }
 
@@ -311,6 +383,9 @@ hipError_t autotune_group(int n, ptd_dtype dt, bool herm, int reps, hipStream_t 
     }
     e = settle([&] { return batched_launch(dt, herm, false, false, b.A, b.out, b.ws, count, bl, cus, st); }, SETTLE_MS,
                st, e0, e1);
+    // the shipped plan at this size (plan 0 is the bit reference)
+    const int defp = group_default_plan(n, dt, herm);
+    float def_ms = 1e30f, def_spread = 0.f;
     // plans that differ at this size: 1024-thread workgroups at n = 10 only,
     // radix-32 rounds for complex64 at n >= 6 only; the shared launch of the
     // small sizes in a batch runs one fixed plan, so only plan 0 is timed there
@@ -320,7 +395,7 @@ hipError_t autotune_group(int n, ptd_dtype dt, bool herm, int reps, hipStream_t 
         cands.push_back(2);
         if (n == 10) cands.push_back(3);
     }
-    float bestt = 1e30f;
+    float bestt = 1e30f, best_spread = 0.f;
     int bp = 0, ntried = 0, nadmit = 0;
     for (int plan : cands) {
         if (e != hipSuccess) break;
@@ -337,15 +412,17 @@ hipError_t autotune_group(int n, ptd_dtype dt, bool herm, int reps, hipStream_t 
         if ((e = hipStreamSynchronize(st)) != hipSuccess) break;
         if (diff != 0) continue;
         ++nadmit;
-        if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
-        for (int r = 0; r < reps; ++r) (void)batched_launch(dt, herm, false, false, b.A, b.out, b.ws, count, cl, cus, st);
-        if ((e = hipEventRecord(e1, st)) != hipSuccess) break;
-        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
-        float ms = 0.f;
-        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-        ms /= (float)reps;
+        float ms = 0.f, spread = 0.f;
+        e = time_trials([&] { return batched_launch(dt, herm, false, false, b.A, b.out, b.ws, count, cl, cus, st); },
+                        reps, st, e0, e1, &ms, &spread);
+        if (e != hipSuccess) break;
+        if (plan == defp) {
+            def_ms = ms;
+            def_spread = spread;
+        }
         if (ms < bestt) {
             bestt = ms;
+            best_spread = spread;
             bp = plan;
         }
     }
@@ -353,11 +430,20 @@ hipError_t autotune_group(int n, ptd_dtype dt, bool herm, int reps, hipStream_t 
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return e;
     if (nadmit == 0) return hipErrorUnknown;
+    // keep the fastest only if it beats the shipped plan beyond the spread
+    // (the shipped plan is among the candidates at every size)
+    const float noise = def_spread > best_spread ? def_spread : best_spread;
+    const bool keep = bp != defp && def_ms - bestt > noise;
+    if (!keep && def_ms < 1e29f) {
+        bp = defp;
+        bestt = def_ms;
+    }
     *best = bp;
     *best_ms = bestt;
     *tried = ntried;
     *admitted = nadmit;
     set_group_tuning(n, dt, herm, bp);
+    record_report(key_of(n, dt, herm), def_ms, bestt, noise, keep);
     return hipSuccess;
 }
 

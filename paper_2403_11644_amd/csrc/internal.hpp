@@ -167,6 +167,8 @@ inline int group_effective_rmax(int n, ptd_dtype dt, int plan)
 int group_default_plan(int n, ptd_dtype dt, bool herm);
 bool get_group_tuning(int n, ptd_dtype dt, bool herm, int* plan);
 void set_group_tuning(int n, ptd_dtype dt, bool herm, int plan);
+// Medians and spread of the last autotune of a point (autotune.hip).
+bool get_tune_report(int n, ptd_dtype dt, bool herm, float* default_ms, float* best_ms, float* spread_ms, int* kept);
 hipError_t autotune_group(int n, ptd_dtype dt, bool herm, int reps, hipStream_t st, int* best, float* best_ms,
                           int* tried, int* admitted);
 

@@ -41,6 +41,10 @@ def autotune(n: int, dtype_code: int, hermitian: bool = False, reps: int = 5, sa
     _native.check(st, "ptd_autotune")
     rec = {"cfg": cfg.value, "lookahead": la.value, "ms": ms.value, "candidates": tried.value,
            "admitted": adm.value}
+    dms, bms, spr, kept = ctypes.c_float(), ctypes.c_float(), ctypes.c_float(), ctypes.c_int()
+    if L.ptd_autotune_report(n, dtype_code, api.HERMITIAN if hermitian else 0, ctypes.byref(dms), ctypes.byref(bms),
+                             ctypes.byref(spr), ctypes.byref(kept)) == 1:
+        rec.update({"default_ms": dms.value, "spread_ms": spr.value, "kept": bool(kept.value)})
     if save:
         path = cache_path()
         data = {}

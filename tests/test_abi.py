@@ -415,3 +415,11 @@ def test_bandwidth_probe_arguments(lib):
     assert bw(3 | (1 << 4), None, c, 65536, None) == -1  # write-back probe takes no other bits
     assert bw(3, None, None, 65536, None) == -1
     assert bw(3, None, c, 2 << 30, None) == -1  # at most 1 GiB
+
+
+def test_autotune_report_arguments(lib):
+    f, g, h, k = ctypes.c_float(), ctypes.c_float(), ctypes.c_float(), ctypes.c_int()
+    lib.ptd_clear_tuning()
+    assert lib.ptd_autotune_report(12, 0, 0, ctypes.byref(f), ctypes.byref(g), ctypes.byref(h), ctypes.byref(k)) == 0
+    assert lib.ptd_autotune_report(12, 0, 2, ctypes.byref(f), ctypes.byref(g), ctypes.byref(h), ctypes.byref(k)) == -1
+    assert lib.ptd_autotune_report(12, 0, 0, None, ctypes.byref(g), ctypes.byref(h), ctypes.byref(k)) == -1

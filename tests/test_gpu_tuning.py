@@ -1,5 +1,7 @@
 """Autotuner: candidates admitted only when bit-identical on integer input;
 the chosen setting is used by pauli_decompose afterwards."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -20,6 +22,27 @@ def ptd():
     return p
 
 
+def _check_report(rec, n, code, hermitian):
+    """The kept setting is the default unless it beat the default's median by
+    more than the larger run-to-run spread; the report says which."""
+    from paper_2403_11644_amd import _native
+
+    assert {"default_ms", "spread_ms", "kept"} <= set(rec)
+    assert rec["spread_ms"] >= 0.0 and rec["default_ms"] > 0.0
+    if rec["kept"]:
+        assert rec["default_ms"] - rec["ms"] > rec["spread_ms"]
+    else:
+        assert rec["ms"] == rec["default_ms"]
+        cfg, la = ctypes.c_int(), ctypes.c_int()
+        L = _native.lib()
+        assert L.ptd_get_tuning(n, code, 1 if hermitian else 0, ctypes.byref(cfg), ctypes.byref(la)) == 1
+        L.ptd_clear_tuning()
+        dcfg, dla = ctypes.c_int(), ctypes.c_int()
+        assert L.ptd_get_tuning(n, code, 1 if hermitian else 0, ctypes.byref(dcfg), ctypes.byref(dla)) == 0
+        assert (cfg.value, la.value) == (dcfg.value, dla.value)  # the default setting
+        L.ptd_set_tuning(n, code, 1 if hermitian else 0, cfg.value, la.value)
+
+
 @pytest.mark.parametrize("code,hermitian", [(0, False), (1, False), (1, True)])
 def test_autotune_n11(ptd, oracle_mod, tmp_path, monkeypatch, code, hermitian):
     import ctypes
@@ -36,6 +59,7 @@ def test_autotune_n11(ptd, oracle_mod, tmp_path, monkeypatch, code, hermitian):
     before = to_host(ptd.decompose(A, hermitian=hermitian))
     rec = tuning.autotune(n, code, hermitian=hermitian, reps=2)
     assert rec["admitted"] >= 1 and rec["candidates"] >= rec["admitted"]
+    _check_report(rec, n, code, hermitian)
     cfg, la = ctypes.c_int(), ctypes.c_int()
     assert L.ptd_get_tuning(n, code, 1 if hermitian else 0, ctypes.byref(cfg), ctypes.byref(la)) == 1
     assert (cfg.value, la.value) == (rec["cfg"], rec["lookahead"])
@@ -70,6 +94,7 @@ def test_autotune_group_plan(ptd, oracle_mod, code, hermitian, n):
     rec = tuning.autotune(n, code, hermitian=hermitian, reps=2, save=False)
     assert rec["admitted"] == rec["candidates"] >= 1
     assert rec["lookahead"] == 0
+    _check_report(rec, n, code, hermitian)
     dt = np.complex128 if code == 0 else np.complex64
     plans = [0, 1] + ([2, 3] if code == 1 else [])
     mats = [synth.hermitian(n, seed=s, dtype=dt) if hermitian else synth.dense(n, seed=s, dtype=dt)
