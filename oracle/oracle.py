@@ -393,6 +393,40 @@ def sparse_nonempty_x(n: int, rows, cols) -> list[int]:
     return sorted({int(x) for x in (rows[ok] ^ cols[ok])})
 
 
+def csr_to_coo(n: int, row_ptr, col_idx, vals):
+    """The coordinate entries (rows, cols, vals) of a matrix in compressed
+    row form: row r holds the entries row_ptr[r] .. row_ptr[r + 1] - 1 of
+    col_idx and vals, the range's ends clipped to [0, nnz) (nnz = len(col_idx))
+    and the end raised to the start where it lies below it.  Plain loops."""
+    N = 1 << n
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col_idx = np.asarray(col_idx, dtype=np.int64)
+    vals = np.asarray(vals)
+    nnz = len(col_idx)
+    rows, cols, vs = [], [], []
+    for r in range(N):
+        lo = min(max(int(row_ptr[r]), 0), nnz)
+        hi = min(max(int(row_ptr[r + 1]), lo), nnz)
+        for e in range(lo, hi):
+            rows.append(r)
+            cols.append(int(col_idx[e]))
+            vs.append(vals[e])
+    return (np.array(rows, dtype=np.int64), np.array(cols, dtype=np.int64),
+            np.array(vs, dtype=vals.dtype if len(vs) else np.complex128))
+
+
+def csr_to_dense(n: int, row_ptr, col_idx, vals) -> np.ndarray:
+    """The 2^n x 2^n matrix of compressed-row entries (csr_to_coo), repeated
+    coordinates added up and columns outside [0, 2^n) dropped."""
+    return sparse_to_dense(n, *csr_to_coo(n, row_ptr, col_idx, vals))
+
+
+def csr_nonempty_x(n: int, row_ptr, col_idx) -> list[int]:
+    """The X-patterns r ^ c of the compressed-row entries, ascending."""
+    rows, cols, _ = csr_to_coo(n, row_ptr, col_idx, np.zeros(len(col_idx), dtype=np.complex128))
+    return sparse_nonempty_x(n, rows, cols)
+
+
 def mixed_density(U: np.ndarray) -> np.ndarray:
     """The matrix U U^* = sum_r u_r u_r^* over the columns u_r of the
     2^n x R factor U: a mixed state (a density matrix of rank <= R, the

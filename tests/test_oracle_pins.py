@@ -421,6 +421,51 @@ def test_sparse_support(oracle_mod):
     assert nz == oracle_mod.sparse_nonempty_x(n, rows, cols)
 
 
+def test_csr_matches_scipy(oracle_mod):
+    # compressed rows: the assembled matrix equals scipy's own conversion of
+    # the same arrays (repeated columns in a row summed), and the X-pattern
+    # list equals the one of the same entries given as coordinates
+    import scipy.sparse
+
+    n = 5
+    N = 1 << n
+    rng = np.random.default_rng(88)
+    counts = rng.integers(0, 6, size=N)
+    counts[0] = 3  # row 0 holds a repeated column
+    counts[3] = 0  # an empty row
+    row_ptr = np.concatenate([[0], np.cumsum(counts)])
+    nnz = int(row_ptr[-1])
+    col_idx = rng.integers(0, N, size=nnz)
+    col_idx[1] = col_idx[0]
+    vals = rng.standard_normal(nnz) + 1j * rng.standard_normal(nnz)
+    want = scipy.sparse.csr_matrix((vals, col_idx, row_ptr), shape=(N, N)).toarray()
+    np.testing.assert_array_equal(oracle_mod.csr_to_dense(n, row_ptr, col_idx, vals), want)
+    rows = np.repeat(np.arange(N), counts)
+    assert oracle_mod.csr_nonempty_x(n, row_ptr, col_idx) == oracle_mod.sparse_nonempty_x(n, rows, col_idx)
+    c = oracle_mod.decompose(want)
+    assert [x for x in range(N) if np.any(c[x] != 0)] == oracle_mod.csr_nonempty_x(n, row_ptr, col_idx)
+
+
+def test_csr_clipped_ranges(oracle_mod):
+    # out-of-range pointers and columns, worked by hand (n = 2, nnz = 4,
+    # row_ptr = [0, 2, 5, -3, 9]): row 0 takes entries 0, 1; row 1's range
+    # [2, 5) clips to [2, 4), and entry 3's column 7 lies outside the
+    # matrix; row 2's range [5, -3) clips to [4, 4), empty; row 3's range
+    # [-3, 9) clips to [0, 4), all four entries again
+    row_ptr = [0, 2, 5, -3, 9]
+    col_idx = [1, 2, 0, 7]
+    vals = np.array([1, 2j, 3, 4], dtype=np.complex128)
+    rows, cols, vs = oracle_mod.csr_to_coo(2, row_ptr, col_idx, vals)
+    assert rows.tolist() == [0, 0, 1, 1, 3, 3, 3, 3]
+    assert cols.tolist() == [1, 2, 0, 7, 1, 2, 0, 7]
+    assert vs.tolist() == [1, 2j, 3, 4, 1, 2j, 3, 4]
+    want = np.zeros((4, 4), dtype=np.complex128)
+    want[0, 1], want[0, 2], want[1, 0] = 1, 2j, 3
+    want[3, 1], want[3, 2], want[3, 0] = 1, 2j, 3
+    np.testing.assert_array_equal(oracle_mod.csr_to_dense(2, row_ptr, col_idx, vals), want)
+    assert oracle_mod.csr_nonempty_x(2, row_ptr, col_idx) == [1, 2, 3]
+
+
 def test_pure_state_expectations(oracle_mod):
     # the coefficients of |psi><psi| are <psi|P|psi> / 2^n (textbook: P from
     # np.kron applied to psi), real; c_I = |psi|^2 / 2^n and Parseval gives
