@@ -639,7 +639,19 @@ def main() -> int:
         band_legs["sparse"] = {"nnz": int(r.shape[0]), "nonempty_x": int(sp_xs.numel()),
                                "call_compact_us": round(us, 2),
                                "call_compact_cold_us": round(_call_us(sp_call, 5, 1, stream, before=cold), 2)}
-        del rd, cd, vd, sp_out, sp_xs, flush
+        # the same entries in compressed-row form (rows sorted, one wave per row)
+        order = np.argsort(r, kind="stable")
+        rp = np.concatenate([[0], np.cumsum(np.bincount(r, minlength=N))]).astype(np.int64)
+        rpd = torch.from_numpy(rp).to(dev)
+        cs = cd[torch.from_numpy(order).to(dev)].contiguous()
+        vs = vd[torch.from_numpy(order).to(dev)].contiguous()
+        csr_out, csr_xs = ptd.decompose_csr(rpd, cs, vs, n, compact=True)
+        csr_call = lambda: ptd.decompose_csr(rpd, cs, vs, n, compact=True, out=csr_out)
+        us = _call_us(csr_call, 10, 3, stream)
+        band_legs["csr"] = {"nnz": int(r.shape[0]), "nonempty_x": int(csr_xs.numel()),
+                            "call_compact_us": round(us, 2),
+                            "call_compact_cold_us": round(_call_us(csr_call, 5, 1, stream, before=cold), 2)}
+        del rd, cd, vd, sp_out, sp_xs, rpd, cs, vs, csr_out, csr_xs, flush
         legs["structured_n14"] = band_legs
     if "toeplitz" in want_legs:
         _progress("leg toeplitz")

@@ -298,6 +298,30 @@ ptd_status pauli_decompose_sparse(int n, ptd_dtype dtype, unsigned flags, int64_
                                   void *ws, size_t ws_bytes, ptd_stream stream);
 
 /*
+ * Sparse input in compressed-row (CSR) form: the same argument (Sec. IV-A
+ * for any pattern) and the same two calls as for coordinate entries, with
+ * row_ptr in place of rows.  Device arrays: row_ptr holds 2^n + 1 int64
+ * values, col_idx nnz int32 columns, vals nnz complex values of dtype.  Row
+ * r holds the entries row_ptr[r] .. row_ptr[r + 1] - 1, each range clipped
+ * to [0, nnz) (its end raised to its start where it lies below it), so no
+ * read leaves the arrays whatever row_ptr holds; a column repeated within a
+ * row is summed, columns outside [0, 2^n) are ignored.  row_ptr, col_idx
+ * and vals may be null only when nnz == 0.
+ *
+ * ptd_csr_nonempty_x: the X-patterns of the entries, ascending, into xs_out
+ * (room for min(nnz, 2^n)), their number into *count_host; synchronises
+ * `stream`.  pauli_decompose_csr: the coefficients of the listed X-patterns,
+ * with the list check, flags and output of pauli_decompose_sparse.  ws holds
+ * ptd_sparse_workspace_bytes(n) bytes.  PTD_EINVAL also when the output or
+ * the workspace overlaps an input array or each other.
+ */
+ptd_status ptd_csr_nonempty_x(int n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx, uint32_t *xs_out,
+                              int *count_host, void *ws, size_t ws_bytes, ptd_stream stream);
+ptd_status pauli_decompose_csr(int n, ptd_dtype dtype, unsigned flags, int64_t nnz, const int64_t *row_ptr,
+                               const int32_t *col_idx, const void *vals, const uint32_t *xs, int count, void *coeff,
+                               void *ws, size_t ws_bytes, ptd_stream stream);
+
+/*
  * Combinations of decompositions (Sec. IV-B, "Combinations of matrices"):
  * the coefficients of a matrix assembled from matrices whose coefficients
  * are known, computed from those coefficients alone, with no matrix formed

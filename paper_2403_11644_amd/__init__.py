@@ -6,8 +6,8 @@ computed by hand-written gfx950 HIP kernels behind a C ABI (include/ptd.h).
 from .api import (  # noqa: F401
     ADJOINT, ANTIDIAGONAL, BANDED, BANDS_IN, C64, C128, COMPACT, COMPENSATED, DIAGONAL, HERMITIAN, LOW_RANK,
     PURE_STATE, TOEPLITZ, BatchPlan,
-    block_diagonal, decompose, decompose_batched, decompose_sparse, direct_sum, hermitian_augment, lcu_amplitudes,
-    linear_combination, nonempty_x, num_nonempty_x, pad_to_power_of_two, parseval, reconstruct,
+    block_diagonal, decompose, decompose_batched, decompose_csr, decompose_sparse, direct_sum, hermitian_augment,
+    lcu_amplitudes, linear_combination, nonempty_x, num_nonempty_x, pad_to_power_of_two, parseval, reconstruct,
 )
 from .labels import flat_index, index, label, to_dict  # noqa: F401
 from .host_tree import host_tree_decompose  # noqa: F401

@@ -49,6 +49,8 @@ SIGNATURES = {
     "ptd_sparse_workspace_bytes": (SZ, [I]),
     "ptd_sparse_nonempty_x": (I, [I, I64, P, P, P, P, P, SZ, P]),
     "pauli_decompose_sparse": (I, [I, I, U, I64, P, P, P, P, I, P, P, SZ, P]),
+    "ptd_csr_nonempty_x": (I, [I, I64, P, P, P, P, P, SZ, P]),
+    "pauli_decompose_csr": (I, [I, I, U, I64, P, P, P, P, I, P, P, SZ, P]),
     "ptd_host_tree_decompose": (I, [I, U, P, I64, P, I, I64, I64, I, P]),
     "ptd_autotune": (I, [I, I, U, I, P, P, P, P, P, P]),
     "ptd_set_tuning": (I, [I, I, U, I, I]),

@@ -459,6 +459,47 @@ def decompose_sparse(rows: torch.Tensor, cols: torch.Tensor, vals: torch.Tensor,
 
 
 @_on_stream
+def decompose_csr(row_ptr: torch.Tensor, col_idx: torch.Tensor, vals: torch.Tensor, n: int, *,
+                  compact: bool = False, out: torch.Tensor | None = None, stream=None):
+    """Coefficients of a sparse 2^n x 2^n matrix in compressed-row form
+    (int64 row_ptr of 2^n + 1 values, int32 col_idx, complex vals, all on
+    the GPU; row r holds entries row_ptr[r] .. row_ptr[r + 1] - 1, clipped to
+    the arrays; a column repeated within a row is summed).  Returns
+    (coefficients, xs) as decompose_sparse does."""
+    for t, name in ((row_ptr, "row_ptr"), (col_idx, "col_idx"), (vals, "vals")):
+        _require_device(t, name)
+        if t.dim() != 1 or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous 1-D tensor" % name)
+    if row_ptr.dtype != torch.int64 or col_idx.dtype != torch.int32:
+        raise TypeError("row_ptr must be int64 and col_idx int32")
+    N = 1 << n
+    if row_ptr.shape[0] != N + 1:
+        raise ValueError("row_ptr must hold 2^n + 1 values")
+    nnz = col_idx.shape[0]
+    if vals.shape[0] != nnz:
+        raise ValueError("col_idx and vals must have the same length")
+    code = _dtype_code(vals.dtype)
+    L = _native.lib()
+    wsb = L.ptd_sparse_workspace_bytes(n)
+    if wsb == 0:
+        raise ValueError("n must lie in 1..16")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=vals.device)
+    xs = torch.empty(max(1, min(nnz, N)), dtype=torch.int32, device=vals.device)
+    cnt = ctypes.c_int()
+    h = _stream_handle(vals.device, stream)
+    st = L.ptd_csr_nonempty_x(n, nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(xs), ctypes.byref(cnt), _ptr(ws), wsb, h)
+    _native.check(st, "ptd_csr_nonempty_x")
+    count = cnt.value
+    out = _check_out(out, ((count if compact else N), N), vals.dtype, vals.device)
+    if compact and count == 0:
+        return out, xs[:0].to(torch.int64)
+    st = L.pauli_decompose_csr(n, code, COMPACT if compact else 0, nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(vals),
+                               _ptr(xs), count, _ptr(out), _ptr(ws), wsb, h)
+    _native.check(st, "pauli_decompose_csr")
+    return out, xs[:count].to(torch.int64)
+
+
+@_on_stream
 def lcu_amplitudes(c: torch.Tensor, *, hermitian: bool = False, out: torch.Tensor | None = None, stream=None):
     """Amplitudes sqrt(|c_P| / lambda) of the ancilla state that prepares a
     block-encoding by a linear combination of the strings, and lambda =

@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -406,7 +407,8 @@ ptd_status ptd_sparse_nonempty_x(int n, int64_t nnz, const int32_t* rows, const 
     if (n < 1 || n > 16 || nnz < 0 || !xs_out || !count_host) return PTD_EINVAL;
     if (nnz > 0 && (!rows || !cols)) return PTD_EINVAL;
     if (!ws || ws_bytes < ptd::sparse_workspace_bytes(n)) return PTD_ENOSPC;
-    return hip_status(ptd::launch_sparse_nonempty_x(n, nnz, rows, cols, xs_out, count_host, ws, (hipStream_t)stream));
+    return hip_status(
+        ptd::launch_sparse_nonempty_x(n, nnz, rows, nullptr, cols, xs_out, count_host, ws, (hipStream_t)stream));
 }
 
 ptd_status pauli_decompose_sparse(int n, ptd_dtype dtype, unsigned flags, int64_t nnz, const int32_t* rows,
@@ -420,8 +422,51 @@ ptd_status pauli_decompose_sparse(int n, ptd_dtype dtype, unsigned flags, int64_
     if (coeff == vals) return PTD_EINVAL;
     if (!ws || ws_bytes < ptd::sparse_workspace_bytes(n)) return PTD_ENOSPC;
     bool bad = false;
-    const ptd_status st = hip_status(ptd::launch_sparse(n, dtype, flags & PTD_COMPACT, nnz, rows, cols, vals, xs,
-                                                        count, coeff, ws, &bad, (hipStream_t)stream));
+    const ptd_status st = hip_status(ptd::launch_sparse(n, dtype, flags & PTD_COMPACT, nnz, rows, nullptr, cols, vals,
+                                                        xs, count, coeff, ws, &bad, (hipStream_t)stream));
+    if (st != PTD_OK) return st;
+    return bad ? PTD_EINVAL : PTD_OK;
+}
+
+ptd_status ptd_csr_nonempty_x(int n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx, uint32_t* xs_out,
+                              int* count_host, void* ws, size_t ws_bytes, ptd_stream stream)
+{
+    if (n < 1 || n > 16 || nnz < 0 || !xs_out || !count_host) return PTD_EINVAL;
+    if (nnz > 0 && (!row_ptr || !col_idx)) return PTD_EINVAL;
+    if (!ws || ws_bytes < ptd::sparse_workspace_bytes(n)) return PTD_ENOSPC;
+    const size_t N = (size_t)1 << n;
+    const size_t wsb = ptd::sparse_workspace_bytes(n);
+    if (nnz > 0 && (overlap(ws, wsb, xs_out, std::min((size_t)nnz, N) * 4) || overlap(ws, wsb, row_ptr, (N + 1) * 8) || overlap(ws, wsb, col_idx, (size_t)nnz * 4) ||
+                    overlap(xs_out, std::min((size_t)nnz, N) * 4, row_ptr, (N + 1) * 8) ||
+                    overlap(xs_out, std::min((size_t)nnz, N) * 4, col_idx, (size_t)nnz * 4)))
+        return PTD_EINVAL;
+    return hip_status(
+        ptd::launch_sparse_nonempty_x(n, nnz, nullptr, row_ptr, col_idx, xs_out, count_host, ws, (hipStream_t)stream));
+}
+
+ptd_status pauli_decompose_csr(int n, ptd_dtype dtype, unsigned flags, int64_t nnz, const int64_t* row_ptr,
+                               const int32_t* col_idx, const void* vals, const uint32_t* xs, int count, void* coeff,
+                               void* ws, size_t ws_bytes, ptd_stream stream)
+{
+    if (n < 1 || n > 16 || !valid_dtype(dtype) || nnz < 0 || !coeff) return PTD_EINVAL;
+    if (flags & ~PTD_COMPACT) return PTD_EINVAL;
+    if (nnz > 0 && (!row_ptr || !col_idx || !vals)) return PTD_EINVAL;
+    if (count < 0 || count > (1 << n) || (count > 0 && !xs)) return PTD_EINVAL;
+    if (!ws || ws_bytes < ptd::sparse_workspace_bytes(n)) return PTD_ENOSPC;
+    const size_t N = (size_t)1 << n;
+    const size_t eb = elem_bytes(dtype);
+    const size_t out_bytes = ((flags & PTD_COMPACT) ? (size_t)count : N) * N * eb;
+    const size_t wsb = ptd::sparse_workspace_bytes(n);
+    // the output and the workspace are written: neither may overlap an input or each other
+    const void* ins[4] = {row_ptr, col_idx, vals, xs};
+    const size_t in_bytes[4] = {nnz > 0 ? (N + 1) * 8 : 0, (size_t)nnz * 4, (size_t)nnz * eb, (size_t)count * 4};
+    for (int i = 0; i < 4; ++i)
+        if (in_bytes[i] && (overlap(coeff, out_bytes, ins[i], in_bytes[i]) || overlap(ws, wsb, ins[i], in_bytes[i])))
+            return PTD_EINVAL;
+    if (overlap(coeff, out_bytes, ws, wsb)) return PTD_EINVAL;
+    bool bad = false;
+    const ptd_status st = hip_status(ptd::launch_sparse(n, dtype, flags & PTD_COMPACT, nnz, nullptr, row_ptr, col_idx,
+                                                        vals, xs, count, coeff, ws, &bad, (hipStream_t)stream));
     if (st != PTD_OK) return st;
     return bad ? PTD_EINVAL : PTD_OK;
 }

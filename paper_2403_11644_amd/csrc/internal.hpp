@@ -53,17 +53,19 @@ hipError_t launch_structured(int n, ptd_dtype dt, bool herm, bool bands, bool co
                              const void* A, int64_t lda, void* out, hipStream_t st);
 
 // Sparse input given as nnz coordinate entries (rows, cols: int32 device
-// arrays; vals: complex of dt).  ws holds sparse_workspace_bytes(n).
+// arrays; vals: complex of dt), or, when rows is null, in compressed-row form
+// (row_ptr: 2^n + 1 int64 device values, each row's range clipped to
+// [0, nnz)).  ws holds sparse_workspace_bytes(n).
 size_t sparse_workspace_bytes(int n);
 // The distinct r ^ c over the entries, ascending, into xs; synchronises st.
-hipError_t launch_sparse_nonempty_x(int n, int64_t nnz, const int32_t* rows, const int32_t* cols, uint32_t* xs,
-                                    int* count_host, void* ws, hipStream_t st);
+hipError_t launch_sparse_nonempty_x(int n, int64_t nnz, const int32_t* rows, const int64_t* row_ptr,
+                                    const int32_t* cols, uint32_t* xs, int* count_host, void* ws, hipStream_t st);
 // Coefficients of the listed X-patterns xs[0..count); *bad_xs is set (and
 // nothing launched after the check) unless xs is strictly ascending inside
 // [0, 2^n).  Synchronises st once, after the check.
-hipError_t launch_sparse(int n, ptd_dtype dt, bool compact, int64_t nnz, const int32_t* rows, const int32_t* cols,
-                         const void* vals, const uint32_t* xs, int count, void* out, void* ws, bool* bad_xs,
-                         hipStream_t st);
+hipError_t launch_sparse(int n, ptd_dtype dt, bool compact, int64_t nnz, const int32_t* rows, const int64_t* row_ptr,
+                         const int32_t* cols, const void* vals, const uint32_t* xs, int count, void* out, void* ws,
+                         bool* bad_xs, hipStream_t st);
 
 // Bandwidth reference kernels (probe.hip): copy / read / write of `bytes`
 // (a multiple of 16) in the shape `variant` encodes.

@@ -322,11 +322,11 @@ hipError_t struct_launch(int n, int s, int count, bool compact, const void* A, i
 }
 
 // ---------------------------------------------------------------- sparse
-// A sparse matrix given by nnz coordinate entries (r, c, v): its strings with
-// X-pattern x read only entries (k, k ^ x), so the X-patterns that can carry
-// a nonzero coefficient are the distinct r ^ c, the same argument as for the
-// diagonal and band cases above.  Entries with r or c outside [0, 2^n) are
-// ignored.
+// A sparse matrix given by nnz coordinate entries (r, c, v), or in
+// compressed-row form: its strings with X-pattern x read only entries
+// (k, k ^ x), so the X-patterns that can carry a nonzero coefficient are the
+// distinct r ^ c, the same argument as for the diagonal and band cases
+// above.  Entries with r or c outside [0, 2^n) are ignored.
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t count, uint32_t v)
 {
@@ -407,9 +407,77 @@ __global__ void k_scatter(const int32_t* __restrict__ rows, const int32_t* __res
     }
 }
 
+// Compressed-row input: row r holds the entries row_ptr[r] .. row_ptr[r+1]-1
+// of cols / vals, the range clipped to [0, nnz) (its end raised to its start
+// where below it), so every access stays inside the caller's arrays whatever
+// the pointers hold.  One wave per row, its lanes over the row's entries
+// (consecutive, so the column and value loads of a wave are coalesced).
+constexpr int CSR_THREADS = 256;
+constexpr int CSR_WAVES = CSR_THREADS / 64;
+
+__device__ __forceinline__ void csr_range(const int64_t* __restrict__ row_ptr, int r, int64_t nnz, int64_t& lo,
+                                          int64_t& hi)
+{
+    const int64_t a = row_ptr[r], b = row_ptr[r + 1];
+    lo = a < 0 ? 0 : (a > nnz ? nnz : a);
+    hi = b < lo ? lo : (b > nnz ? nnz : b);
+}
+
+__global__ __launch_bounds__(CSR_THREADS) void k_mark_x_csr(const int64_t* __restrict__ row_ptr,
+                                                             const int32_t* __restrict__ cols, int64_t nnz, int n,
+                                                             uint32_t* __restrict__ flags)
+{
+    const int32_t N = 1 << n;
+    const int lane = threadIdx.x & 63;
+    for (int r = blockIdx.x * CSR_WAVES + (int)(threadIdx.x >> 6); r < N; r += gridDim.x * CSR_WAVES) {
+        int64_t lo, hi;
+        csr_range(row_ptr, r, nnz, lo, hi);
+        for (int64_t e = lo + lane; e < hi; e += 64) {
+            const int32_t c = cols[e];
+            if (c >= 0 && c < N) flags[r ^ c] = 1u;
+        }
+    }
+}
+
+// d_x[r] += v for the entries (r, c, v) of row r with x = r ^ c listed,
+// atomically as for coordinate input (a row may repeat a column)
 template <class V>
-hipError_t sparse_t(int n, bool compact, int64_t nnz, const int32_t* rows, const int32_t* cols, const void* vals,
-                    const uint32_t* xs, int count, void* out, void* ws, bool* bad_xs, hipStream_t st)
+__global__ __launch_bounds__(CSR_THREADS) void k_scatter_csr(const int64_t* __restrict__ row_ptr,
+                                                              const int32_t* __restrict__ cols,
+                                                              const cplx<V>* __restrict__ vals, int64_t nnz, int n,
+                                                              const int32_t* __restrict__ xpos, int compact,
+                                                              cplx<V>* __restrict__ out)
+{
+    const int32_t N = 1 << n;
+    const int lane = threadIdx.x & 63;
+    for (int r = blockIdx.x * CSR_WAVES + (int)(threadIdx.x >> 6); r < N; r += gridDim.x * CSR_WAVES) {
+        int64_t lo, hi;
+        csr_range(row_ptr, r, nnz, lo, hi);
+        for (int64_t e = lo + lane; e < hi; e += 64) {
+            const int32_t c = cols[e];
+            if (c < 0 || c >= N) continue;
+            const int32_t x = r ^ c;
+            const int32_t i = xpos[x];
+            if (i < 0) continue;
+            const cplx<V> v = vals[e];
+            V* p = (V*)(out + (((int64_t)(compact ? i : x)) << n) + r);
+            __hip_atomic_fetch_add(p, v.re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(p + 1, v.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+int csr_grid(int n)
+{
+    const int rows_blocks = ((1 << n) + CSR_WAVES - 1) / CSR_WAVES;
+    return rows_blocks < 8192 ? rows_blocks : 8192;
+}
+
+// rows == nullptr: the entries are in compressed-row form (row_ptr)
+template <class V>
+hipError_t sparse_t(int n, bool compact, int64_t nnz, const int32_t* rows, const int64_t* row_ptr,
+                    const int32_t* cols, const void* vals, const uint32_t* xs, int count, void* out, void* ws,
+                    bool* bad_xs, hipStream_t st)
 {
     const int64_t N = (int64_t)1 << n;
     int32_t* xpos = (int32_t*)ws;
@@ -429,9 +497,12 @@ hipError_t sparse_t(int n, bool compact, int64_t nnz, const int32_t* rows, const
     hipLaunchKernelGGL(k_fill_u32, dim3(4096), dim3(256), 0, st, (uint32_t*)out, words, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, st, (uint32_t*)xpos, N, 0xffffffffu);
     hipLaunchKernelGGL(k_xpos, dim3(grid), dim3(256), 0, st, xs, count, xpos);
-    if (nnz > 0)
+    if (nnz > 0 && rows)
         hipLaunchKernelGGL(k_scatter<V>, dim3(4096), dim3(256), 0, st, rows, cols, (const cplx<V>*)vals, nnz, n,
                            xpos, compact ? 1 : 0, (cplx<V>*)out);
+    else if (nnz > 0)
+        hipLaunchKernelGGL(k_scatter_csr<V>, dim3(csr_grid(n)), dim3(CSR_THREADS), 0, st, row_ptr, cols,
+                           (const cplx<V>*)vals, nnz, n, xpos, compact ? 1 : 0, (cplx<V>*)out);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (count == 0) return hipSuccess;
     return struct_launch<V, SRC_ROWS, false>(n, 0, count, compact, nullptr, 0, out, xs, st);
@@ -458,13 +529,15 @@ hipError_t launch_structured(int n, ptd_dtype dt, bool herm, bool bands, bool co
 
 size_t sparse_workspace_bytes(int n) { return ((size_t)4 << n) + 256; }
 
-hipError_t launch_sparse_nonempty_x(int n, int64_t nnz, const int32_t* rows, const int32_t* cols, uint32_t* xs,
-                                    int* count_host, void* ws, hipStream_t st)
+hipError_t launch_sparse_nonempty_x(int n, int64_t nnz, const int32_t* rows, const int64_t* row_ptr,
+                                    const int32_t* cols, uint32_t* xs, int* count_host, void* ws, hipStream_t st)
 {
     uint32_t* flags = (uint32_t*)ws;
     uint32_t* cnt = (uint32_t*)((unsigned char*)ws + sparse_workspace_bytes(n) - 256);
     hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, st, flags, (int64_t)1 << n, 0u);
-    if (nnz > 0) hipLaunchKernelGGL(k_mark_x, dim3(4096), dim3(256), 0, st, rows, cols, nnz, n, flags);
+    if (nnz > 0 && rows) hipLaunchKernelGGL(k_mark_x, dim3(4096), dim3(256), 0, st, rows, cols, nnz, n, flags);
+    else if (nnz > 0)
+        hipLaunchKernelGGL(k_mark_x_csr, dim3(csr_grid(n)), dim3(CSR_THREADS), 0, st, row_ptr, cols, nnz, n, flags);
     hipLaunchKernelGGL(k_list_x, dim3(1), dim3(LIST_THREADS), 0, st, flags, n, xs, cnt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -476,12 +549,13 @@ hipError_t launch_sparse_nonempty_x(int n, int64_t nnz, const int32_t* rows, con
     return hipSuccess;
 }
 
-hipError_t launch_sparse(int n, ptd_dtype dt, bool compact, int64_t nnz, const int32_t* rows, const int32_t* cols,
-                         const void* vals, const uint32_t* xs, int count, void* out, void* ws, bool* bad_xs,
-                         hipStream_t st)
+hipError_t launch_sparse(int n, ptd_dtype dt, bool compact, int64_t nnz, const int32_t* rows, const int64_t* row_ptr,
+                         const int32_t* cols, const void* vals, const uint32_t* xs, int count, void* out, void* ws,
+                         bool* bad_xs, hipStream_t st)
 {
-    return dt == PTD_C128 ? sparse_t<double>(n, compact, nnz, rows, cols, vals, xs, count, out, ws, bad_xs, st)
-                          : sparse_t<float>(n, compact, nnz, rows, cols, vals, xs, count, out, ws, bad_xs, st);
+    return dt == PTD_C128
+               ? sparse_t<double>(n, compact, nnz, rows, row_ptr, cols, vals, xs, count, out, ws, bad_xs, st)
+               : sparse_t<float>(n, compact, nnz, rows, row_ptr, cols, vals, xs, count, out, ws, bad_xs, st);
 }
 
 }  // namespace ptd

@@ -423,3 +423,48 @@ def test_autotune_report_arguments(lib):
     assert lib.ptd_autotune_report(12, 0, 0, ctypes.byref(f), ctypes.byref(g), ctypes.byref(h), ctypes.byref(k)) == 0
     assert lib.ptd_autotune_report(12, 0, 2, ctypes.byref(f), ctypes.byref(g), ctypes.byref(h), ctypes.byref(k)) == -1
     assert lib.ptd_autotune_report(12, 0, 0, None, ctypes.byref(g), ctypes.byref(h), ctypes.byref(k)) == -1
+
+
+def test_csr_argument_errors(lib):
+    """Compressed-row input: argument and overlap errors come back before
+    any HIP call (fake device addresses are never dereferenced)."""
+    EINVAL, ENOSPC = -1, -2
+    n = 6
+    N = 1 << n
+    wsb = lib.ptd_sparse_workspace_bytes(n)
+    assert wsb == 4 * N + 256
+    rp, ci, va, xs, out, ws = (ctypes.c_void_p(FAKE_A + k * (1 << 24)) for k in range(6))
+    cnt = ctypes.c_int()
+    # nonempty list: bad n, negative nnz, missing arrays, short workspace
+    assert lib.ptd_csr_nonempty_x(0, 4, rp, ci, xs, ctypes.byref(cnt), ws, wsb, None) == EINVAL
+    assert lib.ptd_csr_nonempty_x(n, -1, rp, ci, xs, ctypes.byref(cnt), ws, wsb, None) == EINVAL
+    assert lib.ptd_csr_nonempty_x(n, 4, None, ci, xs, ctypes.byref(cnt), ws, wsb, None) == EINVAL
+    assert lib.ptd_csr_nonempty_x(n, 4, rp, None, xs, ctypes.byref(cnt), ws, wsb, None) == EINVAL
+    assert lib.ptd_csr_nonempty_x(n, 4, rp, ci, None, ctypes.byref(cnt), ws, wsb, None) == EINVAL
+    assert lib.ptd_csr_nonempty_x(n, 4, rp, ci, xs, None, ws, wsb, None) == EINVAL
+    assert lib.ptd_csr_nonempty_x(n, 4, rp, ci, xs, ctypes.byref(cnt), ws, wsb - 1, None) == ENOSPC
+    assert lib.ptd_csr_nonempty_x(n, 4, rp, ci, xs, ctypes.byref(cnt), None, wsb, None) == ENOSPC
+    # the workspace over row_ptr (2^n + 1 int64 values) or the list over col_idx
+    assert lib.ptd_csr_nonempty_x(n, 4, rp, ci, xs, ctypes.byref(cnt), ctypes.c_void_p(FAKE_A + 8 * N), wsb,
+                                  None) == EINVAL
+    assert lib.ptd_csr_nonempty_x(n, 4, rp, ci, ctypes.c_void_p(FAKE_A + (1 << 24) + 12), ctypes.byref(cnt), ws, wsb,
+                                  None) == EINVAL
+
+    def dec(flags=0, nnz=4, dt=0, rp=rp, ci=ci, va=va, xs=xs, count=2, out=out, ws=ws, wsb=wsb):
+        return lib.pauli_decompose_csr(n, dt, flags, nnz, rp, ci, va, xs, count, out, ws, wsb, None)
+
+    assert dec(dt=7) == EINVAL
+    assert dec(flags=1) == EINVAL  # only PTD_COMPACT
+    assert dec(nnz=-1) == EINVAL
+    assert dec(rp=None) == EINVAL and dec(ci=None) == EINVAL and dec(va=None) == EINVAL
+    assert dec(count=-1) == EINVAL and dec(count=N + 1) == EINVAL and dec(xs=None) == EINVAL
+    assert dec(out=None) == EINVAL
+    assert dec(wsb=wsb - 1) == ENOSPC
+    # the output over the values, over row_ptr's last value, or over the
+    # workspace; the workspace over the list
+    assert dec(out=ctypes.c_void_p(FAKE_A + 2 * (1 << 24) + 48)) == EINVAL
+    assert dec(out=ctypes.c_void_p(FAKE_A + 8 * N)) == EINVAL
+    assert dec(out=ctypes.c_void_p(FAKE_A + 5 * (1 << 24) - N * N * 16 + 16)) == EINVAL
+    assert dec(ws=ctypes.c_void_p(FAKE_A + 3 * (1 << 24) + 4)) == EINVAL
+    # compact output: count rows of it, ending 16 bytes into the values
+    assert dec(flags=1 << 2, out=ctypes.c_void_p(FAKE_A + 2 * (1 << 24) - 2 * N * 16 + 16)) == EINVAL
