@@ -420,9 +420,16 @@ ptd_status ptd_parseval_residual(int n, ptd_dtype dtype, unsigned flags, const v
  * reaches single calls only (and the tuner times plan 0 alone).  Every plan
  * gives the same bits.
  *
- * n = 11..15, the single-launch schedule (complex128 for n <= 14): cfg holds
- * the workgroup shape and the cache policies of the gathers, the final
- * stores and the re-read partial results; lookahead is the queue lookahead.
+ * n = 11..15, the single-launch schedule (complex128 for n <= 14): cfg & 3
+ * is the shape, which fixes the tile and the stage split: 1 = 1024-thread
+ * workgroups, 10 low WHT stages per phase-1 item (n - 10 in phase 2), a
+ * group of X-patterns filling a 128-byte row segment (T = 16 complex64 or 8
+ * complex128); 2 = 512 threads, 9 low stages, the same T; 3 = 512 threads,
+ * 10 low stages, half that T (64-byte segments, half the partial band in
+ * flight); shapes 2 and 3 exist for n <= 14.  cfg bits 2..4 are the cache
+ * policies (non-temporal gathers of A, final stores, phase-2 loads of the
+ * partial results); lookahead is the queue lookahead (1..64).
+ * ptd_describe_tuning decodes a setting into these terms.
  *
  * ptd_autotune times the candidate settings at this (n, dtype, Hermitian)
  * point on device buffers it allocates itself, admits a candidate only if
@@ -445,6 +452,13 @@ ptd_status ptd_autotune(int n, ptd_dtype dtype, unsigned flags, int reps, ptd_st
  * PTD_EINVAL on a bad argument.  Host-only. */
 int ptd_autotune_report(int n, ptd_dtype dtype, unsigned flags, float *default_ms, float *best_ms, float *spread_ms,
                         int *kept);
+/* The single-launch schedule's reading of setting cfg (0 = the default) at
+ * (n, dtype, flags & PTD_HERMITIAN), n = 11..15: workgroup threads, the low
+ * WHT stages a phase-1 item applies (the other n - phase1_bits run in phase
+ * 2) and the X-patterns per group (T).  PTD_EINVAL for a setting the
+ * schedule does not build there.  Host-only. */
+ptd_status ptd_describe_tuning(int n, ptd_dtype dtype, unsigned flags, int cfg, int *threads, int *phase1_bits,
+                               int *group_patterns);
 ptd_status ptd_set_tuning(int n, ptd_dtype dtype, unsigned flags, int cfg, int lookahead);
 int ptd_get_tuning(int n, ptd_dtype dtype, unsigned flags, int *cfg, int *lookahead);
 void ptd_clear_tuning(void);

@@ -53,6 +53,7 @@ SIGNATURES = {
     "pauli_decompose_csr": (I, [I, I, U, I64, P, P, P, P, I, P, P, SZ, P]),
     "ptd_host_tree_decompose": (I, [I, U, P, I64, P, I, I64, I64, I, P]),
     "ptd_autotune": (I, [I, I, U, I, P, P, P, P, P, P]),
+    "ptd_describe_tuning": (I, [I, I, U, I, P, P, P]),
     "ptd_set_tuning": (I, [I, I, U, I, I]),
     "ptd_get_tuning": (I, [I, I, U, P, P]),
     "ptd_clear_tuning": (None, []),

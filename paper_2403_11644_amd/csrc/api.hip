@@ -657,6 +657,16 @@ ptd_status ptd_set_tuning(int n, ptd_dtype dtype, unsigned flags, int cfg, int l
     return PTD_OK;
 }
 
+ptd_status ptd_describe_tuning(int n, ptd_dtype dtype, unsigned flags, int cfg, int* threads, int* phase1_bits,
+                               int* group_patterns)
+{
+    if (!valid_dtype(dtype) || (flags & ~PTD_HERMITIAN) || !threads || !phase1_bits || !group_patterns)
+        return PTD_EINVAL;
+    if (!ptd::describe_fused(n, dtype, flags & PTD_HERMITIAN, cfg, threads, phase1_bits, group_patterns))
+        return PTD_EINVAL;
+    return PTD_OK;
+}
+
 int ptd_get_tuning(int n, ptd_dtype dtype, unsigned flags, int* cfg, int* lookahead)
 {
     if (!valid_dtype(dtype) || (flags & ~PTD_HERMITIAN) || !cfg || !lookahead) return PTD_EINVAL;

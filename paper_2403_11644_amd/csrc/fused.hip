@@ -159,4 +159,12 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st)
     return hipGetLastError();
 }
 
+bool describe_fused(int n, ptd_dtype dt, bool herm, int cfg, int* threads, int* phase1_bits, int* group_patterns)
+{
+    int logt = 0;
+    if (!fused::fused_describe(n, dt == PTD_C64, herm, cfg, threads, phase1_bits, &logt)) return false;
+    *group_patterns = 1 << logt;
+    return true;
+}
+
 }  // namespace ptd

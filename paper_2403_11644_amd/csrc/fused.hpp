@@ -799,6 +799,24 @@ hipError_t fused_dispatch(int n, const void* A, int64_t lda, void* out, void* ws
 #undef PTD_CFG
 }
 
+// What fused_dispatch builds for a setting, in the schedule's own terms:
+// workgroup threads, the low WHT stages each phase-1 item applies (the
+// remaining n - kap run in phase 2: the stage split) and log2 of the
+// X-patterns per group (the tile width T).  False where fused_dispatch
+// would refuse the setting.
+inline bool fused_describe(int n, bool c64, bool herm, int cfg, int* threads, int* kap, int* logt)
+{
+    const int LT = c64 ? 4 : 3;
+    if (n < 11 || n > 15 || (n == 15 && (!c64 || herm))) return false;
+    if (cfg == 0) cfg = fused_default(n, c64 ? PTD_C64 : PTD_C128, herm).cfg;
+    const int shape = cfg & 3;
+    if (shape == 0 || (shape >= 2 && n > 14) || (cfg >> 5) != 0) return false;
+    *threads = shape == 1 ? 1024 : 512;
+    *kap = shape == 2 ? 9 : 10;
+    *logt = shape == 3 ? LT - 1 : LT;
+    return true;
+}
+
 
 }  // namespace fused
 }  // namespace ptd

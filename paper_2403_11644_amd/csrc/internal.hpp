@@ -102,6 +102,9 @@ constexpr int FUSED_WS_ERR_WORD = 17;
 // fused_workspace_bytes() bytes of queue and group counters; la = lookahead.
 size_t fused_workspace_bytes(int n, ptd_dtype dt);
 // cfg 0 = default shape; see fused.hpp for the others.
+// The single-launch schedule's reading of a setting (0 = the default):
+// workgroup threads, low WHT stages per phase-1 item, X-patterns per group.
+bool describe_fused(int n, ptd_dtype dt, bool herm, int cfg, int* threads, int* phase1_bits, int* group_patterns);
 hipError_t launch_fused_fwd(int n, ptd_dtype dt, bool herm, const void* A, int64_t lda, void* out, void* ws, int la,
                             int cfg, hipStream_t st, bool unscaled = false);
 // Per-dtype instantiations of the single-launch schedule (fused_*.hip).

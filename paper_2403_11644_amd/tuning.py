@@ -45,6 +45,8 @@ def autotune(n: int, dtype_code: int, hermitian: bool = False, reps: int = 5, sa
     if L.ptd_autotune_report(n, dtype_code, api.HERMITIAN if hermitian else 0, ctypes.byref(dms), ctypes.byref(bms),
                              ctypes.byref(spr), ctypes.byref(kept)) == 1:
         rec.update({"default_ms": dms.value, "spread_ms": spr.value, "kept": bool(kept.value)})
+    if n >= 11:
+        rec.update(describe(n, dtype_code, hermitian, cfg.value))
     if save:
         path = cache_path()
         data = {}
@@ -60,6 +62,18 @@ def autotune(n: int, dtype_code: int, hermitian: bool = False, reps: int = 5, sa
             json.dump(data, f, indent=1, sort_keys=True)
         os.replace(tmp, path)
     return rec
+
+
+def describe(n: int, dtype_code: int, hermitian: bool = False, cfg: int = 0) -> dict:
+    """The single-launch schedule's reading of a setting (n = 11..15; cfg 0
+    is the default): workgroup threads, the low WHT stages per phase-1 item
+    (the stage split) and the X-patterns per group (the tile width T)."""
+    th, kap, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    st = _native.lib().ptd_describe_tuning(n, dtype_code, api.HERMITIAN if hermitian else 0, cfg, ctypes.byref(th),
+                                           ctypes.byref(kap), ctypes.byref(t))
+    _native.check(st, "ptd_describe_tuning")
+    return {"threads": th.value, "phase1_bits": kap.value, "phase2_bits": n - kap.value,
+            "group_patterns": t.value}
 
 
 def load(path: str | None = None) -> int:

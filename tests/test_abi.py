@@ -468,3 +468,33 @@ def test_csr_argument_errors(lib):
     assert dec(ws=ctypes.c_void_p(FAKE_A + 3 * (1 << 24) + 4)) == EINVAL
     # compact output: count rows of it, ending 16 bytes into the values
     assert dec(flags=1 << 2, out=ctypes.c_void_p(FAKE_A + 2 * (1 << 24) - 2 * N * 16 + 16)) == EINVAL
+
+
+def test_describe_tuning(lib):
+    """The single-launch settings in the schedule's terms: threads, low WHT
+    stages per phase-1 item (the stage split), X-patterns per group (T)."""
+    from paper_2403_11644_amd import api, tuning
+
+    assert tuning.describe(14, api.C128, False, 1) == {"threads": 1024, "phase1_bits": 10, "phase2_bits": 4,
+                                                       "group_patterns": 8}
+    assert tuning.describe(14, api.C128, False, 2) == {"threads": 512, "phase1_bits": 9, "phase2_bits": 5,
+                                                       "group_patterns": 8}
+    assert tuning.describe(13, api.C64, True, 3 | 4 | 8) == {"threads": 512, "phase1_bits": 10, "phase2_bits": 3,
+                                                             "group_patterns": 8}
+    assert tuning.describe(15, api.C64, False, 1)["group_patterns"] == 16
+    # the default setting is one of the built shapes at every point
+    for n in range(11, 16):
+        for dt in (api.C128, api.C64):
+            for herm in (False, True):
+                if n == 15 and (dt == api.C128 or herm):
+                    continue
+                d = tuning.describe(n, dt, herm, 0)
+                assert d["threads"] in (512, 1024) and d["phase1_bits"] in (9, 10)
+    th, kap, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    args = (ctypes.byref(th), ctypes.byref(kap), ctypes.byref(t))
+    assert lib.ptd_describe_tuning(15, api.C128, 0, 1, *args) == -1  # not built
+    assert lib.ptd_describe_tuning(15, api.C64, 0, 2, *args) == -1  # shape 2 stops at n = 14
+    assert lib.ptd_describe_tuning(10, api.C64, 0, 1, *args) == -1  # the group kernel's plans
+    assert lib.ptd_describe_tuning(14, api.C64, 0, 32, *args) == -1
+    assert lib.ptd_describe_tuning(14, api.C64, 2, 1, *args) == -1
+    assert lib.ptd_describe_tuning(14, api.C64, 0, 1, None, ctypes.byref(kap), ctypes.byref(t)) == -1
