@@ -605,7 +605,7 @@ ptd_status ptd_batch_plan_create(int count, ptd_dtype dtype, unsigned flags, con
     if (e == hipSuccess) {
         // the queue counter is reset by a kernel node (no memset node in the graph)
         hipError_t le = ptd::batched_launch(dtype, flags & PTD_HERMITIAN, rec, flags & PTD_ADJOINT, in_base, out_base,
-                                            p->buf, count, bl, ptd::device_cu_count(), cs);
+                                            p->buf, count, bl, ptd::device_cu_count(), cs, true);
         e = hipStreamEndCapture(cs, &p->graph);
         if (le != hipSuccess) e = le;
     }

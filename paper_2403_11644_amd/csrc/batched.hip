@@ -18,6 +18,7 @@
 //                           apart (only sizes 8..10 take them)
 //                           (zeroed by a kernel before each launch)
 //   [BATCH_HEAD_BYTES, ...) BatchMat[count] then BatchItem[items]
+#include <mutex>
 #include <vector>
 
 #include "engine.hpp"
@@ -218,24 +219,27 @@ void launch_size_plan(int plan, const void* in_base, void* out_base, const Batch
     launch_size<V, NN, HERM, REC, 512, 4>(in_base, out_base, mats, its, begin, end, counter, adj, cus, st);
 }
 
+// The launches of a batch: one per size 10..SMALL_MAX+1 present, largest
+// first, then the shared launch of the small sizes; launch i goes to
+// lanes[i] (all the same stream, or one stream each).
+int batch_launch_count(const BatchLaunch& bl)
+{
+    int k = bl.begin[0] > bl.begin[SMALL_MAX] ? 1 : 0;
+    for (int n = 10; n > SMALL_MAX; --n) k += bl.begin[n - 1] > bl.begin[n] ? 1 : 0;
+    return k;
+}
+
 template <class V, bool HERM, bool REC>
 void launch_all(const BatchLaunch& bl, const void* in_base, void* out_base, const BatchMat* mats,
-                const BatchItem* its, uint32_t* counters, int adj, int cus, hipStream_t st)
+                const BatchItem* its, uint32_t* counters, int adj, int cus, const hipStream_t* lanes)
 {
-    {
-        // sizes 1..SMALL_MAX are contiguous at the end of the list
-        const int b = bl.begin[SMALL_MAX], e = bl.begin[0];
-        if (e > b) {
-            const int cap = SMALL_WGS * cus;
-            hipLaunchKernelGGL((k_batched_small<V, HERM, REC>), dim3(e - b < cap ? e - b : cap), dim3(SMALL_NT), 0, st,
-                               in_base, out_base, mats, its, b, e, adj);
-        }
-    }
+    int li = 0;
     for (int n = 10; n > SMALL_MAX; --n) {
         const int b = bl.begin[n], e = bl.begin[n - 1];
         if (e <= b) continue;
         uint32_t* c = counters + n * COUNTER_STRIDE;
         const int plan = bl.plan[n];
+        const hipStream_t st = lanes[li++];
         switch (n) {
 #define PTD_CASE(NN)                                                                                    \
     case NN:                                                                                            \
@@ -246,6 +250,47 @@ void launch_all(const BatchLaunch& bl, const void* in_base, void* out_base, cons
             default: break;
         }
     }
+    {
+        // sizes 1..SMALL_MAX are contiguous at the end of the list
+        const int b = bl.begin[SMALL_MAX], e = bl.begin[0];
+        if (e > b) {
+            const int cap = SMALL_WGS * cus;
+            hipLaunchKernelGGL((k_batched_small<V, HERM, REC>), dim3(e - b < cap ? e - b : cap), dim3(SMALL_NT), 0,
+                               lanes[li++], in_base, out_base, mats, its, b, e, adj);
+        }
+    }
+}
+
+// Side streams of this device for concurrent batch launches (created once,
+// kept until the process ends), and the events that fork and join them.
+constexpr int MAX_LANES = 4;
+struct SideLanes {
+    bool ready = false;
+    hipStream_t s[MAX_LANES - 1] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[MAX_LANES - 1] = {};
+};
+std::mutex g_lanes_mu;
+SideLanes g_lanes[64];
+
+hipError_t side_lanes(SideLanes** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    SideLanes& L = g_lanes[dev];
+    if (!L.ready) {
+        for (int i = 0; i < MAX_LANES - 1 && e == hipSuccess; ++i) {
+            if (!L.s[i]) e = hipStreamCreateWithFlags(&L.s[i], hipStreamNonBlocking);
+            if (e == hipSuccess && !L.join[i]) e = hipEventCreateWithFlags(&L.join[i], hipEventDisableTiming);
+        }
+        if (e == hipSuccess && !L.fork) e = hipEventCreateWithFlags(&L.fork, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+        L.ready = true;
+    }
+    *out = &L;
+    return hipSuccess;
 }
 
 }  // namespace
@@ -301,7 +346,7 @@ void batched_fill(int count, ptd_dtype dt, bool herm, bool rec, const int32_t* n
 }
 
 hipError_t batched_launch(ptd_dtype dt, bool herm, bool rec, bool adjoint, const void* in_base, void* out_base,
-                          void* buf, int count, const BatchLaunch& bl, int cus, hipStream_t st)
+                          void* buf, int count, const BatchLaunch& bl, int cus, hipStream_t st, bool concurrent)
 {
     uint32_t* counters = (uint32_t*)buf;
     const BatchMat* mats = (const BatchMat*)((unsigned char*)buf + BATCH_HEAD_BYTES);
@@ -311,7 +356,22 @@ hipError_t batched_launch(ptd_dtype dt, bool herm, bool rec, bool adjoint, const
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int adj = adjoint ? 1 : 0;
-#define PTD_ALL(VV, HH, RR) launch_all<VV, HH, RR>(bl, in_base, out_base, mats, its, counters, adj, cus, st)
+    hipStream_t lanes[MAX_LANES] = {st, st, st, st};
+    const int nl = batch_launch_count(bl);
+    SideLanes* L = nullptr;
+    std::unique_lock<std::mutex> lk(g_lanes_mu, std::defer_lock);
+    if (concurrent && nl > 1) {
+        // fork: every launch after the first waits for the counters' reset
+        // on a side stream of its own; the caller's stream joins them all
+        lk.lock();
+        if ((e = side_lanes(&L)) != hipSuccess) return e;
+        if ((e = hipEventRecord(L->fork, st)) != hipSuccess) return e;
+        for (int i = 1; i < nl; ++i) {
+            lanes[i] = L->s[i - 1];
+            if ((e = hipStreamWaitEvent(lanes[i], L->fork, 0)) != hipSuccess) return e;
+        }
+    }
+#define PTD_ALL(VV, HH, RR) launch_all<VV, HH, RR>(bl, in_base, out_base, mats, its, counters, adj, cus, lanes)
     if (dt == PTD_C128) {
         if (rec) {
             if (herm) PTD_ALL(double, true, true); else PTD_ALL(double, false, true);
@@ -326,7 +386,14 @@ hipError_t batched_launch(ptd_dtype dt, bool herm, bool rec, bool adjoint, const
         }
     }
 #undef PTD_ALL
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (L) {
+        for (int i = 1; i < nl; ++i) {
+            if ((e = hipEventRecord(L->join[i - 1], lanes[i])) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(st, L->join[i - 1], 0)) != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
 }
 
 }  // namespace ptd

@@ -196,8 +196,12 @@ size_t batched_buffer_bytes(int count, ptd_dtype dt, const int32_t* n_host);
 // takes each size's tuned or default plan (forward only).
 void batched_fill(int count, ptd_dtype dt, bool herm, bool rec, const int32_t* n_host, const int64_t* in_off,
                   const int64_t* out_off, std::vector<unsigned char>& img, BatchLaunch* bl, int force_plan = -1);
+// concurrent: the per-size launches go to side streams forked from st after
+// the counter reset and joined back into st, so each can take the CUs the
+// previous one leaves as it drains (within a graph capture: parallel branches)
 hipError_t batched_launch(ptd_dtype dt, bool herm, bool rec, bool adjoint, const void* in_base, void* out_base,
-                          void* buf, int count, const BatchLaunch& bl, int cus, hipStream_t st);
+                          void* buf, int count, const BatchLaunch& bl, int cus, hipStream_t st,
+                          bool concurrent = false);
 
 // Combinations of decompositions (algebra.hip).  Block i of a block-diagonal
 // assembly is read from blocks.p[i] (4^k elements each, 2^m blocks, m <= 5).
