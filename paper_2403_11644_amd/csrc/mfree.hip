@@ -18,9 +18,12 @@
 // round into registers, and finishes there with the butterfly over the top
 // bit.
 //
-// Every path applies the radix-2 stages in ascending bit order with the same
-// additions as the kernels for stored matrices, so a matrix-free call gives
-// the bits of a dense call on the materialised matrix.
+// For a Toeplitz source every path applies the radix-2 stages in ascending
+// bit order with the same additions as the kernels for stored matrices, so a
+// matrix-free call gives the bits of a dense call on the materialised
+// matrix.  The density-matrix sources take a real transform per row, two
+// rows per workgroup (mf_paired below): the same coefficients within
+// rounding, half the transform work.
 //
 // The kernels are bound by LDS traffic as much as by the output writes, so
 // the two-halves kernel keeps each half's last round in registers (the
@@ -92,9 +95,23 @@ struct MfWrite {
     }
 };
 
-// d_x[kb + p] for the 2^LM positions p, into LDS; consecutive lanes take
-// consecutive positions, so the source reads of a wave stay within a few
-// cache lines
+// Density-matrix sources (a state vector or a low-rank factor) are
+// Hermitian by construction, which halves their transform: the row
+// transform W = WHT(d_x) of Hermitian input is real where popcount(x & z) is
+// even and imaginary where it is odd (pairing k with k ^ x), so the real
+// transform of e_x = Re d_x + Im d_x equals the nonzero part of W at every
+// z, and the coefficient is s(p) WHT(e_x)[z] 2^-n with p = popcount(x & z)
+// mod 4 and s = +1, -1, -1, +1 for p = 0..3.  Two real rows travel as one
+// complex row: the workgroup of pair j transforms e_{2j} + i e_{2j+1}.
+template <int SRC>
+constexpr bool mf_paired()
+{
+    return SRC == SRC_PURE || SRC == SRC_LOWRANK || SRC == SRC_LOWRANK_T;
+}
+
+// d_x[kb + p] for the 2^LM positions p, into LDS (or, paired, e_x + i e_{x+1}
+// for even x); consecutive lanes take consecutive positions, so the source
+// reads of a wave stay within a few cache lines
 template <class V, int LM, int NT, int SRC>
 __device__ __forceinline__ void mf_gather(const cplx<V>* __restrict__ src, int64_t ld, int logn, uint32_t x, int kb,
                                           cplx<V>* lds)
@@ -102,7 +119,16 @@ __device__ __forceinline__ void mf_gather(const cplx<V>* __restrict__ src, int64
 #pragma unroll 4
     for (int p = threadIdx.x; p < (1 << LM); p += NT) {
         const int k = kb + p;
-        lds[mf_slot<V>(p)] = source_entry<V, SRC>(src, ld, logn, k, k ^ (int)x);
+        if constexpr (mf_paired<SRC>()) {
+            const cplx<V> a = source_entry<V, SRC>(src, ld, logn, k, k ^ (int)x);
+            const cplx<V> b = source_entry<V, SRC>(src, ld, logn, k, k ^ (int)(x | 1u));
+            cplx<V> v;
+            v.re = a.re + a.im;
+            v.im = b.re + b.im;
+            lds[mf_slot<V>(p)] = v;
+        } else {
+            lds[mf_slot<V>(p)] = source_entry<V, SRC>(src, ld, logn, k, k ^ (int)x);
+        }
     }
 }
 
@@ -176,17 +202,59 @@ __device__ __forceinline__ void mf_store(void* __restrict__ out, int logn, uint3
     }
 }
 
+// Paired rows x (even) and x + 1 from the transform value (re, im) at z:
+// s(p) re to row x, s(p') im to row x + 1 (imaginary parts 0 in complex output)
+template <class V, bool REAL_OUT>
+__device__ __forceinline__ void mf_store_pair(void* __restrict__ out, int logn, uint32_t x, uint32_t z, V re, V im,
+                                              V scale)
+{
+    const int p0 = __popc(x & z) & 3, p1 = __popc((x | 1u) & z) & 3;
+    V v0 = re * scale, v1 = im * scale;
+    if ((p0 + 1) & 2) v0 = -v0;
+    if ((p1 + 1) & 2) v1 = -v1;
+    const int64_t o0 = ((int64_t)x << logn) + z, o1 = o0 + ((int64_t)1 << logn);
+    if constexpr (REAL_OUT) {
+        __builtin_nontemporal_store(v0, (V*)out + o0);
+        __builtin_nontemporal_store(v1, (V*)out + o1);
+    } else {
+        typedef V v2 __attribute__((ext_vector_type(2)));
+        v2 a, b;
+        a.x = v0;
+        a.y = (V)0;
+        b.x = v1;
+        b.y = (V)0;
+        __builtin_nontemporal_store(a, (v2*)out + o0);
+        __builtin_nontemporal_store(b, (v2*)out + o1);
+    }
+}
+
+template <class V, bool REAL_OUT, int SRC>
+__device__ __forceinline__ void mf_put(void* __restrict__ out, int logn, uint32_t x, uint32_t z, V re, V im, V scale)
+{
+    if constexpr (mf_paired<SRC>())
+        mf_store_pair<V, REAL_OUT>(out, logn, x, z, re, im, scale);
+    else
+        mf_store<V, REAL_OUT>(out, logn, x, z, re, im, scale);
+}
+
+// X-pattern (the first of the pair, for paired sources) of this workgroup
+template <int SRC>
+__device__ __forceinline__ uint32_t mf_row()
+{
+    return mf_paired<SRC>() ? blockIdx.x << 1 : blockIdx.x;
+}
+
 template <class V, int LOGN, bool REAL_OUT, int SRC>
 __global__ __launch_bounds__(mf_threads(LOGN)) void k_mfree_row(const cplx<V>* __restrict__ src, int64_t ld,
                                                                 void* __restrict__ out)
 {
     constexpr int NT = mf_threads(LOGN);
     __shared__ cplx<V> lds[mf_lds_elems<V>(LOGN)];
-    const uint32_t x = blockIdx.x;
+    const uint32_t x = mf_row<SRC>();
     const V scale = exp2_neg<V>(LOGN);
     mf_gather<V, LOGN, NT, SRC>(src, ld, LOGN, x, 0, lds);
     __syncthreads();
-    auto store = [&](int, int pos, V re, V im) { mf_store<V, REAL_OUT>(out, LOGN, x, (uint32_t)pos, re, im, scale); };
+    auto store = [&](int, int pos, V re, V im) { mf_put<V, REAL_OUT, SRC>(out, LOGN, x, (uint32_t)pos, re, im, scale); };
     mf_rounds<V, LOGN, NT, mf_rmax<V>(), 0>(lds, store);
 }
 
@@ -199,7 +267,7 @@ __global__ __launch_bounds__(MF_HALF_THREADS) void k_mfree_halves(const cplx<V>*
     constexpr int RM = mf_rmax<V>();
     constexpr int LB0 = ((LH - 1) / RM) * RM;  // first bit of the last round
     __shared__ cplx<V> lds[mf_lds_elems<V>(LH)];
-    const uint32_t x = blockIdx.x;
+    const uint32_t x = mf_row<SRC>();
     const int t = threadIdx.x;
 
     // the transform over bits 0 .. LH-1 of half h: the rounds below LB0 in
@@ -222,9 +290,9 @@ __global__ __launch_bounds__(MF_HALF_THREADS) void k_mfree_halves(const cplx<V>*
 #pragma unroll
         for (int m = 0; m < w0.R; ++m) {
             const uint32_t z = (uint32_t)(t + NT * i + (m << LB0));
-            mf_store<V, REAL_OUT>(out, LOGN, x, z, w0.re[i][m] + w1.re[i][m], w0.im[i][m] + w1.im[i][m], scale);
-            mf_store<V, REAL_OUT>(out, LOGN, x, z | (1u << LH), w0.re[i][m] - w1.re[i][m],
-                                  w0.im[i][m] - w1.im[i][m], scale);
+            mf_put<V, REAL_OUT, SRC>(out, LOGN, x, z, w0.re[i][m] + w1.re[i][m], w0.im[i][m] + w1.im[i][m], scale);
+            mf_put<V, REAL_OUT, SRC>(out, LOGN, x, z | (1u << LH), w0.re[i][m] - w1.re[i][m],
+                                     w0.im[i][m] - w1.im[i][m], scale);
         }
     }
 }
@@ -232,7 +300,7 @@ __global__ __launch_bounds__(MF_HALF_THREADS) void k_mfree_halves(const cplx<V>*
 template <class V, bool REAL_OUT, int SRC>
 hipError_t mfree_t(int n, const void* src, int64_t ld, void* out, hipStream_t st)
 {
-    const dim3 grid(1u << n);
+    const dim3 grid(mf_paired<SRC>() ? 1u << (n - 1) : 1u << n);
     const cplx<V>* s = (const cplx<V>*)src;
     switch (n) {
 #define PTD_ROW(NN)                                                                                         \
