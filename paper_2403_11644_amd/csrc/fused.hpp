@@ -459,7 +459,14 @@ __global__ __launch_bounds__(S::NT, 4) void k_fused_fwd(const cplx<V>* __restric
                                                      void* __restrict__ out, uint32_t* __restrict__ ws, int Q,
                                                      int LA, WaitLimits wl, V unit)
 {
-    constexpr int NP1 = S::NP1, NP2 = S::NP2, NG = S::NG;
+    // Hermitian phase-2 rows are half the bytes of complex ones: several per
+    // item (one ticket and one counter wait for all of them).  Measured at
+    // n = 13: complex64 0.2045 / 0.190 / 0.187 ms with 1 / 2 / 4 rows per
+    // item, complex128 unchanged with 2; complex rows stay one per item
+    // (2 per item: n = 15 complex64 4.94 -> 6.64 ms)
+    constexpr int P2M = HERM ? (sizeof(V) == 4 ? 4 : 2) : 1;
+    constexpr int NP1 = S::NP1, NP2 = S::NP2 / P2M, NG = S::NG;
+    static_assert(S::NP2 % P2M == 0, "whole phase-2 pairs");
     __shared__ cplx<V> lds[(1 << S::LOGT) * ((1 << S::KAP) + 1)];
     __shared__ int s_next;
     __shared__ int s_last;
@@ -493,7 +500,8 @@ __global__ __launch_bounds__(S::NT, 4) void k_fused_fwd(const cplx<V>* __restric
                 publish(it.group);
             } else {
                 const bool failed = wait_group(it.group);
-                phase2<V, S, HERM, POL>(out, it.group, it.sub, lds, failed, unit);
+#pragma unroll
+                for (int u = 0; u < P2M; ++u) phase2<V, S, HERM, POL>(out, it.group, it.sub * P2M + u, lds, failed, unit);
             }
             __syncthreads();  // LDS reuse, s_next reuse
             if (threadIdx.x == 0)
