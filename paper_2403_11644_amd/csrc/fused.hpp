@@ -463,7 +463,11 @@ __global__ __launch_bounds__(S::NT, 4) void k_fused_fwd(const cplx<V>* __restric
     // item (one ticket and one counter wait for all of them).  Measured at
     // n = 13: complex64 0.2045 / 0.190 / 0.187 ms with 1 / 2 / 4 rows per
     // item, complex128 unchanged with 2; complex rows stay one per item
-    // (2 per item: n = 15 complex64 4.94 -> 6.64 ms)
+    // (2 per item: n = 15 complex64 4.94 -> 6.64 ms).  Listing only the
+    // Hermitian phase-1 blocks that do work (half the items where a block's
+    // mirror is another block) measured 0.187 -> 0.185 ms complex64 but
+    // 0.342 -> 0.368 ms complex128: phase-2 items reach their group sooner
+    // and wait, so the empty items stay
     constexpr int P2M = HERM ? (sizeof(V) == 4 ? 4 : 2) : 1;
     constexpr int NP1 = S::NP1, NP2 = S::NP2 / P2M, NG = S::NG;
     static_assert(S::NP2 % P2M == 0, "whole phase-2 pairs");
