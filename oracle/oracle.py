@@ -393,6 +393,37 @@ def sparse_nonempty_x(n: int, rows, cols) -> list[int]:
     return sorted({int(x) for x in (rows[ok] ^ cols[ok])})
 
 
+def sparse_coeffs(n: int, rows, cols, vals, xs, zs) -> np.ndarray:
+    """Coefficients (xs[i], zs[i]) of the matrix with these coordinate
+    entries (repeats summed, entries outside [0, 2^n) dropped), from the
+    entries alone, for sizes whose dense matrix does not fit in memory.
+    Algorithm 2's sum over k reads A[k][k ^ x], which is nonzero only at
+    stored entries, so c[x][z] = 2^-n i^popcount(x & z) times the sum, over
+    the entries (r, c, v) with r ^ c = x, of (-1)^popcount(z & r) v.
+    A loop over the requested strings (float64)."""
+    N = 1 << n
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    vals = np.asarray(vals).astype(np.complex128)
+    ok = (rows >= 0) & (rows < N) & (cols >= 0) & (cols < N)
+    rows, cols, vals = rows[ok], cols[ok], vals[ok]
+    xe = rows ^ cols
+    order = np.argsort(xe, kind="stable")
+    xe, re_, ve = xe[order], rows[order], vals[order]
+    out = np.empty(len(xs), dtype=np.complex128)
+    for i, (x, z) in enumerate(zip(xs, zs)):
+        x, z = int(x), int(z)
+        lo, hi = np.searchsorted(xe, x, "left"), np.searchsorted(xe, x, "right")
+        r = re_[lo:hi]
+        par = np.zeros(len(r), dtype=np.int64)
+        zr = r & z
+        for b in range(n):  # parity of popcount(z & r), bit by bit
+            par ^= (zr >> b) & 1
+        total = np.sum(np.where(par == 1, -ve[lo:hi], ve[lo:hi]))
+        out[i] = (1j ** (bin(x & z).count("1") % 4)) * total / N
+    return out
+
+
 def csr_to_coo(n: int, row_ptr, col_idx, vals):
     """The coordinate entries (rows, cols, vals) of a matrix in compressed
     row form: row r holds the entries row_ptr[r] .. row_ptr[r + 1] - 1 of

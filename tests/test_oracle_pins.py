@@ -421,6 +421,24 @@ def test_sparse_support(oracle_mod):
     assert nz == oracle_mod.sparse_nonempty_x(n, rows, cols)
 
 
+def test_sparse_coeffs_from_entries(oracle_mod):
+    # the sum over stored entries equals the dense oracle on the assembled
+    # matrix (repeats, out-of-range entries, every string of a small case)
+    n = 5
+    N = 1 << n
+    rng = np.random.default_rng(89)
+    rows = rng.integers(0, N, size=40)
+    cols = rng.integers(0, N, size=40)
+    rows[:3], cols[:3] = rows[3:6], cols[3:6]  # repeats
+    rows = np.append(rows, [N, -2])
+    cols = np.append(cols, [1, 0])
+    vals = rng.standard_normal(42) + 1j * rng.standard_normal(42)
+    A = oracle_mod.sparse_to_dense(n, rows, cols, vals)
+    xs, zs = np.divmod(np.arange(N * N), N)
+    got = oracle_mod.sparse_coeffs(n, rows, cols, vals, xs, zs)
+    np.testing.assert_allclose(got, oracle_mod.coeffs(A, xs, zs), rtol=0, atol=1e-14)
+
+
 def test_csr_matches_scipy(oracle_mod):
     # compressed rows: the assembled matrix equals scipy's own conversion of
     # the same arrays (repeated columns in a row summed), and the X-pattern
