@@ -255,3 +255,42 @@ def test_csr_clipped_pointers(ptd, oracle_mod):
     assert xs.numel() == 0 and float(got.abs().max()) == 0.0
     got, xs = ptd.decompose_csr(rp0, e32, ev, n, compact=True)
     assert got.shape == (0, N)
+
+
+@pytest.mark.parametrize("dt", [np.complex128, np.complex64])
+def test_sparse_and_csr_at_n16(ptd, oracle_mod, dt):
+    """The largest size (n = 16): a tridiagonal matrix plus 64 scattered
+    entries, as coordinates and as compressed rows, compact output.  The
+    X-pattern lists equal the oracle's, the two forms agree bit for bit (no
+    repeated coordinate), and sampled strings of every listed row equal the
+    oracle's sum over the stored entries."""
+    n = 16
+    N = 1 << n
+    rng = np.random.default_rng(740)
+    r = np.repeat(np.arange(N), 3)
+    c = r + np.tile(np.array([-1, 0, 1]), N)
+    keep = (c >= 0) & (c < N)
+    r, c = r[keep], c[keep]
+    sr = rng.integers(0, N, size=64)
+    sc = (sr + rng.integers(2, N - 2, size=64)) % N  # off the three diagonals
+    pairs = sorted(set(zip(sr.tolist(), sc.tolist())))
+    r = np.append(r, [p[0] for p in pairs])
+    c = np.append(c, [p[1] for p in pairs])
+    vals = synth.complex_normal(len(r), seed=741, dtype=dt)
+    want_xs = oracle_mod.sparse_nonempty_x(n, r, c)
+    got, xs = ptd.decompose_sparse(to_dev(r.astype(np.int32)), to_dev(c.astype(np.int32)), to_dev(vals), n,
+                                   compact=True)
+    assert to_host(xs).tolist() == want_xs
+    order = np.argsort(r, kind="stable")
+    row_ptr = np.concatenate([[0], np.cumsum(np.bincount(r, minlength=N))]).astype(np.int64)
+    got_csr, xs_csr = ptd.decompose_csr(to_dev(row_ptr), to_dev(c[order].astype(np.int32)), to_dev(vals[order]), n,
+                                        compact=True)
+    assert to_host(xs_csr).tolist() == want_xs
+    g = to_host(got)
+    np.testing.assert_array_equal(to_host(got_csr), g)
+    zs = rng.integers(0, N, size=(len(want_xs), 4))
+    xq = np.repeat(np.array(want_xs), 4)
+    zq = zs.reshape(-1)
+    want = oracle_mod.sparse_coeffs(n, r, c, vals, xq, zq)
+    idx = np.repeat(np.arange(len(want_xs)), 4)
+    assert rel_err(g[idx, zq], want) <= TOL[dt]
