@@ -600,6 +600,7 @@ ptd_status ptd_batch_plan_create(int count, ptd_dtype dtype, unsigned flags, con
     }
     hipError_t e = hipMemcpy((unsigned char*)p->buf + ptd::BATCH_HEAD_BYTES, img.data(), img.size(), hipMemcpyHostToDevice);
     hipStream_t cs = nullptr;
+    if (e == hipSuccess) e = ptd::prepare_batch_lanes();
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {

@@ -295,6 +295,13 @@ hipError_t side_lanes(SideLanes** out)
 
 }  // namespace
 
+hipError_t prepare_batch_lanes()
+{
+    std::lock_guard<std::mutex> lk(g_lanes_mu);
+    SideLanes* L = nullptr;
+    return side_lanes(&L);
+}
+
 int64_t batched_item_count(int count, ptd_dtype dt, const int32_t* n_host)
 {
     int64_t items = 0;

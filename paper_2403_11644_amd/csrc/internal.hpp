@@ -202,6 +202,9 @@ void batched_fill(int count, ptd_dtype dt, bool herm, bool rec, const int32_t* n
 hipError_t batched_launch(ptd_dtype dt, bool herm, bool rec, bool adjoint, const void* in_base, void* out_base,
                           void* buf, int count, const BatchLaunch& bl, int cus, hipStream_t st,
                           bool concurrent = false);
+// Creates this device's side streams and events for concurrent launches
+// (once); called before a graph capture so that none is created inside it.
+hipError_t prepare_batch_lanes();
 
 // Combinations of decompositions (algebra.hip).  Block i of a block-diagonal
 // assembly is read from blocks.p[i] (4^k elements each, 2^m blocks, m <= 5).

@@ -21,9 +21,9 @@
 // For a Toeplitz source every path applies the radix-2 stages in ascending
 // bit order with the same additions as the kernels for stored matrices, so a
 // matrix-free call gives the bits of a dense call on the materialised
-// matrix.  The density-matrix sources take a real transform per row, two
-// rows per workgroup (mf_paired below): the same coefficients within
-// rounding, half the transform work.
+// matrix.  The density-matrix sources take one real transform per row (real
+// rows below): the same coefficients within rounding, half the transform
+// work and half the LDS per row.
 //
 // The kernels are bound by LDS traffic as much as by the output writes, so
 // the two-halves kernel keeps each half's last round in registers (the
@@ -95,23 +95,9 @@ struct MfWrite {
     }
 };
 
-// Density-matrix sources (a state vector or a low-rank factor) are
-// Hermitian by construction, which halves their transform: the row
-// transform W = WHT(d_x) of Hermitian input is real where popcount(x & z) is
-// even and imaginary where it is odd (pairing k with k ^ x), so the real
-// transform of e_x = Re d_x + Im d_x equals the nonzero part of W at every
-// z, and the coefficient is s(p) WHT(e_x)[z] 2^-n with p = popcount(x & z)
-// mod 4 and s = +1, -1, -1, +1 for p = 0..3.  Two real rows travel as one
-// complex row: the workgroup of pair j transforms e_{2j} + i e_{2j+1}.
-template <int SRC>
-constexpr bool mf_paired()
-{
-    return SRC == SRC_PURE || SRC == SRC_LOWRANK || SRC == SRC_LOWRANK_T;
-}
-
-// d_x[kb + p] for the 2^LM positions p, into LDS (or, paired, e_x + i e_{x+1}
-// for even x); consecutive lanes take consecutive positions, so the source
-// reads of a wave stay within a few cache lines
+// d_x[kb + p] for the 2^LM positions p, into LDS; consecutive lanes take
+// consecutive positions, so the source reads of a wave stay within a few
+// cache lines
 template <class V, int LM, int NT, int SRC>
 __device__ __forceinline__ void mf_gather(const cplx<V>* __restrict__ src, int64_t ld, int logn, uint32_t x, int kb,
                                           cplx<V>* lds)
@@ -119,16 +105,7 @@ __device__ __forceinline__ void mf_gather(const cplx<V>* __restrict__ src, int64
 #pragma unroll 4
     for (int p = threadIdx.x; p < (1 << LM); p += NT) {
         const int k = kb + p;
-        if constexpr (mf_paired<SRC>()) {
-            const cplx<V> a = source_entry<V, SRC>(src, ld, logn, k, k ^ (int)x);
-            const cplx<V> b = source_entry<V, SRC>(src, ld, logn, k, k ^ (int)(x | 1u));
-            cplx<V> v;
-            v.re = a.re + a.im;
-            v.im = b.re + b.im;
-            lds[mf_slot<V>(p)] = v;
-        } else {
-            lds[mf_slot<V>(p)] = source_entry<V, SRC>(src, ld, logn, k, k ^ (int)x);
-        }
+        lds[mf_slot<V>(p)] = source_entry<V, SRC>(src, ld, logn, k, k ^ (int)x);
     }
 }
 
@@ -202,59 +179,17 @@ __device__ __forceinline__ void mf_store(void* __restrict__ out, int logn, uint3
     }
 }
 
-// Paired rows x (even) and x + 1 from the transform value (re, im) at z:
-// s(p) re to row x, s(p') im to row x + 1 (imaginary parts 0 in complex output)
-template <class V, bool REAL_OUT>
-__device__ __forceinline__ void mf_store_pair(void* __restrict__ out, int logn, uint32_t x, uint32_t z, V re, V im,
-                                              V scale)
-{
-    const int p0 = __popc(x & z) & 3, p1 = __popc((x | 1u) & z) & 3;
-    V v0 = re * scale, v1 = im * scale;
-    if ((p0 + 1) & 2) v0 = -v0;
-    if ((p1 + 1) & 2) v1 = -v1;
-    const int64_t o0 = ((int64_t)x << logn) + z, o1 = o0 + ((int64_t)1 << logn);
-    if constexpr (REAL_OUT) {
-        __builtin_nontemporal_store(v0, (V*)out + o0);
-        __builtin_nontemporal_store(v1, (V*)out + o1);
-    } else {
-        typedef V v2 __attribute__((ext_vector_type(2)));
-        v2 a, b;
-        a.x = v0;
-        a.y = (V)0;
-        b.x = v1;
-        b.y = (V)0;
-        __builtin_nontemporal_store(a, (v2*)out + o0);
-        __builtin_nontemporal_store(b, (v2*)out + o1);
-    }
-}
-
-template <class V, bool REAL_OUT, int SRC>
-__device__ __forceinline__ void mf_put(void* __restrict__ out, int logn, uint32_t x, uint32_t z, V re, V im, V scale)
-{
-    if constexpr (mf_paired<SRC>())
-        mf_store_pair<V, REAL_OUT>(out, logn, x, z, re, im, scale);
-    else
-        mf_store<V, REAL_OUT>(out, logn, x, z, re, im, scale);
-}
-
-// X-pattern (the first of the pair, for paired sources) of this workgroup
-template <int SRC>
-__device__ __forceinline__ uint32_t mf_row()
-{
-    return mf_paired<SRC>() ? blockIdx.x << 1 : blockIdx.x;
-}
-
 template <class V, int LOGN, bool REAL_OUT, int SRC>
 __global__ __launch_bounds__(mf_threads(LOGN)) void k_mfree_row(const cplx<V>* __restrict__ src, int64_t ld,
                                                                 void* __restrict__ out)
 {
     constexpr int NT = mf_threads(LOGN);
     __shared__ cplx<V> lds[mf_lds_elems<V>(LOGN)];
-    const uint32_t x = mf_row<SRC>();
+    const uint32_t x = blockIdx.x;
     const V scale = exp2_neg<V>(LOGN);
     mf_gather<V, LOGN, NT, SRC>(src, ld, LOGN, x, 0, lds);
     __syncthreads();
-    auto store = [&](int, int pos, V re, V im) { mf_put<V, REAL_OUT, SRC>(out, LOGN, x, (uint32_t)pos, re, im, scale); };
+    auto store = [&](int, int pos, V re, V im) { mf_store<V, REAL_OUT>(out, LOGN, x, (uint32_t)pos, re, im, scale); };
     mf_rounds<V, LOGN, NT, mf_rmax<V>(), 0>(lds, store);
 }
 
@@ -267,7 +202,7 @@ __global__ __launch_bounds__(MF_HALF_THREADS) void k_mfree_halves(const cplx<V>*
     constexpr int RM = mf_rmax<V>();
     constexpr int LB0 = ((LH - 1) / RM) * RM;  // first bit of the last round
     __shared__ cplx<V> lds[mf_lds_elems<V>(LH)];
-    const uint32_t x = mf_row<SRC>();
+    const uint32_t x = blockIdx.x;
     const int t = threadIdx.x;
 
     // the transform over bits 0 .. LH-1 of half h: the rounds below LB0 in
@@ -290,17 +225,217 @@ __global__ __launch_bounds__(MF_HALF_THREADS) void k_mfree_halves(const cplx<V>*
 #pragma unroll
         for (int m = 0; m < w0.R; ++m) {
             const uint32_t z = (uint32_t)(t + NT * i + (m << LB0));
-            mf_put<V, REAL_OUT, SRC>(out, LOGN, x, z, w0.re[i][m] + w1.re[i][m], w0.im[i][m] + w1.im[i][m], scale);
-            mf_put<V, REAL_OUT, SRC>(out, LOGN, x, z | (1u << LH), w0.re[i][m] - w1.re[i][m],
-                                     w0.im[i][m] - w1.im[i][m], scale);
+            mf_store<V, REAL_OUT>(out, LOGN, x, z, w0.re[i][m] + w1.re[i][m], w0.im[i][m] + w1.im[i][m], scale);
+            mf_store<V, REAL_OUT>(out, LOGN, x, z | (1u << LH), w0.re[i][m] - w1.re[i][m],
+                                  w0.im[i][m] - w1.im[i][m], scale);
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Real rows.  Density-matrix sources (a state vector or a low-rank factor)
+// are Hermitian by construction, which halves their transform: the row
+// transform W = WHT(d_x) of Hermitian input is real where popcount(x & z) is
+// even and imaginary where it is odd (pairing k with k ^ x), so the real
+// transform of e_x = Re d_x + Im d_x equals the nonzero part of W at every
+// z, and the coefficient is s(p) WHT(e_x)[z] 2^-n with p = popcount(x & z)
+// mod 4 and s = +1, -1, -1, +1 for p = 0..3.  One workgroup per X-pattern
+// holds the real row (or half-row) in LDS, at most 64 KiB, so two
+// workgroups share a CU.  The rounds are the complex ones with a reader
+// that returns 0 for the imaginary part (folded away) and a writer that
+// drops it; the stages keep their ascending order.
+template <class V>
+__device__ __forceinline__ int mf_slot_r(int p)
+{
+    return p + (p >> 4);
+}
+template <class V>
+constexpr int mf_lds_r(int logm)
+{
+    return (1 << logm) + (1 << (logm - 4));
+}
+
+template <class V>
+struct MfReadR {
+    const V* p;
+    __device__ __forceinline__ void operator()(int, int pos, V& re, V& im) const
+    {
+        re = p[mf_slot_r<V>(pos)];
+        im = (V)0;
+    }
+};
+
+template <class V>
+struct MfWriteR {
+    V* p;
+    __device__ __forceinline__ void operator()(int, int pos, V re, V) const { p[mf_slot_r<V>(pos)] = re; }
+};
+
+template <class V, int LM, int NT, int RMAX, int B0, int END>
+__device__ __forceinline__ void mf_rounds_to_r(V* lds)
+{
+    if constexpr (B0 < END) {
+        constexpr int NB = (END - B0) < RMAX ? (END - B0) : RMAX;
+        wht_round<V, 0, LM, B0, NB, NT, false>(MfReadR<V>{lds}, MfWriteR<V>{lds});
+        __syncthreads();
+        mf_rounds_to_r<V, LM, NT, RMAX, B0 + NB, END>(lds);
+    }
+}
+
+template <class V, int LM, int NT, int RMAX, int B0, class Last>
+__device__ __forceinline__ void mf_rounds_r(V* lds, const Last& last)
+{
+    constexpr int NB = (LM - B0) < RMAX ? (LM - B0) : RMAX;
+    if constexpr (B0 + NB == LM) {
+        wht_round<V, 0, LM, B0, NB, NT, false>(MfReadR<V>{lds}, last);
+    } else {
+        wht_round<V, 0, LM, B0, NB, NT, false>(MfReadR<V>{lds}, MfWriteR<V>{lds});
+        __syncthreads();
+        mf_rounds_r<V, LM, NT, RMAX, B0 + NB>(lds, last);
+    }
+}
+
+// e_x[kb + p] = Re d + Im d for the 2^LM positions p
+template <class V, int LM, int NT, int SRC>
+__device__ __forceinline__ void mf_gather_r(const cplx<V>* __restrict__ src, int64_t ld, int logn, uint32_t x,
+                                            int kb, V* lds)
+{
+#pragma unroll 4
+    for (int p = threadIdx.x; p < (1 << LM); p += NT) {
+        const int k = kb + p;
+        const cplx<V> d = source_entry<V, SRC>(src, ld, logn, k, k ^ (int)x);
+        lds[mf_slot_r<V>(p)] = d.re + d.im;
+    }
+}
+
+// coefficient s(p) v 2^-n of row x at z (imaginary part 0 in complex output)
+template <class V, bool REAL_OUT>
+__device__ __forceinline__ void mf_store_r(void* __restrict__ out, int logn, uint32_t x, uint32_t z, V v, V scale)
+{
+    v *= scale;
+    if ((__popc(x & z) + 1) & 2) v = -v;
+    const int64_t o = ((int64_t)x << logn) + z;
+    if constexpr (REAL_OUT) {
+        __builtin_nontemporal_store(v, (V*)out + o);
+    } else {
+        typedef V v2 __attribute__((ext_vector_type(2)));
+        v2 a;
+        a.x = v;
+        a.y = (V)0;
+        __builtin_nontemporal_store(a, (v2*)out + o);
+    }
+}
+
+constexpr int MFR_THREADS = 512;
+
+template <class V, int LOGN, bool REAL_OUT, int SRC>
+__global__ __launch_bounds__(MFR_THREADS, 4) void k_mfree_row_r(const cplx<V>* __restrict__ src, int64_t ld,
+                                                                void* __restrict__ out)
+{
+    constexpr int NT = MFR_THREADS;
+    __shared__ V lds[mf_lds_r<V>(LOGN)];
+    const uint32_t x = blockIdx.x;
+    const V scale = exp2_neg<V>(LOGN);
+    mf_gather_r<V, LOGN, NT, SRC>(src, ld, LOGN, x, 0, lds);
+    __syncthreads();
+    auto store = [&](int, int pos, V re, V) { mf_store_r<V, REAL_OUT>(out, LOGN, x, (uint32_t)pos, re, scale); };
+    mf_rounds_r<V, LOGN, NT, 4, 0>(lds, store);
+}
+
+template <class V, int LM, int NT, int B0>
+struct MfLastR {
+    static constexpr int NB = LM - B0, R = 1 << NB, ITER = (1 << B0) / NT;
+    static_assert(ITER >= 1 && ITER * NT == (1 << B0), "whole items per thread");
+    V re[ITER][R];
+    __device__ __forceinline__ void run(const V* lds)
+    {
+#pragma unroll
+        for (int i = 0; i < ITER; ++i) {
+            const int base = (int)threadIdx.x + NT * i;
+            V im[R];
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                re[i][m] = lds[mf_slot_r<V>(base + (m << B0))];
+                im[m] = (V)0;
+            }
+            wht_reg<V, NB>(re[i], im);
+        }
+    }
+};
+
+template <class V, int LOGN, bool REAL_OUT, int SRC>
+__global__ __launch_bounds__(MFR_THREADS, 4) void k_mfree_halves_r(const cplx<V>* __restrict__ src, int64_t ld,
+                                                                   void* __restrict__ out)
+{
+    constexpr int LH = LOGN - 1;
+    constexpr int NT = MFR_THREADS;
+    constexpr int LB0 = ((LH - 1) / 4) * 4;  // first bit of the last round
+    __shared__ V lds[mf_lds_r<V>(LH)];
+    const uint32_t x = blockIdx.x;
+    const int t = threadIdx.x;
+    auto half = [&](int h, MfLastR<V, LH, NT, LB0>& r) {
+        mf_gather_r<V, LH, NT, SRC>(src, ld, LOGN, x, h << LH, lds);
+        __syncthreads();
+        mf_rounds_to_r<V, LH, NT, 4, 0, LB0>(lds);
+        r.run(lds);
+        __syncthreads();
+    };
+    MfLastR<V, LH, NT, LB0> w0, w1;
+    half(0, w0);
+    half(1, w1);
+    const V scale = exp2_neg<V>(LOGN);
+#pragma unroll
+    for (int i = 0; i < w0.ITER; ++i) {
+#pragma unroll
+        for (int m = 0; m < w0.R; ++m) {
+            const uint32_t z = (uint32_t)(t + NT * i + (m << LB0));
+            mf_store_r<V, REAL_OUT>(out, LOGN, x, z, w0.re[i][m] + w1.re[i][m], scale);
+            mf_store_r<V, REAL_OUT>(out, LOGN, x, z | (1u << LH), w0.re[i][m] - w1.re[i][m], scale);
+        }
+    }
+}
+
+template <int SRC>
+constexpr bool mf_real_rows()
+{
+    return SRC == SRC_PURE || SRC == SRC_LOWRANK || SRC == SRC_LOWRANK_T;
+}
+
+template <class V, bool REAL_OUT, int SRC>
+hipError_t mfree_real_t(int n, const void* src, int64_t ld, void* out, hipStream_t st)
+{
+    const dim3 grid(1u << n);
+    const cplx<V>* s = (const cplx<V>*)src;
+    constexpr int FULL_MAX = sizeof(V) == 8 ? 13 : 14;  // 2^n values in 64 KiB
+    switch (n) {
+#define PTD_ROWR(NN)                                                                                          \
+    case NN:                                                                                                  \
+        if constexpr (NN <= FULL_MAX)                                                                         \
+            hipLaunchKernelGGL((k_mfree_row_r<V, NN, REAL_OUT, SRC>), grid, dim3(MFR_THREADS), 0, st, s, ld, out); \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_mfree_halves_r<V, NN, REAL_OUT, SRC>), grid, dim3(MFR_THREADS), 0, st, s, ld,  \
+                               out);                                                                          \
+        break;
+        PTD_ROWR(11) PTD_ROWR(12) PTD_ROWR(13) PTD_ROWR(14)
+#undef PTD_ROWR
+        case 15:
+            if constexpr (sizeof(V) == 4) {
+                hipLaunchKernelGGL((k_mfree_halves_r<V, 15, REAL_OUT, SRC>), grid, dim3(MFR_THREADS), 0, st, s, ld,
+                                   out);
+                break;
+            }
+            return hipErrorInvalidValue;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <class V, bool REAL_OUT, int SRC>
 hipError_t mfree_t(int n, const void* src, int64_t ld, void* out, hipStream_t st)
 {
-    const dim3 grid(mf_paired<SRC>() ? 1u << (n - 1) : 1u << n);
+    if constexpr (mf_real_rows<SRC>()) return mfree_real_t<V, REAL_OUT, SRC>(n, src, ld, out, st);
+    const dim3 grid(1u << n);
     const cplx<V>* s = (const cplx<V>*)src;
     switch (n) {
 #define PTD_ROW(NN)                                                                                         \
