@@ -2,9 +2,9 @@
 // coefficients are known (Sec. IV-B): block-diagonal assembly and its m = 1
 // case the direct sum, Hermitian augmentation, linear combination.  Each is
 // one pass over HBM (read the inputs once, write the output once), so the
-// kernels are plain grid-stride streams with coalesced row accesses; the
-// block-diagonal one applies a length-2^m transform over the block index in
-// registers.
+// kernels are streams with coalesced row accesses, each workgroup over one
+// contiguous range; the block-diagonal one applies a length-2^m transform
+// over the block index in registers.
 #include "engine.hpp"
 #include "internal.hpp"
 
@@ -16,6 +16,41 @@ constexpr int ALG_THREADS = 256;
 
 int alg_grid() { return device_cu_count() * 8; }
 
+// The one-pass combinations run in the shape of the fastest copy measured on
+// MI355X: one 1024-thread workgroup per CU, each owning one contiguous range
+// of positions, non-temporal loads and stores.
+constexpr int ALG_BLK_THREADS = 1024;
+
+int alg_blk_grid() { return device_cu_count(); }
+
+__device__ __forceinline__ void block_range(int64_t count, int64_t& lo, int64_t& hi)
+{
+    const int64_t per = (count + gridDim.x - 1) / gridDim.x;
+    lo = (int64_t)blockIdx.x * per;
+    hi = lo + per < count ? lo + per : count;
+}
+
+template <class V>
+__device__ __forceinline__ cplx<V> ld_nt(const cplx<V>* p)
+{
+    typedef V v2 __attribute__((ext_vector_type(2)));
+    const v2 v = __builtin_nontemporal_load((const v2*)p);
+    cplx<V> c;
+    c.re = v.x;
+    c.im = v.y;
+    return c;
+}
+
+template <class V>
+__device__ __forceinline__ void st_nt(cplx<V>* p, V re, V im)
+{
+    typedef V v2 __attribute__((ext_vector_type(2)));
+    v2 v;
+    v.x = re;
+    v.y = im;
+    __builtin_nontemporal_store(v, (v2*)p);
+}
+
 // Output element (x, (t << k) | z) of diag(A_0, ..., A_{2^M - 1}) for every
 // input position idx = x * 2^k + z < count = 4^k: the sum over blocks i of
 // (-1)^popcount(t & i) c_i[idx], times 2^-M.  The pairwise direct sums of the
@@ -26,31 +61,27 @@ int alg_grid() { return device_cu_count() * 8; }
 // (One position per thread and grid step: unrolling four to eight positions
 // per thread to put more loads in flight measured 5-10% slower.)
 template <class V, int M>
-__global__ __launch_bounds__(ALG_THREADS) void k_block_diag(BlockPtrs blocks, cplx<V>* __restrict__ out, int k,
-                                                            int64_t count)
+__global__ __launch_bounds__(ALG_BLK_THREADS) void k_block_diag(BlockPtrs blocks, cplx<V>* __restrict__ out, int k,
+                                                                int64_t count)
 {
     constexpr int NB = 1 << M;
     const V scale = exp2_neg<V>(M);
     const int64_t zmask = ((int64_t)1 << k) - 1;
     const int64_t pitch = (int64_t)1 << (k + M);
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count;
-         idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo, hi;
+    block_range(count, lo, hi);
+    for (int64_t idx = lo + threadIdx.x; idx < hi; idx += ALG_BLK_THREADS) {
         V re[NB], im[NB];
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-            const cplx<V> c = ((const cplx<V>*)blocks.p[i])[idx];
+            const cplx<V> c = ld_nt<V>((const cplx<V>*)blocks.p[i] + idx);
             re[i] = c.re;
             im[i] = c.im;
         }
         wht_reg<V, M>(re, im);
         cplx<V>* row = out + (idx >> k) * pitch + (idx & zmask);
 #pragma unroll
-        for (int t = 0; t < NB; ++t) {
-            cplx<V> c;
-            c.re = re[t] * scale;
-            c.im = im[t] * scale;
-            row[(int64_t)t << k] = c;
-        }
+        for (int t = 0; t < NB; ++t) st_nt<V>(row + ((int64_t)t << k), re[t] * scale, im[t] * scale);
     }
 }
 
@@ -58,33 +89,33 @@ __global__ __launch_bounds__(ALG_THREADS) void k_block_diag(BlockPtrs blocks, cp
 // compact) of the 2^(n+1)-wide real output gets Re c[x][z] at z and Im c[x][z]
 // at 2^n + z.
 template <class V>
-__global__ __launch_bounds__(ALG_THREADS) void k_herm_augment(const cplx<V>* __restrict__ in, V* __restrict__ out,
-                                                              int n, int compact, int64_t count)
+__global__ __launch_bounds__(ALG_BLK_THREADS) void k_herm_augment(const cplx<V>* __restrict__ in,
+                                                                  V* __restrict__ out, int n, int compact,
+                                                                  int64_t count)
 {
     const int64_t zmask = ((int64_t)1 << n) - 1;
     const int64_t half = (int64_t)1 << n;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const cplx<V> c = in[idx];
+    int64_t lo, hi;
+    block_range(count, lo, hi);
+    for (int64_t idx = lo + threadIdx.x; idx < hi; idx += ALG_BLK_THREADS) {
+        const cplx<V> c = ld_nt<V>(in + idx);
         const int64_t x = idx >> n, z = idx & zmask;
         V* row = out + ((compact ? 0 : half) + x) * (half << 1);
-        row[z] = c.re;
-        row[half + z] = c.im;
+        __builtin_nontemporal_store(c.re, row + z);
+        __builtin_nontemporal_store(c.im, row + half + z);
     }
 }
 
 // out = mu * a + b, each part rounded in this order (no fused multiply-add).
 template <class V>
-__global__ __launch_bounds__(ALG_THREADS) void k_lincomb(const cplx<V>* a, const cplx<V>* b, cplx<V>* out, V mr,
-                                                         V mi, int64_t count)
+__global__ __launch_bounds__(ALG_BLK_THREADS) void k_lincomb(const cplx<V>* a, const cplx<V>* b, cplx<V>* out, V mr,
+                                                             V mi, int64_t count)
 {
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const cplx<V> u = a[idx], v = b[idx];
-        cplx<V> w;
-        w.re = (mr * u.re - mi * u.im) + v.re;
-        w.im = (mr * u.im + mi * u.re) + v.im;
-        out[idx] = w;
+    int64_t lo, hi;
+    block_range(count, lo, hi);
+    for (int64_t idx = lo + threadIdx.x; idx < hi; idx += ALG_BLK_THREADS) {
+        const cplx<V> u = ld_nt<V>(a + idx), v = ld_nt<V>(b + idx);
+        st_nt<V>(out + idx, (mr * u.re - mi * u.im) + v.re, (mr * u.im + mi * u.re) + v.im);
     }
 }
 
@@ -128,7 +159,7 @@ hipError_t block_diag_t(int k, int m, bool compact, const BlockPtrs& blocks, voi
     switch (m) {
 #define PTD_M(MM)                                                                                         \
     case MM:                                                                                              \
-        hipLaunchKernelGGL((k_block_diag<V, MM>), dim3(alg_grid()), dim3(ALG_THREADS), 0, st, blocks,     \
+        hipLaunchKernelGGL((k_block_diag<V, MM>), dim3(alg_blk_grid()), dim3(ALG_BLK_THREADS), 0, st, blocks,     \
                            (cplx<V>*)out, k, count);                                                      \
         break;
         PTD_M(1) PTD_M(2) PTD_M(3) PTD_M(4) PTD_M(5)
@@ -148,7 +179,8 @@ template <class V>
 hipError_t herm_augment_t(int n, bool compact, const void* in, void* out, hipStream_t st)
 {
     const int64_t count = (int64_t)1 << (2 * n);
-    hipLaunchKernelGGL(k_herm_augment<V>, dim3(alg_grid()), dim3(ALG_THREADS), 0, st, (const cplx<V>*)in, (V*)out, n,
+    hipLaunchKernelGGL(k_herm_augment<V>, dim3(alg_blk_grid()), dim3(ALG_BLK_THREADS), 0, st, (const cplx<V>*)in,
+                       (V*)out, n,
                        compact ? 1 : 0, count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || compact) return e;
@@ -188,10 +220,10 @@ hipError_t launch_linear_combination(int n, ptd_dtype dt, double mu_re, double m
 {
     const int64_t count = (int64_t)1 << (2 * n);
     if (dt == PTD_C128)
-        hipLaunchKernelGGL(k_lincomb<double>, dim3(alg_grid()), dim3(ALG_THREADS), 0, st, (const cplx<double>*)a,
+        hipLaunchKernelGGL(k_lincomb<double>, dim3(alg_blk_grid()), dim3(ALG_BLK_THREADS), 0, st, (const cplx<double>*)a,
                            (const cplx<double>*)b, (cplx<double>*)out, mu_re, mu_im, count);
     else
-        hipLaunchKernelGGL(k_lincomb<float>, dim3(alg_grid()), dim3(ALG_THREADS), 0, st, (const cplx<float>*)a,
+        hipLaunchKernelGGL(k_lincomb<float>, dim3(alg_blk_grid()), dim3(ALG_BLK_THREADS), 0, st, (const cplx<float>*)a,
                            (const cplx<float>*)b, (cplx<float>*)out, (float)mu_re, (float)mu_im, count);
     return hipGetLastError();
 }
