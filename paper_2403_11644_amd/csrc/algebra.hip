@@ -148,7 +148,8 @@ __global__ __launch_bounds__(ALG_THREADS) void k_zero_pad(const cplx<V>* __restr
 hipError_t zero_bytes(void* p, int64_t bytes, hipStream_t st)
 {
     if (bytes <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero16, dim3(alg_grid()), dim3(ALG_THREADS), 0, st, (uint4*)p, bytes / 16);
+    // one 256-thread workgroup per CU: the shape of the fastest write-only sweep
+    hipLaunchKernelGGL(k_zero16, dim3(device_cu_count()), dim3(ALG_THREADS), 0, st, (uint4*)p, bytes / 16);
     return hipGetLastError();
 }
 

@@ -273,8 +273,19 @@ __global__ void k_zero_unlisted(void* __restrict__ out, int n, int s)
 {
     const int64_t N = (int64_t)1 << n;
     const int64_t total = N * N;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
+    constexpr int EB = HERM ? (int)sizeof(V) : 2 * (int)sizeof(V);  // output element bytes
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (N * EB >= 16 && ((uintptr_t)out & 15) == 0) {
+        // whole 16-byte words of each unlisted row (rows are whole words)
+        const int lw = n + (EB == 4 ? 2 : EB == 8 ? 3 : 4) - 4;  // log2 of words per row
+        const int64_t words = total * EB / 16;
+        uint4* w = (uint4*)out;
+        const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+            if (!is_listed((uint32_t)(i >> lw), n, s)) w[i] = zero;
+        return;
+    }
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
         const uint32_t x = (uint32_t)(e >> n);
         if (!is_listed(x, n, s)) put_final<V, HERM>(out, e, (V)0, (V)0);
     }
@@ -286,7 +297,9 @@ hipError_t struct_launch(int n, int s, int count, bool compact, const void* A, i
 {
     const cplx<V>* a = (const cplx<V>*)A;
     if (!compact && SRC != SRC_ROWS) {
-        hipLaunchKernelGGL((k_zero_unlisted<V, HERM>), dim3(2048), dim3(256), 0, st, out, n, s);
+        // plain 16-byte stores, one 256-thread workgroup per CU: the shape of
+        // the fastest write-only sweep
+        hipLaunchKernelGGL((k_zero_unlisted<V, HERM>), dim3(device_cu_count()), dim3(256), 0, st, out, n, s);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
