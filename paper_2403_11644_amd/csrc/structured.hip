@@ -347,6 +347,14 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t count, uint32_t v)
         p[i] = v;
 }
 
+// zero `words` 16-byte words (the output before the scatter)
+__global__ void k_zero_words16(uint4* __restrict__ p, int64_t words)
+{
+    const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = zero;
+}
+
 __global__ void k_mark_x(const int32_t* __restrict__ rows, const int32_t* __restrict__ cols, int64_t nnz, int n,
                          uint32_t* __restrict__ flags)
 {
@@ -506,8 +514,11 @@ hipError_t sparse_t(int n, bool compact, int64_t nnz, const int32_t* rows, const
     if (*bad_xs) return hipSuccess;
     // zero the output (compact rows, or the whole dense array), scatter, then
     // the transform in place over the listed rows
-    const int64_t words = (compact ? (int64_t)count * N : N * N) * (int64_t)sizeof(cplx<V>) / 4;
-    hipLaunchKernelGGL(k_fill_u32, dim3(4096), dim3(256), 0, st, (uint32_t*)out, words, 0u);
+    const int64_t out_bytes = (compact ? (int64_t)count * N : N * N) * (int64_t)sizeof(cplx<V>);
+    if (((uintptr_t)out & 15) == 0 && (out_bytes & 15) == 0)  // plain 16-byte stores, one workgroup per CU
+        hipLaunchKernelGGL(k_zero_words16, dim3(device_cu_count()), dim3(256), 0, st, (uint4*)out, out_bytes / 16);
+    else
+        hipLaunchKernelGGL(k_fill_u32, dim3(4096), dim3(256), 0, st, (uint32_t*)out, out_bytes / 4, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, st, (uint32_t*)xpos, N, 0xffffffffu);
     hipLaunchKernelGGL(k_xpos, dim3(grid), dim3(256), 0, st, xs, count, xpos);
     if (nnz > 0 && rows)
