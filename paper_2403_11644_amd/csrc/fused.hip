@@ -109,12 +109,13 @@ FusedTuning fused_default(int n, ptd_dtype dt, bool herm)
             return c128 && !herm ? FusedTuning{29, 16} : FusedTuning{1, 16};
         case 12:
             if (c128) return herm ? FusedTuning{29, 12} : FusedTuning{29, 16};
-            return FusedTuning{1, 8};
+            return herm ? FusedTuning{1, 12} : FusedTuning{1, 8};
         case 13:
-            if (herm) return c128 ? FusedTuning{13, 8} : FusedTuning{29, 6};
+            if (herm) return c128 ? FusedTuning{13, 8} : FusedTuning{29, 4};
             return FusedTuning{30, 8};
         case 14:
-            if (herm) return c128 ? FusedTuning{30, 6} : FusedTuning{29, 12};
+            // complex64 Hermitian: half-width groups (shape 3) win
+            if (herm) return c128 ? FusedTuning{30, 6} : FusedTuning{31, 8};
             return c128 ? FusedTuning{14, 4} : FusedTuning{30, 6};
         default:
             return FusedTuning{29, 4};
