@@ -5,7 +5,12 @@ qubit order reversed, a dropped term of the sum, a shifted instead of
 XOR-ed column index, the Z sign taken from the column instead of the row).
 The pins of the oracle (worked examples, n = 1 closed forms, one-hot
 outputs of Theorem 1, Parseval, real coefficients of Hermitian input) must
-reject every one of them, while the oracle itself passes.  CPU only."""
+reject every one of them, while the oracle itself passes.  The same holds
+for the sparse-input functions: a compressed-row reader whose row ranges
+end one short or are not clipped, and a sum over stored entries with the
+sign taken from the column or without the i^p phase, each fail a pin
+(scipy's compressed-row conversion, the hand-worked clipped case, the
+dense oracle).  CPU only."""
 import json
 import os
 
@@ -178,3 +183,91 @@ def test_every_mutant_is_caught(oracle_mod, name):
     dec = mutants(oracle_mod)[name]
     res = all_pins(oracle_mod, dec)
     assert not all(res.values()), "%s passed every pin: %r" % (name, res)
+
+
+# -- sparse input: the entry-based oracle functions and their pins -------------
+
+def pin_csr_scipy(oracle_mod, to_coo):
+    import scipy.sparse
+
+    n, N = 5, 32
+    rng = np.random.default_rng(90)
+    counts = rng.integers(0, 6, size=N)
+    counts[0], counts[3] = 3, 0
+    row_ptr = np.concatenate([[0], np.cumsum(counts)])
+    col = rng.integers(0, N, size=int(row_ptr[-1]))
+    col[1] = col[0]
+    vals = rng.standard_normal(len(col)) + 1j * rng.standard_normal(len(col))
+    want = scipy.sparse.csr_matrix((vals, col, row_ptr), shape=(N, N)).toarray()
+    return np.array_equal(oracle_mod.sparse_to_dense(n, *to_coo(n, row_ptr, col, vals)), want)
+
+
+def pin_csr_clipped(oracle_mod, to_coo):
+    rows, cols, _ = to_coo(2, [0, 2, 5, -3, 9], [1, 2, 0, 7], np.array([1, 2j, 3, 4], dtype=np.complex128))
+    return rows.tolist() == [0, 0, 1, 1, 3, 3, 3, 3] and cols.tolist() == [1, 2, 0, 7, 1, 2, 0, 7]
+
+
+def pin_sparse_coeffs(oracle_mod, coeffs):
+    n, N = 4, 16
+    rng = np.random.default_rng(91)
+    rows, cols = rng.integers(0, N, size=30), rng.integers(0, N, size=30)
+    vals = rng.standard_normal(30) + 1j * rng.standard_normal(30)
+    xs, zs = np.divmod(np.arange(N * N), N)
+    want = oracle_mod.coeffs(oracle_mod.sparse_to_dense(n, rows, cols, vals), xs, zs)
+    return np.allclose(coeffs(n, rows, cols, vals, xs, zs), want, rtol=0, atol=1e-14)
+
+
+def _csr_mutant(end_shift=0, clip_start=True):
+    def to_coo(n, row_ptr, col_idx, vals):
+        row_ptr = np.asarray(row_ptr, dtype=np.int64)
+        col_idx = np.asarray(col_idx, dtype=np.int64)
+        vals = np.asarray(vals)
+        nnz = len(col_idx)
+        rows, cols, vs = [], [], []
+        for r in range(1 << n):
+            lo = min(max(int(row_ptr[r]), 0), nnz) if clip_start else min(int(row_ptr[r]), nnz)
+            hi = min(max(int(row_ptr[r + 1]) + end_shift, lo), nnz)
+            for e in range(lo, hi):
+                rows.append(r)
+                cols.append(int(col_idx[e]))
+                vs.append(vals[e])
+        return np.array(rows, dtype=np.int64), np.array(cols, dtype=np.int64), np.array(vs, dtype=np.complex128)
+    return to_coo
+
+
+def _sparse_coeffs_mutant(sign_from_col=False, no_phase=False):
+    def coeffs(n, rows, cols, vals, xs, zs):
+        N = 1 << n
+        rows, cols = np.asarray(rows, dtype=np.int64), np.asarray(cols, dtype=np.int64)
+        vals = np.asarray(vals).astype(np.complex128)
+        out = np.empty(len(xs), dtype=np.complex128)
+        for i, (x, z) in enumerate(zip(xs, zs)):
+            sel = (rows ^ cols) == int(x)
+            idx = cols[sel] if sign_from_col else rows[sel]
+            sgn = np.array([(-1) ** _pc(int(z) & int(k)) for k in idx])
+            total = np.sum(sgn * vals[sel]) if len(idx) else 0.0
+            ph = 1 if no_phase else 1j ** (_pc(int(x) & int(z)) % 4)
+            out[i] = ph * total / N
+        return out
+    return coeffs
+
+
+def test_sparse_oracle_passes_its_pins(oracle_mod):
+    assert pin_csr_scipy(oracle_mod, oracle_mod.csr_to_coo)
+    assert pin_csr_clipped(oracle_mod, oracle_mod.csr_to_coo)
+    assert pin_sparse_coeffs(oracle_mod, oracle_mod.sparse_coeffs)
+    # the mutant generators with no slip are the oracle
+    assert pin_csr_scipy(oracle_mod, _csr_mutant()) and pin_csr_clipped(oracle_mod, _csr_mutant())
+    assert pin_sparse_coeffs(oracle_mod, _sparse_coeffs_mutant())
+
+
+@pytest.mark.parametrize("slip", ["row end one short", "start not clipped"])
+def test_csr_mutants_are_caught(oracle_mod, slip):
+    to_coo = _csr_mutant(end_shift=-1) if slip == "row end one short" else _csr_mutant(clip_start=False)
+    assert not (pin_csr_scipy(oracle_mod, to_coo) and pin_csr_clipped(oracle_mod, to_coo))
+
+
+@pytest.mark.parametrize("slip", ["sign from the column", "no i^p phase"])
+def test_sparse_coeffs_mutants_are_caught(oracle_mod, slip):
+    coeffs = _sparse_coeffs_mutant(sign_from_col=slip == "sign from the column", no_phase=slip == "no i^p phase")
+    assert not pin_sparse_coeffs(oracle_mod, coeffs)
