@@ -113,3 +113,20 @@ def test_write_traffic_scales_every_kernel_by_the_copy(bench, tmp_path, monkeypa
     assert data["kernels"]["ptd::k_x<float>(b)"] == {"fetch_bytes": 2 * 16 * 4 ** n, "write_bytes": 3 * 16 * 4 ** n}
     assert json.loads((tmp_path / "profiles" / "traffic.json").read_text()) == data
     assert bench._traffic("k_x<float>") == (2 * 16 * 4 ** n, 3 * 16 * 4 ** n)
+
+
+def test_counter_means_merge_every_file_of_a_folder(bench, tmp_path):
+    # a second counter pass over other legs writes into the same folder under
+    # another prefix: both files are read, and a kernel seen in both is
+    # averaged over all its dispatches
+    def write(name, rows):
+        with open(tmp_path / name, "w", newline="") as f:
+            w = csv.writer(f)
+            w.writerow(["Kernel_Name", "Counter_Name", "Counter_Value"])
+            for r in rows:
+                w.writerow(r)
+    write("f_counter_collection.csv", [("k_a(...)", "FETCH_SIZE", 10.0), ("k_both(...)", "FETCH_SIZE", 2.0)])
+    write("fb_counter_collection.csv", [("k_b(...)", "FETCH_SIZE", 30.0), ("k_both(...)", "FETCH_SIZE", 4.0),
+                                        ("k_both(...)", "FETCH_SIZE", 6.0)])
+    m = bench._counter_means(str(tmp_path), "FETCH_SIZE")
+    assert m == {"k_a(...)": 10.0, "k_b(...)": 30.0, "k_both(...)": 4.0}
